@@ -1,0 +1,207 @@
+"""Seeded synthetic inputs for the walker local-energy path.
+
+This module only *builds inputs*: a one-dimensional chain Hamiltonian
+(electron-repulsion integrals and their pivoted Cholesky factorisation), a
+localized single-determinant trial and a population of noisy walkers.  It holds
+none of the energy method's arithmetic (no Green's functions, no half-rotation,
+no pair compression, no energies), so the CPU reference and the GPU library can
+both consume it without sharing any of the method.
+
+Model (the paper's molecules are replaced by this synthetic stand-in):
+
+* M basis functions at x_p = p (unit spacing), treated as orthonormal.
+* S_pq = exp(-(x_p - x_q)^2 / 2), set to zero for |p - q| > band (default 8,
+  where the dropped values are below 1.3e-14).  Zeroing entries of S is a
+  congruence with a diagonal matrix, so the ERI matrix below stays PSD.
+* (pq|rs) = S_pq S_rs / sqrt(1 + (c_pq - c_rs)^2) with c_pq = (x_p + x_q)/2.
+  1/sqrt(1+d^2) has a positive Fourier transform (2 K_0(|k|)), so the matrix
+  over pair indices is positive semidefinite and admits a Cholesky factor.
+* The two-electron operator is factorised as V_pqrs = (pr|qs) =
+  sum_g L_g[p][r] L_g[q][s] (Sec. 2.1.1, the three-index form below Eq. 13) by
+  a diagonal-pivoted ("modified") Cholesky decomposition stopped when the
+  largest residual diagonal falls below tol.  Ties pick the lowest flattened
+  pair index p*M + q.
+* Trial: n Gaussians exp(-(p - c_k)^2/2) centred at c_k = floor(k*M/n),
+  Lowdin-orthonormalised, C = G (G^T G)^{-1/2}.  These orbitals are already
+  localized, which is what the compression of Sec. 2.3.1 relies on.
+* Walkers: Q factor of the thin QR of Psi_T + sigma (Z1 + i Z2), with Z1, Z2
+  independent standard normal matrices.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+DEFAULT_BAND = 8
+
+
+# ----------------------------------------------------------------------------
+# Chain Hamiltonian
+# ----------------------------------------------------------------------------
+
+def chain_overlap(M: int, band: int = DEFAULT_BAND) -> np.ndarray:
+    """S_pq = exp(-(p-q)^2/2) for |p-q| <= band, zero beyond."""
+    p = np.arange(M, dtype=np.float64)
+    d = p[:, None] - p[None, :]
+    S = np.exp(-0.5 * d * d)
+    S[np.abs(d) > band] = 0.0
+    return S
+
+
+def chain_eri_dense(M: int, band: int = DEFAULT_BAND) -> np.ndarray:
+    """Dense chemists'-notation tensor eri[p,q,r,s] = (pq|rs) (small M only)."""
+    if M > 40:
+        raise ValueError("dense ERI is M^4; use the Cholesky factor for M > 40")
+    S = chain_overlap(M, band)
+    x = np.arange(M, dtype=np.float64)
+    c = 0.5 * (x[:, None] + x[None, :])
+    d = c[:, :, None, None] - c[None, None, :, :]
+    return S[:, :, None, None] * S[None, None, :, :] / np.sqrt(1.0 + d * d)
+
+
+def _unique_pairs(M: int, band: int):
+    """Pairs p <= q with q - p <= band, ordered by flattened index p*M + q."""
+    ps, qs = [], []
+    for p in range(M):
+        for q in range(p, min(M, p + band + 1)):
+            ps.append(p)
+            qs.append(q)
+    return np.asarray(ps, dtype=np.int64), np.asarray(qs, dtype=np.int64)
+
+
+def chain_cholesky(M: int, tol: float, band: int = DEFAULT_BAND,
+                   max_vectors: int | None = None) -> np.ndarray:
+    """Pivoted Cholesky factor of the chain ERI, returned as L[g][p][q].
+
+    Each L_g is symmetric (the ERI is symmetric under p<->q), so the
+    factorisation runs on the unique pairs p <= q and is mirrored at the end.
+    The residual diagonal of every pair stays below ``tol`` on exit.
+    """
+    ps, qs = _unique_pairs(M, band)
+    npair = ps.size
+    S = chain_overlap(M, band)
+    s_pair = S[ps, qs]
+    c_pair = 0.5 * (ps + qs).astype(np.float64)
+    diag = s_pair * s_pair  # (pq|pq) = S_pq^2
+    cap = max_vectors if max_vectors is not None else min(npair, 12 * M + 64)
+    Lp = np.zeros((cap, npair), dtype=np.float64)
+    k = 0
+    while k < cap:
+        piv = int(np.argmax(diag))  # first maximum = lowest flattened index
+        dmax = diag[piv]
+        if dmax < tol:
+            break
+        d = c_pair - c_pair[piv]
+        col = s_pair * s_pair[piv] / np.sqrt(1.0 + d * d)
+        if k:
+            col -= Lp[:k].T @ Lp[:k, piv]
+        v = col / math.sqrt(dmax)
+        Lp[k] = v
+        diag = diag - v * v
+        diag[piv] = 0.0
+        k += 1
+    else:
+        raise RuntimeError("pivoted Cholesky did not converge within %d vectors" % cap)
+    L = np.zeros((k, M, M), dtype=np.float64)
+    L[:, ps, qs] = Lp[:k]
+    L[:, qs, ps] = Lp[:k]
+    return L
+
+
+def chain_cholesky_residual_max(M: int, L: np.ndarray, band: int = DEFAULT_BAND) -> float:
+    """max_pq [(pq|pq) - sum_g L_g[p][q]^2] over all pairs (a check helper)."""
+    S = chain_overlap(M, band)
+    resid = S * S - np.einsum("gpq,gpq->pq", L, L)
+    return float(resid.max())
+
+
+# ----------------------------------------------------------------------------
+# Trial determinant and walkers
+# ----------------------------------------------------------------------------
+
+def gaussian_centres(M: int, n: int) -> np.ndarray:
+    return np.array([(k * M) // n for k in range(n)], dtype=np.int64)
+
+
+def lowdin_gaussian_trial(M: int, n: int) -> np.ndarray:
+    """Real M x n trial with orthonormal, localized columns."""
+    p = np.arange(M, dtype=np.float64)[:, None]
+    c = gaussian_centres(M, n).astype(np.float64)[None, :]
+    G = np.exp(-0.5 * (p - c) ** 2)
+    w, V = np.linalg.eigh(G.T @ G)
+    return G @ (V * (1.0 / np.sqrt(w))) @ V.T
+
+
+def noisy_walkers(trial: np.ndarray, nw: int, sigma: float,
+                  rng: np.random.Generator) -> np.ndarray:
+    """nw walkers [nw][M][n] complex128: Q of QR(trial + sigma (Z1 + i Z2))."""
+    M, n = trial.shape
+    out = np.empty((nw, M, n), dtype=np.complex128)
+    for w in range(nw):
+        z = rng.standard_normal((M, n)) + 1j * rng.standard_normal((M, n))
+        q, _ = np.linalg.qr(trial + sigma * z)
+        out[w] = q
+    return out
+
+
+def random_orthogonal(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-ish random real orthogonal n x n matrix (used to delocalize a trial)."""
+    q, r = np.linalg.qr(rng.standard_normal((n, n)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def random_symmetric_cholesky(M: int, X: int, rng: np.random.Generator) -> np.ndarray:
+    """X random symmetric M x M matrices: a generic factorised Hamiltonian."""
+    A = rng.standard_normal((X, M, M)) / M
+    return 0.5 * (A + A.transpose(0, 2, 1))
+
+
+# ----------------------------------------------------------------------------
+# Named workloads
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class ChainConfig:
+    name: str
+    M: int            # basis functions
+    n: int            # occupied orbitals per spin
+    nw: int           # walkers
+    chol_tol: float   # pivoted Cholesky stopping tolerance
+    sigma: float      # walker noise
+    seed: int
+    epsilons: tuple = (1e-3, 1e-4, 1e-5)
+
+
+# Small case: 48 sites, 8 orbitals per spin (Gaussians on every 6th site),
+# Cholesky to 1e-6, 16 walkers with noise 0.1.
+CHAIN_SMALL = ChainConfig("chain-M48-n8-w16", 48, 8, 16, 1e-6, 0.1, 1001)
+# Polyacene-scale case: 400 sites, 60 orbitals per spin, Cholesky to 1e-5,
+# 512 walkers with noise 0.2.
+CHAIN_POLYACENE = ChainConfig("chain-M400-n60-w512", 400, 60, 512, 1e-5, 0.2, 1002)
+# Mixed-precision study size: 500 sites, 48 orbitals, 1024 walkers.
+CHAIN_PRECISION = ChainConfig("chain-M500-n48-w1024", 500, 48, 1024, 1e-5, 0.2, 1003,
+                              epsilons=(1e-4,))
+
+CONFIGS = {c.name: c for c in (CHAIN_SMALL, CHAIN_POLYACENE, CHAIN_PRECISION)}
+
+
+@dataclasses.dataclass
+class ChainSystem:
+    config: ChainConfig
+    chol: np.ndarray      # [X][M][M] float64
+    trial: np.ndarray     # [M][n]   float64
+    walkers: np.ndarray   # [nw][M][n] complex128
+
+    @property
+    def n_chol(self) -> int:
+        return self.chol.shape[0]
+
+
+def make_system(cfg: ChainConfig, nw: int | None = None) -> ChainSystem:
+    rng = np.random.default_rng(cfg.seed)
+    chol = chain_cholesky(cfg.M, cfg.chol_tol)
+    trial = lowdin_gaussian_trial(cfg.M, cfg.n)
+    walkers = noisy_walkers(trial, cfg.nw if nw is None else nw, cfg.sigma, rng)
+    return ChainSystem(cfg, chol, trial, walkers)

@@ -1,0 +1,283 @@
+"""Pins of the CPU reference against facts fixed outside it.
+
+Each test ties a route of the reference to something independent of that
+route: the second-quantised Fock-space expansion, textbook closed forms
+(closed-shell Hartree-Fock, two electrons in one orbital), exact algebraic
+invariances, the exactness of the SVD compression at T_SVD = 0 (Sec. 2.3.1)
+and the spectral-norm bound of the truncation.
+"""
+import numpy as np
+import pytest
+
+from oracle import energy as E
+from oracle import fock as F
+from paper_2202_00832_amd import synth
+
+
+def _rand_walker(rng, M, n, scale=0.3, base=None):
+    z = rng.standard_normal((M, n)) + 1j * rng.standard_normal((M, n))
+    return (base if base is not None else 0.0) + scale * z
+
+
+def _rel(a, b):
+    return abs(a - b) / max(1.0, abs(b))
+
+
+# ---------------------------------------------------------------------------
+# Fock space pins the Wick form (Eq. 10) and the G definition (Eq. 11)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,n,kind,seed", [
+    (4, 1, "chain", 1), (5, 2, "chain", 2), (4, 2, "random", 3), (5, 1, "random", 4), (6, 2, "chain", 5),
+])
+def test_fock_matches_wick_restricted(M, n, kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "chain":
+        eri = synth.chain_eri_dense(M)
+    else:
+        eri = E.eri_from_cholesky(synth.random_symmetric_cholesky(M, 3 * M, rng))
+    trial = synth.lowdin_gaussian_trial(M, n)
+    phi = _rand_walker(rng, M, n, 0.4, trial)
+    e_fock, _ = F.mixed_energy_restricted(eri, trial, phi)
+    ej, ek = E.e2_wick_restricted(eri, trial, phi)
+    assert _rel(ej + ek, e_fock) < 1e-12
+
+
+@pytest.mark.parametrize("M,na,nb,seed", [(4, 2, 1, 11), (5, 2, 2, 12), (4, 1, 1, 13)])
+def test_fock_matches_wick_unrestricted(M, na, nb, seed):
+    rng = np.random.default_rng(seed)
+    eri = E.eri_from_cholesky(synth.random_symmetric_cholesky(M, 2 * M, rng))
+    ta = np.linalg.qr(rng.standard_normal((M, na)))[0]
+    tb = np.linalg.qr(rng.standard_normal((M, nb)))[0]
+    pa = _rand_walker(rng, M, na, 0.5, ta)
+    pb = _rand_walker(rng, M, nb, 0.5, tb)
+    e_fock, _ = F.mixed_energy(eri, ta, tb, pa, pb)
+    Ga = E.greens_function(ta, pa)
+    Gb = E.greens_function(tb, pb)
+    ej, ek = E.e2_wick(eri, Ga, Gb)
+    assert _rel(ej + ek, e_fock) < 1e-12
+
+
+def test_fock_overlap_is_det_squared():
+    """<Psi_T|phi> of two equal-spin determinants is det(Psi_T^dag phi)^2."""
+    rng = np.random.default_rng(21)
+    M, n = 5, 2
+    trial = synth.lowdin_gaussian_trial(M, n)
+    phi = _rand_walker(rng, M, n, 0.5, trial)
+    _, ovlp = F.mixed_energy_restricted(synth.chain_eri_dense(M), trial, phi)
+    _, logdet, info = E.green_theta(trial, phi)
+    assert info == 0
+    assert abs(np.exp(2 * logdet) - ovlp) < 1e-12 * abs(ovlp)
+
+
+def test_restricted_equals_unrestricted_with_equal_spins():
+    rng = np.random.default_rng(22)
+    M, n = 6, 3
+    eri = synth.chain_eri_dense(M)
+    trial = synth.lowdin_gaussian_trial(M, n)
+    phi = _rand_walker(rng, M, n, 0.3, trial)
+    G = E.greens_function(trial, phi)
+    r = E.e2_wick_restricted(eri, trial, phi)
+    u = E.e2_wick(eri, G, G)
+    assert abs(r[0] - u[0]) < 1e-13 and abs(r[1] - u[1]) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Closed forms
+# ---------------------------------------------------------------------------
+
+def test_hartree_fock_closed_form():
+    """walker = trial: E2 = sum_ij 2 (ii|jj) - (ij|ji) with MO integrals."""
+    M, n = 24, 4
+    chol = synth.chain_cholesky(M, 1e-12)
+    eri = E.eri_from_cholesky(chol)
+    C = synth.lowdin_gaussian_trial(M, n)
+    mo = np.einsum("pqrs,pi,qj,rk,sl->ijkl", eri, C, C, C, C, optimize=True)
+    e_hf = sum(2 * mo[i, i, j, j] - mo[i, j, j, i] for i in range(n) for j in range(n))
+    theta, _, info = E.green_theta(C, C.astype(np.complex128))
+    assert info == 0
+    lbar = E.half_rotate(chol, C)
+    ej, ek = E.e2_cholesky(lbar, theta)
+    assert _rel(ej + ek, e_hf) < 1e-12
+    ej_w, ek_w = E.e2_wick_restricted(eri, C, C.astype(np.complex128))
+    assert _rel(ej_w + ek_w, e_hf) < 1e-12
+    # Coulomb and exchange separately: 2 sum (ii|jj) and -sum (ij|ji)
+    assert _rel(ej, sum(2 * mo[i, i, j, j] for i in range(n) for j in range(n))) < 1e-12
+
+
+def test_two_electron_closed_form():
+    """n = 1 per spin: E2 = (psi phi|psi phi) / (psi^T phi)^2."""
+    rng = np.random.default_rng(31)
+    M = 12
+    chol = synth.chain_cholesky(M, 1e-13)
+    eri = E.eri_from_cholesky(chol)
+    psi = synth.lowdin_gaussian_trial(M, 1)
+    phi = _rand_walker(rng, M, 1, 0.4, psi)
+    closed = np.einsum("pqrs,p,q,r,s->", eri, psi[:, 0], phi[:, 0], psi[:, 0], phi[:, 0]) \
+        / (psi[:, 0] @ phi[:, 0]) ** 2
+    theta, _, _ = E.green_theta(psi, phi)
+    ej, ek = E.e2_cholesky(E.half_rotate(chol, psi), theta)
+    assert _rel(ej + ek, closed) < 1e-12
+    # a single orbital has exchange = -Coulomb / 2 exactly
+    assert abs(ek + 0.5 * ej) < 1e-13 * abs(ej)
+
+
+# ---------------------------------------------------------------------------
+# Route identities
+# ---------------------------------------------------------------------------
+
+def test_cholesky_route_equals_wick_with_rebuilt_eri():
+    rng = np.random.default_rng(41)
+    M, n, X = 9, 3, 20
+    chol = synth.random_symmetric_cholesky(M, X, rng)
+    eri = E.eri_from_cholesky(chol)
+    trial = np.linalg.qr(rng.standard_normal((M, n)))[0]
+    phi = _rand_walker(rng, M, n, 0.5, trial)
+    theta, _, _ = E.green_theta(trial, phi)
+    c = E.e2_cholesky(E.half_rotate(chol, trial), theta)
+    w = E.e2_wick_restricted(eri, trial, phi)
+    assert _rel(c[0], w[0]) < 1e-12 and _rel(c[1], w[1]) < 1e-12
+
+
+def test_cholesky_route_within_factorisation_bound_of_exact_eri():
+    """|dE2| <= 3 tol (sum_pq |G_pq|)^2 for a factor whose residual diag < tol."""
+    rng = np.random.default_rng(42)
+    M, n = 14, 3
+    eri = synth.chain_eri_dense(M)
+    trial = synth.lowdin_gaussian_trial(M, n)
+    phi = _rand_walker(rng, M, n, 0.2, trial)
+    G = E.greens_function(trial, phi)
+    exact = sum(E.e2_wick(eri, G, G))
+    theta, _, _ = E.green_theta(trial, phi)
+    for tol in (1e-2, 1e-4, 1e-8):
+        chol = synth.chain_cholesky(M, tol)
+        approx = sum(E.e2_cholesky(E.half_rotate(chol, trial), theta))
+        assert abs(approx - exact) <= 3 * tol * np.abs(G).sum() ** 2 + 1e-12
+
+
+def test_hr_eri_equals_cholesky():
+    sysm = synth.make_system(synth.CHAIN_SMALL, nw=3)
+    lbar = E.half_rotate(sysm.chol, sysm.trial)
+    for phi in sysm.walkers:
+        theta, _, _ = E.green_theta(sysm.trial, phi)
+        a = E.e2_cholesky(lbar, theta)
+        b = E.e2_hr_eri(lbar, theta)
+        assert _rel(a[0], b[0]) < 1e-12 and _rel(a[1], b[1]) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Green's function intermediate (Eq. 14-15)
+# ---------------------------------------------------------------------------
+
+def test_theta_properties_and_invariance():
+    rng = np.random.default_rng(51)
+    sysm = synth.make_system(synth.CHAIN_SMALL, nw=2)
+    trial = sysm.trial
+    lbar = E.half_rotate(sysm.chol, trial)
+    for phi in sysm.walkers:
+        theta, logdet, info = E.green_theta(trial, phi)
+        assert info == 0
+        assert np.abs(trial.conj().T @ theta - np.eye(trial.shape[1])).max() < 1e-12
+        # G from Q (Eq. 14) equals the definition (Eq. 11)
+        assert np.abs((theta @ trial.conj().T).T - E.greens_function(trial, phi)).max() < 1e-12
+        R = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+        theta_r, logdet_r, _ = E.green_theta(trial, phi @ R)
+        assert np.abs(theta_r - theta).max() < 1e-11 * np.abs(theta).max()
+        assert abs(np.exp(logdet_r - logdet) - np.linalg.det(R)) < 1e-10 * abs(np.linalg.det(R))
+        e0 = sum(E.e2_cholesky(lbar, theta))
+        e1 = sum(E.e2_cholesky(lbar, theta_r))
+        assert _rel(e1, e0) < 1e-11
+
+
+def test_full_energy_invariant_under_trial_rotation():
+    """Rotating the occupied trial orbitals leaves the determinant, hence E2, unchanged."""
+    rng = np.random.default_rng(52)
+    sysm = synth.make_system(synth.CHAIN_SMALL, nw=1)
+    U = synth.random_orthogonal(8, rng)
+    t2 = sysm.trial @ U
+    phi = sysm.walkers[0]
+    th1, _, _ = E.green_theta(sysm.trial, phi)
+    th2, _, _ = E.green_theta(t2, phi)
+    e1 = sum(E.e2_cholesky(E.half_rotate(sysm.chol, sysm.trial), th1))
+    e2 = sum(E.e2_cholesky(E.half_rotate(sysm.chol, t2), th2))
+    assert _rel(e2, e1) < 1e-11
+
+
+def test_singular_overlap_reports_info():
+    """A walker orbital with no weight on the trial's support gives a zero pivot."""
+    M, n = 10, 3
+    trial = np.eye(M)[:, :n]
+    rng = np.random.default_rng(53)
+    phi = _rand_walker(rng, M, n, 1.0)
+    phi[:n, 1] = 0.0  # column 1 of Psi_T^dag phi is exactly zero
+    theta, _, info = E.green_theta(trial, phi)
+    assert theta is None and info == 2
+
+
+# ---------------------------------------------------------------------------
+# LO compression (Sec. 2.3.1-2.3.2)
+# ---------------------------------------------------------------------------
+
+def test_lo_exact_at_zero_threshold():
+    sysm = synth.make_system(synth.CHAIN_SMALL, nw=3)
+    lbar = E.half_rotate(sysm.chol, sysm.trial)
+    fac = E.lo_compress(lbar, 0.0)
+    assert E.lo_ranks(fac, 8).min() == sysm.config.M
+    for phi in sysm.walkers:
+        theta, _, _ = E.green_theta(sysm.trial, phi)
+        a = E.e2_cholesky(lbar, theta)
+        b = E.e2_lo(fac, theta)
+        assert _rel(a[0], b[0]) < 1e-11 and _rel(a[1], b[1]) < 1e-11
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3, 1e-4, 1e-5])
+def test_lo_error_within_a_priori_bound(eps):
+    sysm = synth.make_system(synth.CHAIN_SMALL)
+    lbar = E.half_rotate(sysm.chol, sysm.trial)
+    fac = E.lo_compress(lbar, eps, pairs="upper")
+    for phi in sysm.walkers:
+        theta, _, _ = E.green_theta(sysm.trial, phi)
+        full = sum(E.e2_cholesky(lbar, theta))
+        lo = sum(E.e2_lo(fac, theta))
+        bound = E.lo_error_bound(fac, theta)
+        assert abs(lo - full) <= bound * (1 + 1e-9) + 1e-12
+
+
+def test_lo_ordered_pairs_equal_upper_pairs():
+    """SVD of every ordered block == SVD of i <= j plus the transpose identity."""
+    sysm = synth.make_system(synth.CHAIN_SMALL, nw=2)
+    lbar = E.half_rotate(sysm.chol, sysm.trial)
+    for eps in (1e-3, 1e-4):
+        fo = E.lo_compress(lbar, eps, pairs="ordered")
+        fu = E.lo_compress(lbar, eps, pairs="upper")
+        assert (E.lo_ranks(fo, 8) == E.lo_ranks(fu, 8)).all()
+        for phi in sysm.walkers:
+            theta, _, _ = E.green_theta(sysm.trial, phi)
+            a = E.e2_lo(fo, theta)
+            b = E.e2_lo(fu, theta)
+            assert _rel(a[0], b[0]) < 1e-12 and _rel(a[1], b[1]) < 1e-12
+
+
+def test_lo_error_decreases_with_threshold():
+    sysm = synth.make_system(synth.CHAIN_SMALL)
+    lbar = E.half_rotate(sysm.chol, sysm.trial)
+    thetas = [E.green_theta(sysm.trial, p)[0] for p in sysm.walkers]
+    full = np.array([sum(E.e2_cholesky(lbar, t)) for t in thetas])
+    errs = []
+    for eps in (1e-2, 1e-4, 1e-6):
+        fac = E.lo_compress(lbar, eps, pairs="upper")
+        lo = np.array([sum(E.e2_lo(fac, t)) for t in thetas])
+        errs.append(np.abs(lo - full).max())
+    assert errs[2] < errs[0]
+
+
+def test_localized_orbitals_compress_better():
+    """Sec. 3: localized orbitals give much higher compression than delocalized ones."""
+    sysm = synth.make_system(synth.CHAIN_SMALL, nw=1)
+    rng = np.random.default_rng(61)
+    deloc = sysm.trial @ synth.random_orthogonal(8, rng)
+    eps = 1e-4
+    r_loc = E.lo_ranks(E.lo_compress(E.half_rotate(sysm.chol, sysm.trial), eps, "upper"), 8)
+    r_del = E.lo_ranks(E.lo_compress(E.half_rotate(sysm.chol, deloc), eps, "upper"), 8)
+    M = sysm.config.M
+    assert E.compression_percent(r_loc, M) > E.compression_percent(r_del, M) + 10.0
