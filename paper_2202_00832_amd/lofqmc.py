@@ -1,0 +1,257 @@
+"""Thin ctypes binding of liblofqmc (the C ABI declared in include/lofqmc.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device arrays are torch tensors on the GPU (torch supplies device
+memory and the stream); complex arrays are torch.complex128, whose storage is
+the interleaved (re, im) layout the ABI expects.  The library must have been
+built (python -m paper_2202_00832_amd.build); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblofqmc.so")
+HEADER_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lofqmc.h")
+
+LO_OK, LO_EINVAL, LO_ENOMEM, LO_EHIP, LO_EUNSUPPORTED, LO_ESOLVER = 0, -1, -2, -3, -4, -5
+LO_FP64, LO_FP32, LO_BF16X3 = 0, 1, 2
+_NAMES = {0: "LO_OK", -1: "LO_EINVAL", -2: "LO_ENOMEM", -3: "LO_EHIP", -4: "LO_EUNSUPPORTED", -5: "LO_ESOLVER"}
+
+_c_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_SIGS = {
+    "lo_create": (ctypes.c_int, [ctypes.POINTER(_c_p), _c_p]),
+    "lo_set_stream": (ctypes.c_int, [_c_p, _c_p]),
+    "lo_synchronize": (ctypes.c_int, [_c_p]),
+    "lo_destroy": (ctypes.c_int, [_c_p]),
+    "lo_last_error": (ctypes.c_char_p, [_c_p]),
+    "build_half_rotated_chol": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p]),
+    "build_lo_factors": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, ctypes.c_double, ctypes.POINTER(_c_p)]),
+    "lo_factors_destroy": (ctypes.c_int, [_c_p]),
+    "lo_factors_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "lo_factors_export": (ctypes.c_int, [_c_p, _c_p, _c_p]),
+    "green_theta": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "local_energy_full": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _i64, _c_p, _c_p, _c_p, ctypes.c_int,
+                                         ctypes.c_uint, _c_p]),
+    "local_energy_lo": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p]),
+}
+
+_lib = None
+
+
+class LoError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (%d): %s" % (_NAMES.get(code, "?"), code, message))
+        self.code = code
+
+
+def load() -> ctypes.CDLL:
+    """Loads liblofqmc.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblofqmc.so is not built; run `python -m paper_2202_00832_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions declared in include/lofqmc.h."""
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _check_dev(name, t, dtype, shape):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+
+class Factors:
+    """Owner of a lo_factors handle (device storage held by the library)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        M = ctypes.c_int64()
+        n = ctypes.c_int64()
+        load().lo_factors_info(self._h, ctypes.byref(M), ctypes.byref(n), None, None, None, None)
+        self.M, self.n_occ = M.value, n.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load().lo_factors_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        lib = load()
+        M = ctypes.c_int64()
+        n = ctypes.c_int64()
+        lib.lo_factors_info(self._h, ctypes.byref(M), ctypes.byref(n), None, None, None, None)
+        ranks = np.zeros((n.value, n.value), dtype=np.int32)
+        fd = np.zeros((n.value, n.value), dtype=np.float64)
+        rows = ctypes.c_int64()
+        nbytes = ctypes.c_int64()
+        lib.lo_factors_info(self._h, None, None, ranks.ctypes.data, fd.ctypes.data, ctypes.byref(rows),
+                            ctypes.byref(nbytes))
+        return {"M": M.value, "n_occ": n.value, "ranks": ranks, "first_dropped": fd,
+                "total_rows": rows.value, "bytes": nbytes.value}
+
+    def export(self) -> dict:
+        """{(i, j): (Ubar [M x K], Vbar [K x M], first_dropped)} for i <= j (host copies)."""
+        inf = self.info()
+        M, n = inf["M"], inf["n_occ"]
+        rows = np.zeros((max(inf["total_rows"], 1), M), dtype=np.float64)
+        off = np.zeros((n, n), dtype=np.int64)
+        rc = load().lo_factors_export(self._h, rows.ctypes.data, off.ctypes.data)
+        if rc != LO_OK:
+            raise LoError(rc, "lo_factors_export failed")
+        out = {}
+        for i in range(n):
+            for j in range(i, n):
+                K = int(inf["ranks"][i, j])
+                o = int(off[i, j])
+                Ubar = rows[o:o + K].T.copy()
+                Vbar = rows[o + K:o + 2 * K].copy()
+                out[(i, j)] = (Ubar, Vbar, float(inf["first_dropped"][i, j]))
+        return out
+
+
+class Context:
+    """A library context bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None):
+        self._lib = load()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+        h = ctypes.c_void_p()
+        rc = self._lib.lo_create(ctypes.byref(h), ctypes.c_void_p(stream))
+        if rc != LO_OK:
+            raise LoError(rc, "lo_create failed")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            self._lib.lo_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != LO_OK:
+            raise LoError(rc, self._lib.lo_last_error(self._h).decode())
+
+    def synchronize(self):
+        self._check(self._lib.lo_synchronize(self._h))
+
+    # -- set-up ---------------------------------------------------------------
+    def build_half_rotated_chol(self, chol, trial, lbar=None):
+        import torch
+        X, M, _ = chol.shape
+        n = trial.shape[1]
+        _check_dev("chol", chol, torch.float64, (X, M, M))
+        _check_dev("trial", trial, torch.float64, (M, n))
+        if lbar is None:
+            lbar = torch.empty((X, M, n), dtype=torch.float64, device=chol.device)
+        _check_dev("lbar", lbar, torch.float64, (X, M, n))
+        self._check(self._lib.build_half_rotated_chol(self._h, M, n, X, _ptr(chol), _ptr(trial), _ptr(lbar)))
+        return lbar
+
+    def build_lo_factors(self, lbar, epsilon: float) -> Factors:
+        import torch
+        X, M, n = lbar.shape
+        _check_dev("lbar", lbar, torch.float64, (X, M, n))
+        h = ctypes.c_void_p()
+        self._check(self._lib.build_lo_factors(self._h, M, n, X, _ptr(lbar), float(epsilon), ctypes.byref(h)))
+        return Factors(h.value)
+
+    # -- per walker ---------------------------------------------------------------
+    def green_theta(self, trial, phi, theta=None, log_ovlp=None, info=None):
+        import torch
+        nw, M, n = phi.shape
+        _check_dev("trial", trial, torch.float64, (M, n))
+        _check_dev("phi", phi, torch.complex128, (nw, M, n))
+        dev = phi.device
+        if theta is None:
+            theta = torch.empty((nw, M, n), dtype=torch.complex128, device=dev)
+        if log_ovlp is None:
+            log_ovlp = torch.empty((nw,), dtype=torch.complex128, device=dev)
+        if info is None:
+            info = torch.empty((nw,), dtype=torch.int32, device=dev)
+        _check_dev("theta", theta, torch.complex128, (nw, M, n))
+        _check_dev("log_ovlp", log_ovlp, torch.complex128, (nw,))
+        _check_dev("info", info, torch.int32, (nw,))
+        self._check(self._lib.green_theta(self._h, M, n, nw, _ptr(trial), _ptr(phi), _ptr(theta), _ptr(log_ovlp),
+                                          _ptr(info)))
+        return theta, log_ovlp, info
+
+    def local_energy_full(self, lbar, theta, info=None, energy=None, precision=LO_FP64, flags=0):
+        import torch
+        X, M, n = lbar.shape
+        nw = theta.shape[0]
+        _check_dev("lbar", lbar, torch.float64, (X, M, n))
+        _check_dev("theta", theta, torch.complex128, (nw, M, n))
+        if info is not None:
+            _check_dev("info", info, torch.int32, (nw,))
+        if energy is None:
+            energy = torch.empty((nw, 2), dtype=torch.complex128, device=theta.device)
+        _check_dev("energy", energy, torch.complex128, (nw, 2))
+        self._check(self._lib.local_energy_full(self._h, M, n, X, nw, _ptr(lbar), _ptr(theta), _ptr(info),
+                                                int(precision), int(flags), _ptr(energy)))
+        return energy
+
+    def local_energy_lo(self, factors: Factors, theta, info=None, energy=None, precision=LO_FP64, flags=0):
+        import torch
+        nw = theta.shape[0]
+        _check_dev("theta", theta, torch.complex128, (nw, factors.M, factors.n_occ))
+        if info is not None:
+            _check_dev("info", info, torch.int32, (nw,))
+        if energy is None:
+            energy = torch.empty((nw, 2), dtype=torch.complex128, device=theta.device)
+        _check_dev("energy", energy, torch.complex128, (nw, 2))
+        self._check(self._lib.local_energy_lo(self._h, factors.handle, nw, _ptr(theta), _ptr(info), int(precision),
+                                              int(flags), _ptr(energy)))
+        return energy

@@ -1,0 +1,64 @@
+"""The C ABI library loads on a host without a GPU, exports every declared
+symbol, and rejects bad arguments before touching the device."""
+import ctypes
+import math
+
+import pytest
+
+from paper_2202_00832_amd import lofqmc as L
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return L.load()
+    except ImportError as e:
+        pytest.skip(str(e))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = L.declared_functions()
+    assert len(names) >= 13
+    for name in ["lo_create", "build_half_rotated_chol", "build_lo_factors", "green_theta",
+                 "local_energy_full", "local_energy_lo"]:
+        assert name in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _ctx(lib):
+    h = ctypes.c_void_p()
+    assert lib.lo_create(ctypes.byref(h), None) == L.LO_OK
+    return h
+
+
+def test_validation_errors_need_no_device(lib):
+    h = _ctx(lib)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    try:
+        assert lib.lo_create(None, None) == L.LO_EINVAL
+        assert lib.green_theta(None, 4, 2, 1, fake, fake, fake, None, fake) == L.LO_EINVAL
+        assert lib.green_theta(h, 0, 2, 1, fake, fake, fake, None, fake) == L.LO_EINVAL
+        assert lib.green_theta(h, 4, 5, 1, fake, fake, fake, None, fake) == L.LO_EINVAL   # n > M
+        assert lib.green_theta(h, 100, 65, 1, fake, fake, fake, None, fake) == L.LO_EUNSUPPORTED
+        assert lib.green_theta(h, 8, 2, -1, fake, fake, fake, None, fake) == L.LO_EINVAL
+        assert lib.green_theta(h, 8, 2, 3, None, fake, fake, None, fake) == L.LO_EINVAL
+        assert b"null" in lib.lo_last_error(h)
+        assert lib.green_theta(h, 8, 2, 0, None, None, None, None, None) == L.LO_OK   # empty batch
+        assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP32, 0, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP64, 7, fake) == L.LO_EINVAL
+        assert lib.local_energy_full(h, 8, 2, -3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_full(h, 8, 2, 3, 0, None, None, None, L.LO_FP64, 0, None) == L.LO_OK
+        assert lib.local_energy_lo(h, None, 4, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
+        out = ctypes.c_void_p()
+        for eps in (-1e-4, math.nan, math.inf):
+            assert lib.build_lo_factors(h, 8, 2, 3, fake, eps, ctypes.byref(out)) == L.LO_EINVAL
+        assert lib.build_lo_factors(h, 8, 2, 3, fake, 1e-4, None) == L.LO_EINVAL
+        assert lib.build_lo_factors(h, 8, 9, 3, fake, 1e-4, ctypes.byref(out)) == L.LO_EINVAL
+        assert lib.build_half_rotated_chol(h, 8, 0, 3, fake, fake, fake) == L.LO_EINVAL
+        assert lib.build_half_rotated_chol(h, 8, 2, 0, None, None, None) == L.LO_OK  # nothing to do
+        assert lib.lo_factors_info(None, None, None, None, None, None, None) == L.LO_EINVAL
+        assert lib.lo_factors_destroy(None) == L.LO_OK
+    finally:
+        assert lib.lo_destroy(h) == L.LO_OK
+    assert lib.lo_destroy(None) == L.LO_OK

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 reference.
+
+Both sides receive the same seeded inputs (Cholesky vectors, trial, walkers);
+every expected value is computed by the reference from those inputs.  The
+tolerance is the FP64 bar of 1e-9 Ha per walker on each energy component, and
+1e-12 relative on theta.  Shapes cover several MFMA tiles, ragged tails in
+every dimension (M, n_occ, n_chol, walkers) and degenerate cases.
+"""
+import numpy as np
+import pytest
+
+from oracle import energy as E
+from paper_2202_00832_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_00832_amd import lofqmc  # noqa: E402
+
+TOL_E = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = lofqmc.Context()
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def random_system(M, n, X, nw, seed, sigma=0.3):
+    rng = np.random.default_rng(seed)
+    chol = synth.random_symmetric_cholesky(M, X, rng)
+    trial = np.linalg.qr(rng.standard_normal((M, n)))[0]
+    walkers = synth.noisy_walkers(trial, nw, sigma, rng)
+    return chol, trial, walkers
+
+
+def oracle_thetas(trial, walkers):
+    th, ld, info = E.green_theta_batch(trial, walkers)
+    assert (info == 0).all()
+    return th, ld
+
+
+def assert_energy_close(got, ref, tol=TOL_E):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    err = np.abs(got - ref).max(axis=1)
+    assert err.max() <= tol, "max |dE| = %.3e (walker %d)" % (err.max(), int(err.argmax()))
+
+
+# ---------------------------------------------------------------------------
+# build_half_rotated_chol
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,n,X", [(48, 8, 95), (37, 5, 11), (70, 33, 3), (130, 64, 5), (16, 1, 1)])
+def test_half_rotation(ctx, M, n, X):
+    print("half_rotation M=%d n=%d X=%d" % (M, n, X), flush=True)
+    if (M, n, X) == (48, 8, 95):
+        s = synth.make_system(synth.CHAIN_SMALL, nw=1)
+        chol, trial = s.chol, s.trial
+    else:
+        chol, trial, _ = random_system(M, n, X, 1, seed=M + n + X)
+    lbar = host(ctx.build_half_rotated_chol(dev(chol), dev(trial)))
+    ref = E.half_rotate(chol, trial).transpose(0, 2, 1)   # [g][r][i]
+    assert np.abs(lbar - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+# ---------------------------------------------------------------------------
+# green_theta
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,n,nw", [(48, 8, 16), (37, 1, 3), (50, 17, 5), (70, 33, 4), (100, 60, 3),
+                                    (64, 64, 2), (131, 47, 5), (5, 5, 2)])
+def test_green_theta(ctx, M, n, nw):
+    print("green_theta M=%d n=%d nw=%d" % (M, n, nw), flush=True)
+    if (M, n) == (48, 8):
+        s = synth.make_system(synth.CHAIN_SMALL)
+        trial, walkers = s.trial, s.walkers
+    else:
+        _, trial, walkers = random_system(M, n, 1, nw, seed=7 * M + n)
+    theta, logov, info = ctx.green_theta(dev(trial), dev(walkers))
+    theta, logov, info = host(theta), host(logov), host(info)
+    ref, ref_ld = oracle_thetas(trial, walkers)
+    assert (info == 0).all()
+    scale = np.abs(ref).max()
+    assert np.abs(theta - ref).max() <= 1e-12 * scale
+    # log det: real part exactly comparable, imaginary part modulo 2 pi
+    assert np.abs(logov.real - ref_ld.real).max() <= 1e-11
+    dphi = np.angle(np.exp(1j * (logov.imag - ref_ld.imag)))
+    assert np.abs(dphi).max() <= 1e-11
+
+
+def test_green_theta_zero_pivot_and_nan_energy(ctx):
+    M, n, X = 20, 3, 4
+    rng = np.random.default_rng(3)
+    chol = synth.random_symmetric_cholesky(M, X, rng)
+    trial = np.eye(M)[:, :n].copy()
+    walkers = synth.noisy_walkers(trial, 3, 0.3, rng)
+    walkers[1, :n, 1] = 0.0   # column 1 of the overlap is exactly zero
+    theta, logov, info = ctx.green_theta(dev(trial), dev(walkers))
+    info_h = host(info)
+    _, _, ref_info = E.green_theta(trial, walkers[1])
+    assert list(info_h) == [0, ref_info, 0] and ref_info == 2
+    lbar = ctx.build_half_rotated_chol(dev(chol), dev(trial))
+    e = host(ctx.local_energy_full(lbar, theta, info))
+    assert np.isnan(e[1]).all() and np.isfinite(e[[0, 2]]).all()
+    f = ctx.build_lo_factors(lbar, 1e-6)
+    e_lo = host(ctx.local_energy_lo(f, theta, info))
+    assert np.isnan(e_lo[1]).all() and np.isfinite(e_lo[[0, 2]]).all()
+
+
+# ---------------------------------------------------------------------------
+# local_energy_full
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,n,X,nw", [(37, 5, 11, 3), (50, 17, 23, 7), (100, 60, 40, 5), (64, 64, 9, 4),
+                                      (20, 1, 7, 2), (131, 47, 30, 6), (33, 32, 1, 1), (48, 16, 17, 9)])
+def test_full_energy_from_reference_theta(ctx, M, n, X, nw):
+    print("full M=%d n=%d X=%d nw=%d" % (M, n, X, nw), flush=True)
+    chol, trial, walkers = random_system(M, n, X, nw, seed=M * n + X)
+    thetas, _ = oracle_thetas(trial, walkers)
+    lbar_ref = E.half_rotate(chol, trial)
+    ref = E.e2_cholesky_batch(lbar_ref, thetas)
+    lbar = dev(lbar_ref.transpose(0, 2, 1))
+    got = host(ctx.local_energy_full(lbar, dev(thetas)))
+    assert_energy_close(got, ref)
+
+
+def test_full_energy_chain_end_to_end_and_deterministic(ctx):
+    s = synth.make_system(synth.CHAIN_SMALL)
+    lbar = ctx.build_half_rotated_chol(dev(s.chol), dev(s.trial))
+    theta, _, info = ctx.green_theta(dev(s.trial), dev(s.walkers))
+    e1 = host(ctx.local_energy_full(lbar, theta, info))
+    e2 = host(ctx.local_energy_full(lbar, theta, info))
+    assert np.array_equal(e1.view(np.float64), e2.view(np.float64))
+    thetas, _ = oracle_thetas(s.trial, s.walkers)
+    ref = E.e2_cholesky_batch(E.half_rotate(s.chol, s.trial), thetas)
+    assert_energy_close(e1, ref)
+
+
+def test_full_energy_without_cholesky_vectors_is_zero(ctx):
+    M, n, nw = 12, 3, 2
+    _, trial, walkers = random_system(M, n, 1, nw, seed=5)
+    theta, _, info = ctx.green_theta(dev(trial), dev(walkers))
+    lbar = torch.zeros((0, M, n), dtype=torch.float64, device="cuda")
+    e = host(ctx.local_energy_full(lbar, theta, info))
+    assert np.abs(e).max() == 0.0
+
+
+# ---------------------------------------------------------------------------
+# build_lo_factors + local_energy_lo
+# ---------------------------------------------------------------------------
+
+def _lo_case(ctx, chol, trial, walkers, eps):
+    lbar_ref = E.half_rotate(chol, trial)
+    lbar = ctx.build_half_rotated_chol(dev(chol), dev(trial))
+    f = ctx.build_lo_factors(lbar, eps)
+    theta, _, info = ctx.green_theta(dev(trial), dev(walkers))
+    got = host(ctx.local_energy_lo(f, theta, info))
+    ref_f = E.lo_compress(lbar_ref, eps, pairs="upper")
+    thetas, _ = oracle_thetas(trial, walkers)
+    ref = E.e2_lo_batch(ref_f, thetas)
+    ranks_gpu = f.info()["ranks"]
+    ranks_ref = E.lo_ranks(ref_f, trial.shape[1])
+    return f, got, ref, ranks_gpu, ranks_ref, ref_f, thetas
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-5, 1e-4, 1e-3])
+def test_lo_energy_chain_small(ctx, eps):
+    print("lo chain eps=%g" % eps, flush=True)
+    s = synth.make_system(synth.CHAIN_SMALL)
+    f, got, ref, rg, rr, ref_f, thetas = _lo_case(ctx, s.chol, s.trial, s.walkers, eps)
+    assert np.array_equal(rg, rr)
+    assert_energy_close(got, ref)
+    if eps == 0.0:
+        full = E.e2_cholesky_batch(E.half_rotate(s.chol, s.trial), thetas)
+        assert_energy_close(got, full)
+
+
+@pytest.mark.parametrize("M,n,X,nw,eps", [(37, 5, 11, 3, 1e-3), (50, 17, 23, 70, 1e-2), (70, 33, 30, 5, 1e-4),
+                                          (29, 1, 6, 2, 0.0), (70, 64, 12, 3, 1e-3)])
+def test_lo_energy_ragged(ctx, M, n, X, nw, eps):
+    print("lo M=%d n=%d X=%d nw=%d eps=%g" % (M, n, X, nw, eps), flush=True)
+    chol, trial, walkers = random_system(M, n, X, nw, seed=3 * M + n)
+    f, got, ref, rg, rr, _, _ = _lo_case(ctx, chol, trial, walkers, eps)
+    assert np.array_equal(rg, rr)
+    assert_energy_close(got, ref)
+
+
+def test_lo_threshold_above_every_singular_value_gives_zero(ctx):
+    s = synth.make_system(synth.CHAIN_SMALL, nw=3)
+    lbar = ctx.build_half_rotated_chol(dev(s.chol), dev(s.trial))
+    f = ctx.build_lo_factors(lbar, 1e6)
+    assert f.info()["total_rows"] == 0
+    theta, _, info = ctx.green_theta(dev(s.trial), dev(s.walkers))
+    e = host(ctx.local_energy_lo(f, theta, info))
+    assert np.abs(e).max() == 0.0
+
+
+def test_lo_deterministic(ctx):
+    s = synth.make_system(synth.CHAIN_SMALL)
+    lbar = ctx.build_half_rotated_chol(dev(s.chol), dev(s.trial))
+    f = ctx.build_lo_factors(lbar, 1e-4)
+    theta, _, info = ctx.green_theta(dev(s.trial), dev(s.walkers))
+    e1 = host(ctx.local_energy_lo(f, theta, info))
+    e2 = host(ctx.local_energy_lo(f, theta, info))
+    assert np.array_equal(e1.view(np.float64), e2.view(np.float64))
