@@ -41,6 +41,14 @@ enum lo_status {
   LO_ESOLVER = -5        /* the dense SVD used while building LO factors failed */
 };
 
+/* Layout of theta (the Q matrices) produced by green_theta and read by the
+ * energy calls.  Default: walker-major complex [nw][M][n_occ].  With
+ * LO_THETA_ORBITAL_MAJOR: orbital-major complex [n_occ][M][nw] (walkers
+ * contiguous), the layout the LO energy multiplies directly. */
+enum lo_flags {
+  LO_THETA_ORBITAL_MAJOR = 1u
+};
+
 enum lo_precision {
   LO_FP64 = 0,   /* FP64 contractions and FP64 sums */
   LO_FP32 = 1,   /* reserved: FP32 contractions, FP64 sums */
@@ -118,25 +126,27 @@ int lo_factors_export(const lo_factors* f, double* rows, int64_t* row_offset);
 /* -------------------------------------------------------- per-walker calls */
 
 /* Green's-function intermediate Q of Eq. 15 ("theta"):
- *   O_w = trial^T phi_w (n_occ x n_occ), LU with partial pivoting,
- *   theta_w = phi_w O_w^{-1},  log_ovlp[w] = log det O_w (one spin).
+ *   O_w = trial^T phi_w (n_occ x n_occ), inverted by Gauss-Jordan elimination
+ *   with partial pivoting, theta_w = phi_w O_w^{-1},
+ *   log_ovlp[w] = log det O_w (one spin; imaginary part in (-pi, pi]).
  *   trial    : [M][n_occ] double (real)
  *   phi      : complex [nw][M][n_occ] walker determinants
- *   theta    : complex [nw][M][n_occ] (output)
+ *   theta    : complex [nw][M][n_occ] (output), or [n_occ][M][nw] when flags
+ *              holds LO_THETA_ORBITAL_MAJOR
  *   log_ovlp : complex [nw] (output; may be NULL)
  *   info     : int32 [nw] (output): 0, or k > 0 if the k-th pivot (1-based)
  *              of O_w is exactly zero; theta_w is then undefined and the
  *              energy calls return NaN for that walker.
  * Always FP64.  Supports n_occ <= 64. */
 int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double* trial,
-                const double* phi, double* theta, double* log_ovlp, int32_t* info);
+                const double* phi, double* theta, double* log_ovlp, int32_t* info, unsigned flags);
 
 /* Two-body energy by the half-rotated Cholesky route (Sec. 2.2, Eq. 16):
  *   T_{wg} = Lbar_g^T theta_w (n_occ x n_occ, complex)
  *   E_J[w] = 2 sum_g (Tr T_{wg})^2,   E_K[w] = -sum_g Tr(T_{wg} T_{wg}).
  * The per-(w, g) matrix T is never written to memory.
  *   lbar   : [n_chol][M][n_occ] double
- *   theta  : complex [nw][M][n_occ]
+ *   theta  : complex [nw][M][n_occ] (walker-major)
  *   info   : int32 [nw] from green_theta, or NULL (all valid)
  *   energy : complex [nw][2] (output) = (E_J, E_K) per walker
  * precision must be LO_FP64; flags must be 0.  Supports n_occ <= 64. */
@@ -149,10 +159,12 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
  *   QL_j = Ubar^T Q_j, QR_i = Vbar Q_i (complex K_ij-vectors, bilinear),
  *   E_J = 2 sum_ij QL_i . QR_j,   E_K = -sum_ij QL_j . QR_i.
  *   factors : handle from build_lo_factors (shapes M, n_occ taken from it)
- *   theta   : complex [nw][M][n_occ]
+ *   theta   : complex [nw][M][n_occ], or [n_occ][M][nw] with flags
+ *             LO_THETA_ORBITAL_MAJOR (the walker-major layout is transposed
+ *             into the context workspace first)
  *   info    : int32 [nw] or NULL
  *   energy  : complex [nw][2] (output) = (E_J, E_K)
- * precision must be LO_FP64; flags must be 0. */
+ * precision must be LO_FP64; flags may hold LO_THETA_ORBITAL_MAJOR only. */
 int local_energy_lo(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const double* theta,
                     const int32_t* info, int precision, unsigned flags, double* energy);
 

@@ -145,32 +145,48 @@ def e2_hr_eri(lbar: np.ndarray, theta: np.ndarray):
 # Localized-orbital compression (Sec. 2.3.1, Eq. 18) and LO energy (Eq. 19, 22)
 # ---------------------------------------------------------------------------
 
-def lo_compress(lbar: np.ndarray, eps: float, pairs: str = "ordered"):
-    """Truncated SVD of every pair block Y^{[ij]} (Sec. 2.3.1, Eq. 18).
-
-    Y^{[ij]} = U Sigma V; the singular values sigma_K >= eps are kept (all of
-    them when eps == 0), Ubar = U Sigma^(1/2) and Vbar = Sigma^(1/2) V.
+def lo_decompose(lbar: np.ndarray, pairs: str = "ordered"):
+    """Full SVD Y^{[ij]} = U Sigma V of every pair block (Sec. 2.3.1, Eq. 18).
 
     ``pairs="ordered"`` decomposes all n^2 blocks as the paper lists them;
     ``pairs="upper"`` decomposes only i <= j (Y^{[ji]} is the transpose of
-    Y^{[ij]}, whose SVD is V^T Sigma U^T, so its factors are (Vbar^T, Ubar^T)).
-
-    Returns dict (i, j) -> (Ubar [M x K], Vbar [K x M], sigma [M]) where sigma
-    holds all singular values of the block (for ranks and error bounds).
+    Y^{[ij]}, whose SVD is V^T Sigma U^T).  Returns dict (i, j) -> (U, sigma, V)
+    with sigma in non-increasing order.
     """
-    if not (eps >= 0.0):
-        raise ValueError("eps must be >= 0")
     n = lbar.shape[1]
+    cols = [np.ascontiguousarray(lbar[:, i, :]) for i in range(n)]  # [g, r] per orbital
     out = {}
     for i in range(n):
         for j in range(n):
             if pairs == "upper" and j < i:
                 continue
-            U, s, Vh = np.linalg.svd(pair_block(lbar, i, j))
-            K = s.size if eps == 0.0 else int(np.count_nonzero(s >= eps))
-            root = np.sqrt(s[:K])
-            out[(i, j)] = (U[:, :K] * root[None, :], root[:, None] * Vh[:K], s)
+            out[(i, j)] = np.linalg.svd(cols[i].T @ cols[j])
     return out
+
+
+def lo_truncate(decomp: dict, eps: float):
+    """Keeps the singular values sigma_K >= eps (all of them when eps == 0).
+
+    Ubar = U Sigma^(1/2) and Vbar = Sigma^(1/2) V.  Returns dict (i, j) ->
+    (Ubar [M x K], Vbar [K x M], sigma [M]) where sigma holds all singular
+    values of the block (for ranks and error bounds).
+    """
+    if not (eps >= 0.0):
+        raise ValueError("eps must be >= 0")
+    out = {}
+    for key, (U, s, Vh) in decomp.items():
+        K = s.size if eps == 0.0 else int(np.count_nonzero(s >= eps))
+        root = np.sqrt(s[:K])
+        out[key] = (U[:, :K] * root[None, :], root[:, None] * Vh[:K], s)
+    return out
+
+
+def lo_compress(lbar: np.ndarray, eps: float, pairs: str = "ordered"):
+    """Truncated SVD of every pair block (Sec. 2.3.1, Eq. 18): decompose, then
+    keep sigma_K >= eps (see lo_decompose and lo_truncate)."""
+    if not (eps >= 0.0):
+        raise ValueError("eps must be >= 0")
+    return lo_truncate(lo_decompose(lbar, pairs), eps)
 
 
 def expand_upper(factors: dict, n: int) -> dict:

@@ -39,3 +39,29 @@ __device__ __forceinline__ double wave_sum_lane0(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
+
+// Wave64 maximum of a 64-bit unsigned key, returned in every lane.  Row-local
+// butterflies use DPP (quad permutes and the row mirrors); the two cross-row
+// steps use lane shuffles.  Max is associative and exact, so all lanes agree.
+__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v, int ctrl) {
+  const int lo = (int)(unsigned)(v & 0xffffffffull), hi = (int)(unsigned)(v >> 32);
+  int olo, ohi;
+  switch (ctrl) {
+    case 0: olo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false); ohi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false); break;
+    case 1: olo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false); ohi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;
+    case 2: olo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false); ohi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false); break;
+    default: olo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false); ohi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false); break;
+  }
+  const unsigned long long o = ((unsigned long long)(unsigned)ohi << 32) | (unsigned)olo;
+  return o > v ? o : v;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  v = dpp_max_u64(v, 0);   // quad_perm [1,0,3,2]
+  v = dpp_max_u64(v, 1);   // quad_perm [2,3,0,1]
+  v = dpp_max_u64(v, 2);   // row_half_mirror
+  v = dpp_max_u64(v, 3);   // row_mirror
+  unsigned long long o = __shfl_xor(v, 16, 64);
+  v = o > v ? o : v;
+  o = __shfl_xor(v, 32, 64);
+  return o > v ? o : v;
+}

@@ -176,24 +176,31 @@ __global__ __launch_bounds__(256, 1) void energy_full_kernel(int M, int n, int64
   }
 }
 
-__global__ void reduce_partials_kernel(int64_t nw, int nchunk, const double* __restrict__ partial,
-                                       const int* __restrict__ info, double* __restrict__ energy) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// energy[w] = sum_c partial[c][w] in a fixed order: lane l adds chunks
+// l, l+64, ... and a fixed shuffle tree combines the lanes (one wave per walker).
+__global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t nw, int nchunk,
+                                                              const double* __restrict__ partial,
+                                                              const int* __restrict__ info,
+                                                              double* __restrict__ energy) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nw) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int c = 0; c < nchunk; ++c) {
-    const double* p = partial + ((size_t)c * nw + w) * 4;
-    s0 += p[0];
-    s1 += p[1];
-    s2 += p[2];
-    s3 += p[3];
+  for (int c = lane; c < nchunk; c += 64) {
+    const double4 p = reinterpret_cast<const double4*>(partial)[(size_t)c * nw + w];
+    s0 += p.x;
+    s1 += p.y;
+    s2 += p.z;
+    s3 += p.w;
   }
-  if (info && info[w] != 0) s0 = s1 = s2 = s3 = __builtin_nan("");
-  double* e = energy + w * 4;
-  e[0] = s0;
-  e[1] = s1;
-  e[2] = s2;
-  e[3] = s3;
+  s0 = wave_sum_lane0(s0);
+  s1 = wave_sum_lane0(s1);
+  s2 = wave_sum_lane0(s2);
+  s3 = wave_sum_lane0(s3);
+  if (lane == 0) {
+    if (info && info[w] != 0) s0 = s1 = s2 = s3 = __builtin_nan("");
+    reinterpret_cast<double4*>(energy)[w] = make_double4(s0, s1, s2, s3);
+  }
 }
 
 template <int NB>
@@ -228,7 +235,7 @@ hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw
 hipError_t launch_reduce_partials(hipStream_t s, int64_t nw, int nchunk, const double* partial, const int* info,
                                   double* energy) {
   if (nw <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, nw, nchunk,
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, s, nw, nchunk,
                      partial, info, energy);
   return hipGetLastError();
 }

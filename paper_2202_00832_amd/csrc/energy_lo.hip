@@ -46,59 +46,129 @@ hipError_t launch_theta_transpose(hipStream_t s, int M, int n, int64_t nw, const
   return hipGetLastError();
 }
 
-// Pass 1: tile = up to 64 output rows of one orbital o (wave q: 16 rows) x 64
-// walkers (four 16-walker column blocks, real and imaginary part each).
-__global__ __launch_bounds__(256) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
-                                                       const int* __restrict__ rowidx,
-                                                       const int* __restrict__ tile_orb,
-                                                       const int* __restrict__ tile_row0,
-                                                       const int* __restrict__ tile_nrows,
-                                                       const double2* __restrict__ thetaT,
-                                                       double2* __restrict__ qbar) {
-  const int t = blockIdx.x;
+// Pass 1: tile = up to LO_TILE_ROWS output rows of one orbital o x 32
+// walkers.  Per 16-row slab of r the factor rows (gathered through rowidx)
+// and Q_o of the 32 walkers are staged in LDS (double-buffered).  Wave q
+// takes walker half q / 2 and the real (q even) or imaginary part, against
+// every 16-row block of the tile, so the MFMA count follows the real row
+// count of the tile.
+constexpr int LO_TILE_ROWS = 192;
+constexpr int LO_RB = LO_TILE_ROWS / 16;
+constexpr int LO_WT = 32;
+
+__global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
+                                                          const int* __restrict__ rowidx,
+                                                          const int* __restrict__ tile_orb,
+                                                          const int* __restrict__ tile_row0,
+                                                          const int* __restrict__ tile_nrows,
+                                                          const double2* __restrict__ thetaT,
+                                                          double2* __restrict__ qbar, int ntiles, int nwt) {
+  __shared__ double sA[2][LO_TILE_ROWS][17];   // [row][r], padded against bank conflicts
+  __shared__ double2 sB[2][16][LO_WT];         // [r][walker]
+  // XCD-aware order: workgroups go round-robin over the 8 XCDs; every walker
+  // tile of row tile t runs on XCD t % 8, so its factor rows are read into
+  // one L2 once and reused by all walker tiles.
+  const int xcd = blockIdx.x & 7;
+  const int slot = blockIdx.x >> 3;
+  const int t = xcd + 8 * (slot / nwt);
+  if (t >= ntiles) return;
+  const int64_t w0 = (int64_t)(slot % nwt) * LO_WT;
   const int o = tile_orb[t];
   const int row0 = tile_row0[t];
   const int nrows = tile_nrows[t];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nrb = (nrows + 15) / 16;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int64_t w0 = (int64_t)blockIdx.y * 64;
-  const int myrow = 16 * wv + lr;
-  const bool rok = myrow < nrows;
-  const double* frow = rows + (size_t)(rok ? rowidx[row0 + myrow] : 0) * M;
+  const int half = wv >> 1, part = wv & 1;
   const double2* tho = thetaT + (size_t)o * M * nw;
 
-  d4 aR[4], aI[4];
+  // staging: A = nrows x 16 doubles (each row 128 contiguous bytes), B = 16 x 32 complex
+  constexpr int A_PER = (LO_TILE_ROWS * 16 + 255) / 256;   // 12
+  constexpr int B_PER = (16 * LO_WT + 255) / 256;          // 2
+  double pa[A_PER];
+  double2 pb[B_PER];
+  auto load = [&](int c) {
+    const int rbase = 16 * c;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) { aR[b] = d4zero(); aI[b] = d4zero(); }
-  for (int r0 = 0; r0 < M; r0 += 4) {
-    const int r = r0 + lk;
-    const double a = (rok && r < M) ? frow[r] : 0.0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t w = w0 + 16 * b + lr;
-      const double2 bv = (r < M && w < nw) ? tho[(size_t)r * nw + w] : make_double2(0.0, 0.0);
-      aR[b] = mfma16(a, bv.x, aR[b]);
-      aI[b] = mfma16(a, bv.y, aI[b]);
+    for (int q = 0; q < A_PER; ++q) {
+      const int e = tid + 256 * q;
+      const int row = e >> 4, rr = e & 15;
+      const int r = rbase + rr;
+      pa[q] = (row < nrows && r < M) ? rows[(size_t)rowidx[row0 + row] * M + r] : 0.0;
     }
+#pragma unroll
+    for (int q = 0; q < B_PER; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e / LO_WT, ww = e % LO_WT;
+      const int r = rbase + rr;
+      const int64_t w = w0 + ww;
+      pb[q] = (r < M && w < nw) ? tho[(size_t)r * nw + w] : make_double2(0.0, 0.0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < A_PER; ++q) {
+      const int e = tid + 256 * q;
+      sA[buf][e >> 4][e & 15] = pa[q];
+    }
+#pragma unroll
+    for (int q = 0; q < B_PER; ++q) {
+      const int e = tid + 256 * q;
+      sB[buf][e / LO_WT][e % LO_WT] = pb[q];
+    }
+  };
+
+  d4 acc[LO_RB];
+#pragma unroll
+  for (int b = 0; b < LO_RB; ++b) acc[b] = d4zero();
+  const int nchunk = (M + 15) / 16;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunk) load(c + 1);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int rr = 4 * s4 + lk;
+      const double2 bv = sB[buf][rr][16 * half + lr];
+      const double b = part ? bv.y : bv.x;
+#pragma unroll
+      for (int rb = 0; rb < LO_RB; ++rb) {
+        if (rb < nrb) acc[rb] = mfma16(sA[buf][16 * rb + lr][rr], b, acc[rb]);
+      }
+    }
+    if (c + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
   }
+  // D[row][walker]: lane holds rows 4v + lk of each block, walker 16*half + lr
+  const int64_t w = w0 + 16 * half + lr;
+  if (w < nw) {
+    double* q = reinterpret_cast<double*>(qbar);
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int64_t w = w0 + 16 * b + lr;
+    for (int rb = 0; rb < LO_RB; ++rb) {
+      if (rb < nrb) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int lrow = 16 * wv + 4 * v + lk;
-      if (lrow < nrows && w < nw) qbar[(size_t)(row0 + lrow) * nw + w] = make_double2(aR[b][v], aI[b][v]);
+        for (int v = 0; v < 4; ++v) {
+          const int lrow = 16 * rb + 4 * v + lk;
+          if (lrow < nrows) q[((size_t)(row0 + lrow) * nw + w) * 2 + part] = acc[rb][v];
+        }
+      }
     }
   }
 }
+
+int lo_tile_rows() { return LO_TILE_ROWS; }
 
 hipError_t launch_lo_pass1(hipStream_t s, int M, int64_t nw, int ntiles, const double* rows, const int* rowidx,
                            const int* tile_orb, const int* tile_row0, const int* tile_nrows, const double* thetaT,
                            double* qbar) {
   if (nw <= 0 || ntiles <= 0) return hipSuccess;
-  dim3 grid(ntiles, (unsigned)((nw + 63) / 64));
-  hipLaunchKernelGGL(lo_pass1_kernel, grid, dim3(256), 0, s, M, nw, rows, rowidx, tile_orb, tile_row0, tile_nrows,
-                     (const double2*)thetaT, (double2*)qbar);
+  const int nwt = (int)((nw + LO_WT - 1) / LO_WT);
+  const int64_t grid = (int64_t)8 * ((ntiles + 7) / 8) * nwt;
+  hipLaunchKernelGGL(lo_pass1_kernel, dim3((unsigned)grid), dim3(256), 0, s, M, nw, rows, rowidx, tile_orb, tile_row0,
+                     tile_nrows, (const double2*)thetaT, (double2*)qbar, ntiles, nwt);
   return hipGetLastError();
 }
 
@@ -144,8 +214,8 @@ __global__ __launch_bounds__(64) void lo_pass2_kernel(int64_t nw, int npairs, in
 }
 
 int lo_pass2_chunks(int npairs) {
-  int c = (npairs + 15) / 16;
-  if (c > 128) c = 128;
+  int c = (npairs + 3) / 4;
+  if (c > 512) c = 512;
   if (c < 1) c = 1;
   return c;
 }

@@ -8,7 +8,7 @@ namespace lofqmc {
 
 // ---- per-walker path
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                              double* theta, double* logov, int* info);
+                              double* theta, double* logov, int* info, int orbital_major);
 
 int full_num_chunks(int64_t X, int64_t nw);
 hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* lbar,
@@ -21,6 +21,7 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int64_t nw, int ntiles, const d
                            const int* tile_orb, const int* tile_row0, const int* tile_nrows, const double* thetaT,
                            double* qbar);
 int lo_pass2_chunks(int npairs);
+int lo_tile_rows();
 hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int npairs, int nchunk, const int* pK, const int64_t* offI,
                            const int64_t* offJ, const double* pw, const double* qbar, double* partial);
 

@@ -388,10 +388,15 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
       const int64_t cnt = 2 * (int64_t)f->ranks[o * n + k];
       for (int64_t q = 0; q < cnt; ++q) rowidx[obase[o] + loc[o * n + k] + q] = (int)(src + q);
     }
-    for (int64_t r0 = obase[o]; r0 < obase[o + 1]; r0 += 64) {
+    // split the orbital's rows into near-equal tiles of at most lo_tile_rows()
+    const int64_t R = obase[o + 1] - obase[o];
+    const int64_t cap = lofqmc::lo_tile_rows();
+    const int64_t ntile = (R + cap - 1) / cap;
+    for (int64_t q = 0; q < ntile; ++q) {
+      const int64_t a = obase[o] + R * q / ntile, b = obase[o] + R * (q + 1) / ntile;
       t_orb.push_back(o);
-      t_row0.push_back((int)r0);
-      t_nrows.push_back((int)std::min<int64_t>(64, obase[o + 1] - r0));
+      t_row0.push_back((int)a);
+      t_nrows.push_back((int)(b - a));
     }
   }
   f->ntiles = (int)t_orb.size();
@@ -459,7 +464,7 @@ int lo_factors_export(const lo_factors* f, double* rows, int64_t* row_offset) {
 // ------------------------------------------------------------- per walker
 
 int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double* trial, const double* phi,
-                double* theta, double* log_ovlp, int32_t* info) {
+                double* theta, double* log_ovlp, int32_t* info, unsigned flags) {
   if (!ctx) return LO_EINVAL;
   ctx->err.clear();
   if (M <= 0 || n_occ <= 0 || nw < 0) return fail(ctx, LO_EINVAL, "sizes must be M > 0, n_occ > 0, nw >= 0");
@@ -467,10 +472,11 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   if (n_occ > kMaxOcc) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d", kMaxOcc);
   if (M > (1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "M above 2^24");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
+  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   if (nw == 0) return LO_OK;
   if (!trial || !phi || !theta || !info) return fail(ctx, LO_EINVAL, "null array");
   HIP_OR_FAIL(ctx, lofqmc::launch_green_theta(ctx->stream, (int)M, (int)n_occ, nw, trial, phi, theta, log_ovlp,
-                                              info));
+                                              info, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0));
   return LO_OK;
 }
 
@@ -508,22 +514,26 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
   if (!f) return fail(ctx, LO_EINVAL, "null factors");
   if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
   if (precision != LO_FP64) return fail(ctx, LO_EUNSUPPORTED, "precision %d not implemented", precision);
-  if (flags != 0) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
   if (nw == 0) return LO_OK;
   if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
+  const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
   const int64_t M = f->M, n = f->n;
   const int nchunk = lofqmc::lo_pass2_chunks(f->npairs);
-  const size_t tbytes = align256(sizeof(double) * 2 * (size_t)n * M * nw);
+  const size_t tbytes = orbital_major ? 0 : align256(sizeof(double) * 2 * (size_t)n * M * nw);
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
   const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
   int rc = ensure_ws(ctx, tbytes + qbytes + pbytes);
   if (rc) return rc;
   char* base = (char*)ctx->ws;
-  double* thetaT = (double*)base;
+  const double* thetaT = theta;
   double* qbar = (double*)(base + tbytes);
   double* partial = (double*)(base + tbytes + qbytes);
-  HIP_OR_FAIL(ctx, lofqmc::launch_theta_transpose(ctx->stream, (int)M, (int)n, nw, theta, thetaT));
+  if (!orbital_major) {
+    thetaT = (double*)base;
+    HIP_OR_FAIL(ctx, lofqmc::launch_theta_transpose(ctx->stream, (int)M, (int)n, nw, theta, (double*)base));
+  }
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, nw, f->ntiles, f->rows, f->d_rowidx, f->d_tiles,
                                            f->d_tiles + f->ntiles, f->d_tiles + 2 * f->ntiles, thetaT, qbar));
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->npairs, nchunk, f->d_pK, f->d_off,

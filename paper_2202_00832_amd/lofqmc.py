@@ -19,6 +19,7 @@ HEADER_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__fil
 
 LO_OK, LO_EINVAL, LO_ENOMEM, LO_EHIP, LO_EUNSUPPORTED, LO_ESOLVER = 0, -1, -2, -3, -4, -5
 LO_FP64, LO_FP32, LO_BF16X3 = 0, 1, 2
+LO_THETA_ORBITAL_MAJOR = 1
 _NAMES = {0: "LO_OK", -1: "LO_EINVAL", -2: "LO_ENOMEM", -3: "LO_EHIP", -4: "LO_EUNSUPPORTED", -5: "LO_ESOLVER"}
 
 _c_p = ctypes.c_void_p
@@ -34,7 +35,7 @@ _SIGS = {
     "lo_factors_destroy": (ctypes.c_int, [_c_p]),
     "lo_factors_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "lo_factors_export": (ctypes.c_int, [_c_p, _c_p, _c_p]),
-    "green_theta": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "green_theta": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p, _c_p, _c_p, ctypes.c_uint]),
     "local_energy_full": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _i64, _c_p, _c_p, _c_p, ctypes.c_int,
                                          ctypes.c_uint, _c_p]),
     "local_energy_lo": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p]),
@@ -209,23 +210,26 @@ class Context:
         return Factors(h.value)
 
     # -- per walker ---------------------------------------------------------------
-    def green_theta(self, trial, phi, theta=None, log_ovlp=None, info=None):
+    def green_theta(self, trial, phi, theta=None, log_ovlp=None, info=None, orbital_major=False):
+        """theta is [nw][M][n] (walker-major) or [n][M][nw] when orbital_major."""
         import torch
         nw, M, n = phi.shape
         _check_dev("trial", trial, torch.float64, (M, n))
         _check_dev("phi", phi, torch.complex128, (nw, M, n))
         dev = phi.device
+        tshape = (n, M, nw) if orbital_major else (nw, M, n)
         if theta is None:
-            theta = torch.empty((nw, M, n), dtype=torch.complex128, device=dev)
+            theta = torch.empty(tshape, dtype=torch.complex128, device=dev)
         if log_ovlp is None:
             log_ovlp = torch.empty((nw,), dtype=torch.complex128, device=dev)
         if info is None:
             info = torch.empty((nw,), dtype=torch.int32, device=dev)
-        _check_dev("theta", theta, torch.complex128, (nw, M, n))
+        _check_dev("theta", theta, torch.complex128, tshape)
         _check_dev("log_ovlp", log_ovlp, torch.complex128, (nw,))
         _check_dev("info", info, torch.int32, (nw,))
+        flags = LO_THETA_ORBITAL_MAJOR if orbital_major else 0
         self._check(self._lib.green_theta(self._h, M, n, nw, _ptr(trial), _ptr(phi), _ptr(theta), _ptr(log_ovlp),
-                                          _ptr(info)))
+                                          _ptr(info), flags))
         return theta, log_ovlp, info
 
     def local_energy_full(self, lbar, theta, info=None, energy=None, precision=LO_FP64, flags=0):
@@ -243,10 +247,17 @@ class Context:
                                                 int(precision), int(flags), _ptr(energy)))
         return energy
 
-    def local_energy_lo(self, factors: Factors, theta, info=None, energy=None, precision=LO_FP64, flags=0):
+    def local_energy_lo(self, factors: Factors, theta, info=None, energy=None, precision=LO_FP64, flags=0,
+                        orbital_major=False):
+        """theta is [nw][M][n], or [n][M][nw] when orbital_major."""
         import torch
-        nw = theta.shape[0]
-        _check_dev("theta", theta, torch.complex128, (nw, factors.M, factors.n_occ))
+        if orbital_major:
+            nw = theta.shape[2]
+            _check_dev("theta", theta, torch.complex128, (factors.n_occ, factors.M, nw))
+            flags = flags | LO_THETA_ORBITAL_MAJOR
+        else:
+            nw = theta.shape[0]
+            _check_dev("theta", theta, torch.complex128, (nw, factors.M, factors.n_occ))
         if info is not None:
             _check_dev("info", info, torch.int32, (nw,))
         if energy is None:

@@ -96,6 +96,12 @@ def test_green_theta(ctx, M, n, nw):
     assert (info == 0).all()
     scale = np.abs(ref).max()
     assert np.abs(theta - ref).max() <= 1e-12 * scale
+    # orbital-major output [j][r][w] holds the same numbers
+    theta_om, logov_om, info_om = ctx.green_theta(dev(trial), dev(walkers), orbital_major=True)
+    theta_om = host(theta_om)
+    assert (host(info_om) == 0).all()
+    assert np.abs(theta_om.transpose(2, 1, 0) - ref).max() <= 1e-12 * scale
+    assert np.array_equal(host(logov_om), logov)
     # log det: real part exactly comparable, imaginary part modulo 2 pi
     assert np.abs(logov.real - ref_ld.real).max() <= 1e-11
     dphi = np.angle(np.exp(1j * (logov.imag - ref_ld.imag)))
@@ -169,6 +175,9 @@ def _lo_case(ctx, chol, trial, walkers, eps):
     f = ctx.build_lo_factors(lbar, eps)
     theta, _, info = ctx.green_theta(dev(trial), dev(walkers))
     got = host(ctx.local_energy_lo(f, theta, info))
+    theta_om, _, info_om = ctx.green_theta(dev(trial), dev(walkers), orbital_major=True)
+    got_om = host(ctx.local_energy_lo(f, theta_om, info_om, orbital_major=True))
+    assert np.array_equal(got.view(np.float64), got_om.view(np.float64))
     ref_f = E.lo_compress(lbar_ref, eps, pairs="upper")
     thetas, _ = oracle_thetas(trial, walkers)
     ref = E.e2_lo_batch(ref_f, thetas)
