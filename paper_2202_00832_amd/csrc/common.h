@@ -65,3 +65,13 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   o = __shfl_xor(v, 32, 64);
   return o > v ? o : v;
 }
+
+// Maximum of a 64-bit key over each row of 16 lanes (DPP only, no LDS-path
+// shuffles); every lane of the row receives its row's maximum.
+__device__ __forceinline__ unsigned long long row16_max_u64(unsigned long long v) {
+  v = dpp_max_u64(v, 0);   // quad_perm [1,0,3,2]
+  v = dpp_max_u64(v, 1);   // quad_perm [2,3,0,1]
+  v = dpp_max_u64(v, 2);   // row_half_mirror
+  v = dpp_max_u64(v, 3);   // row_mirror
+  return v;
+}

@@ -22,27 +22,54 @@ template <int NB>
 struct FullCfg {
   static constexpr int NP = 16 * NB;
   static constexpr int NPAIR = NB * (NB - 1) / 2;
+  static constexpr int NPH = (NPAIR + 1) / 2;          // off-diagonal pairs per half
+  static constexpr int NDH = (NB + 1) / 2;             // diagonal blocks per half
   static constexpr int TILE = 16 * NP;                 // 16 rows of r, NP orbitals
-  static constexpr int PER_THREAD = (TILE + 255) / 256;
+  static constexpr int PER_THREAD = (TILE + 511) / 512;
 };
 
+// 8 waves: walker slot ws = wave / 2 (four walkers per workgroup) and half
+// h = wave % 2; half h owns the off-diagonal pairs q with q % 2 == h and the
+// diagonal blocks I with I % 2 == h.
 template <int NB>
-__global__ __launch_bounds__(256, 1) void energy_full_kernel(int M, int n, int64_t X, int64_t nw, int64_t gchunk,
-                                                             int nchunk, const double* __restrict__ lbar,
+__global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64_t X, int64_t nw, int64_t gchunk,
+                                                             int nchunk, int64_t ngrp,
+                                                             const double* __restrict__ lbar,
                                                              const double2* __restrict__ theta,
                                                              double* __restrict__ partial) {
   using C = FullCfg<NB>;
   constexpr int NP = C::NP;
   __shared__ double sL[2][C::TILE];
-  __shared__ double2 sDiag[4][NB][256];
+  __shared__ double2 sDiag[8][C::NDH][256];
+  __shared__ double2 sTr[8];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
+  const int ws = wv >> 1, h = wv & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  const int64_t grp = blockIdx.x / nchunk;
-  const int64_t chunk = blockIdx.x % nchunk;
-  const int64_t w = 4 * grp + wv;
+  // XCD-aware order (workgroups go round-robin over 8 XCDs): the workgroups
+  // of one XCD share a chunk of Cholesky vectors, so each Lbar tile is read
+  // into that XCD's L2 once.
+  int64_t chunk, grp;
+  {
+    const int64_t b = blockIdx.x;
+    const int xcd = (int)(b & 7);
+    const int64_t slot = b >> 3;
+    const int64_t lin = slot * 8 + xcd;           // default linear order
+    if (nchunk % 8 == 0 || 8 % nchunk == 0) {
+      // chunk-major within an XCD
+      const int per_xcd_chunks = nchunk >= 8 ? nchunk / 8 : 1;
+      const int xcds_per_chunk = nchunk >= 8 ? 1 : 8 / nchunk;
+      chunk = (int64_t)(xcd / xcds_per_chunk) * per_xcd_chunks + (slot % per_xcd_chunks);
+      grp = (slot / per_xcd_chunks) * xcds_per_chunk + (xcd % xcds_per_chunk);
+    } else {
+      chunk = lin % nchunk;
+      grp = lin / nchunk;
+    }
+    if (grp >= ngrp || chunk >= nchunk) return;
+  }
+  const int64_t w = 4 * grp + ws;
   const bool wok = w < nw;
   const double2* th = theta + (wok ? w : 0) * (size_t)M * n;
   const int64_t g0 = chunk * gchunk;
@@ -50,7 +77,6 @@ __global__ __launch_bounds__(256, 1) void energy_full_kernel(int M, int n, int64
   const int nkt = (M + 15) / 16;
   const int64_t ntiles = (g1 > g0) ? (g1 - g0) * nkt : 0;
 
-  // cooperative load of Lbar tile t (g = g0 + t / nkt, rows 16 * (t % nkt) ...)
   double pre[C::PER_THREAD];
   auto load_tile = [&](int64_t t) {
     const int64_t g = g0 + t / nkt;
@@ -58,7 +84,7 @@ __global__ __launch_bounds__(256, 1) void energy_full_kernel(int M, int n, int64
     const double* Lg = lbar + (size_t)g * M * n;
 #pragma unroll
     for (int q = 0; q < C::PER_THREAD; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + 512 * q;
       const int rr = e / NP, i = e % NP;
       const int r = rbase + rr;
       pre[q] = (e < C::TILE && r < M && i < n) ? Lg[(size_t)r * n + i] : 0.0;
@@ -67,27 +93,63 @@ __global__ __launch_bounds__(256, 1) void energy_full_kernel(int M, int n, int64
   auto store_tile = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < C::PER_THREAD; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + 512 * q;
       if (e < C::TILE) sL[buf][e] = pre[q];
     }
   };
+  // theta fragments of K-step u (r = 4 u' + lk within the current g)
+  auto load_theta = [&](int kstep, double2 (&tf)[NB]) {
+    const int r = 4 * kstep + lk;
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+      const int j = 16 * I + lr;
+      tf[I] = (wok && r < M && j < n) ? th[(size_t)r * n + j] : make_double2(0.0, 0.0);
+    }
+  };
 
-  d4 dRe[C::NPAIR > 0 ? C::NPAIR : 1], dIm[C::NPAIR > 0 ? C::NPAIR : 1];
-  d4 tRe[C::NPAIR > 0 ? C::NPAIR : 1], tIm[C::NPAIR > 0 ? C::NPAIR : 1];
-  d4 gRe[NB], gIm[NB];
+  d4 dRe[C::NPH > 0 ? C::NPH : 1], dIm[C::NPH > 0 ? C::NPH : 1];
+  d4 tRe[C::NPH > 0 ? C::NPH : 1], tIm[C::NPH > 0 ? C::NPH : 1];
+  d4 gRe[C::NDH], gIm[C::NDH];
   double accJr = 0.0, accJi = 0.0, accKr = 0.0, accKi = 0.0;
-
   auto zero_acc = [&]() {
 #pragma unroll
-    for (int q = 0; q < C::NPAIR; ++q) { dRe[q] = d4zero(); dIm[q] = d4zero(); tRe[q] = d4zero(); tIm[q] = d4zero(); }
+    for (int q = 0; q < C::NPH; ++q) { dRe[q] = d4zero(); dIm[q] = d4zero(); tRe[q] = d4zero(); tIm[q] = d4zero(); }
 #pragma unroll
-    for (int I = 0; I < NB; ++I) { gRe[I] = d4zero(); gIm[I] = d4zero(); }
+    for (int q = 0; q < C::NDH; ++q) { gRe[q] = d4zero(); gIm[q] = d4zero(); }
   };
   zero_acc();
 
+  auto mma_step = [&](const double* Lt, int s, const double2 (&tf)[NB]) {
+    double Lf[NB];
+#pragma unroll
+    for (int I = 0; I < NB; ++I) Lf[I] = Lt[(4 * s + lk) * NP + 16 * I + lr];
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+      if ((I & 1) == h) {
+        gRe[I >> 1] = mfma16(Lf[I], tf[I].x, gRe[I >> 1]);
+        gIm[I >> 1] = mfma16(Lf[I], tf[I].y, gIm[I >> 1]);
+      }
+    }
+    int q = 0;   // flattened pair index (static after unrolling)
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+#pragma unroll
+      for (int J = I + 1; J < NB; ++J, ++q) {
+        if ((q & 1) == h) {
+          dRe[q >> 1] = mfma16(Lf[I], tf[J].x, dRe[q >> 1]);
+          dIm[q >> 1] = mfma16(Lf[I], tf[J].y, dIm[q >> 1]);
+          tRe[q >> 1] = mfma16(tf[I].x, Lf[J], tRe[q >> 1]);
+          tIm[q >> 1] = mfma16(tf[I].y, Lf[J], tIm[q >> 1]);
+        }
+      }
+    }
+  };
+
+  double2 tfa[NB], tfb[NB];
   if (ntiles > 0) {
     load_tile(0);
     store_tile(0);
+    load_theta(0, tfa);
   }
   __syncthreads();
 
@@ -95,68 +157,62 @@ __global__ __launch_bounds__(256, 1) void energy_full_kernel(int M, int n, int64
     const int buf = (int)(t & 1);
     if (t + 1 < ntiles) load_tile(t + 1);
     const int kt = (int)(t % nkt);
+    const int ktn = (kt + 1 == nkt) ? 0 : kt + 1;   // next tile's row block (same or next g)
     const double* Lt = sL[buf];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int r = 16 * kt + 4 * s + lk;
-      double Lf[NB];
-      double2 tf[NB];
-#pragma unroll
-      for (int I = 0; I < NB; ++I) {
-        Lf[I] = Lt[(4 * s + lk) * NP + 16 * I + lr];
-        const int j = 16 * I + lr;
-        tf[I] = (wok && r < M && j < n) ? th[(size_t)r * n + j] : make_double2(0.0, 0.0);
-      }
-      int q = 0;
-#pragma unroll
-      for (int I = 0; I < NB; ++I) {
-        gRe[I] = mfma16(Lf[I], tf[I].x, gRe[I]);
-        gIm[I] = mfma16(Lf[I], tf[I].y, gIm[I]);
-#pragma unroll
-        for (int J = I + 1; J < NB; ++J, ++q) {
-          dRe[q] = mfma16(Lf[I], tf[J].x, dRe[q]);
-          dIm[q] = mfma16(Lf[I], tf[J].y, dIm[q]);
-          tRe[q] = mfma16(tf[I].x, Lf[J], tRe[q]);
-          tIm[q] = mfma16(tf[I].y, Lf[J], tIm[q]);
-        }
-      }
-    }
+    // K-steps 4 kt .. 4 kt + 3; theta of the next K-step is loaded one step ahead
+    load_theta(4 * kt + 1, tfb);
+    mma_step(Lt, 0, tfa);
+    load_theta(4 * kt + 2, tfa);
+    mma_step(Lt, 1, tfb);
+    load_theta(4 * kt + 3, tfb);
+    mma_step(Lt, 2, tfa);
+    load_theta(4 * ktn, tfa);
+    mma_step(Lt, 3, tfb);
     if (t + 1 < ntiles) store_tile(buf ^ 1);
 
     if (kt == nkt - 1) {
       // ---- epilogue for this g: Coulomb trace and exchange sum
       double xr = 0.0, xi = 0.0, cr = 0.0, ci = 0.0;
 #pragma unroll
-      for (int q2 = 0; q2 < C::NPAIR; ++q2) {
+      for (int q2 = 0; q2 < C::NPH; ++q2) {
+        if (2 * q2 + h < C::NPAIR) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          xr += 2.0 * (dRe[q2][v] * tRe[q2][v] - dIm[q2][v] * tIm[q2][v]);
-          xi += 2.0 * (dRe[q2][v] * tIm[q2][v] + dIm[q2][v] * tRe[q2][v]);
+          for (int v = 0; v < 4; ++v) {
+            xr += 2.0 * (dRe[q2][v] * tRe[q2][v] - dIm[q2][v] * tIm[q2][v]);
+            xi += 2.0 * (dRe[q2][v] * tIm[q2][v] + dIm[q2][v] * tRe[q2][v]);
+          }
         }
       }
 #pragma unroll
-      for (int I = 0; I < NB; ++I) {
+      for (int q = 0; q < C::NDH; ++q) {
+        if (2 * q + h < NB) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          sDiag[wv][I][(4 * v + lk) * 16 + lr] = make_double2(gRe[I][v], gIm[I][v]);
-          if (4 * v + lk == lr) { cr += gRe[I][v]; ci += gIm[I][v]; }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int I = 0; I < NB; ++I) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double2 pv = sDiag[wv][I][lr * 16 + 4 * v + lk];
-          xr += gRe[I][v] * pv.x - gIm[I][v] * pv.y;
-          xi += gRe[I][v] * pv.y + gIm[I][v] * pv.x;
+          for (int v = 0; v < 4; ++v) {
+            sDiag[wv][q][(4 * v + lk) * 16 + lr] = make_double2(gRe[q][v], gIm[q][v]);
+            if (4 * v + lk == lr) { cr += gRe[q][v]; ci += gIm[q][v]; }
+          }
         }
       }
       cr = wave_sum_lane0(cr);
       ci = wave_sum_lane0(ci);
-      if (lane == 0) {
-        accJr += cr * cr - ci * ci;
-        accJi += 2.0 * cr * ci;
+      if (lane == 0) sTr[wv] = make_double2(cr, ci);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < C::NDH; ++q) {
+        if (2 * q + h < NB) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double2 pv = sDiag[wv][q][lr * 16 + 4 * v + lk];
+            xr += gRe[q][v] * pv.x - gIm[q][v] * pv.y;
+            xi += gRe[q][v] * pv.y + gIm[q][v] * pv.x;
+          }
+        }
+      }
+      if (h == 0 && lane == 0) {
+        const double2 c0 = sTr[wv], c1 = sTr[wv + 1];
+        const double tr = c0.x + c1.x, ti = c0.y + c1.y;
+        accJr += tr * tr - ti * ti;
+        accJi += 2.0 * tr * ti;
       }
       accKr += xr;
       accKi += xi;
@@ -165,14 +221,18 @@ __global__ __launch_bounds__(256, 1) void energy_full_kernel(int M, int n, int64
     __syncthreads();
   }
 
+  // per-walker partial: the two halves are combined through LDS in a fixed order
   accKr = wave_sum_lane0(accKr);
   accKi = wave_sum_lane0(accKi);
-  if (wok && lane == 0) {
+  if (lane == 0) sTr[wv] = make_double2(accKr, accKi);
+  __syncthreads();
+  if (wok && h == 0 && lane == 0) {
+    const double2 k0 = sTr[wv], k1 = sTr[wv + 1];
     double* out = partial + ((size_t)chunk * nw + w) * 4;
     out[0] = 2.0 * accJr;
     out[1] = 2.0 * accJi;
-    out[2] = -accKr;
-    out[3] = -accKi;
+    out[2] = -(k0.x + k1.x);
+    out[3] = -(k0.y + k1.y);
   }
 }
 
@@ -208,18 +268,26 @@ static hipError_t launch_full_nb(hipStream_t s, int M, int n, int64_t X, int64_t
                                  const double* theta, double* partial, int nchunk) {
   const int64_t ngrp = (nw + 3) / 4;
   const int64_t gchunk = (X + nchunk - 1) / nchunk;
-  hipLaunchKernelGGL(energy_full_kernel<NB>, dim3((unsigned)(ngrp * nchunk)), dim3(256), 0, s, M, n, X, nw,
-                     gchunk, nchunk, lbar, (const double2*)theta, partial);
+  // grid covers every (group, chunk); the XCD-aware order may leave a few
+  // slots without work, which return at once
+  int64_t grid = ngrp * nchunk;
+  if (nchunk % 8 == 0 || 8 % nchunk == 0) {
+    const int per_xcd_chunks = nchunk >= 8 ? nchunk / 8 : 1;
+    const int xcds_per_chunk = nchunk >= 8 ? 1 : 8 / nchunk;
+    const int64_t slots = per_xcd_chunks * ((ngrp + xcds_per_chunk - 1) / xcds_per_chunk);
+    grid = 8 * slots;
+  }
+  hipLaunchKernelGGL(energy_full_kernel<NB>, dim3((unsigned)grid), dim3(512), 0, s, M, n, X, nw, gchunk, nchunk,
+                     ngrp, lbar, (const double2*)theta, partial);
   return hipGetLastError();
 }
 
 int full_num_chunks(int64_t X, int64_t nw) {
-  // about two workgroups per compute unit (256 CUs) when there are few walkers
+  // one workgroup (8 waves) per compute unit (256 CUs): chunks of Cholesky
+  // vectors so that groups x chunks covers the machine about once
   const int64_t ngrp = (nw + 3) / 4;
-  int64_t c = (512 + ngrp - 1) / ngrp;
-  if (c < 1) c = 1;
-  if (c > X) c = X > 0 ? X : 1;
-  if (c > 4096) c = 4096;
+  int64_t c = 1;
+  while (c < 4096 && ngrp * c < 256 && c < X) c *= 2;
   return (int)c;
 }
 

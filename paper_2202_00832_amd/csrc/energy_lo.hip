@@ -49,11 +49,12 @@ hipError_t launch_theta_transpose(hipStream_t s, int M, int n, int64_t nw, const
 // Pass 1: tile = up to LO_TILE_ROWS output rows of one orbital o x 32
 // walkers.  Per 16-row slab of r the factor rows (gathered through rowidx)
 // and Q_o of the 32 walkers are staged in LDS (double-buffered).  Wave q
-// takes walker half q / 2 and the real (q even) or imaginary part, against
-// every 16-row block of the tile, so the MFMA count follows the real row
-// count of the tile.
+// owns the 16-row blocks q, q+4, q+8 of the tile against all four column
+// blocks (two 16-walker halves, real and imaginary part), so every factor
+// fragment is read from LDS once and feeds four MFMAs.
 constexpr int LO_TILE_ROWS = 192;
-constexpr int LO_RB = LO_TILE_ROWS / 16;
+constexpr int LO_RB = LO_TILE_ROWS / 16;     // 12 row blocks per tile
+constexpr int LO_RBW = LO_RB / 4;            // 3 per wave
 constexpr int LO_WT = 32;
 
 __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
@@ -80,7 +81,6 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int half = wv >> 1, part = wv & 1;
   const double2* tho = thetaT + (size_t)o * M * nw;
 
   // staging: A = nrows x 16 doubles (each row 128 contiguous bytes), B = 16 x 32 complex
@@ -119,9 +119,11 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
     }
   };
 
-  d4 acc[LO_RB];
+  d4 acc[LO_RBW][4];   // [row block][half * 2 + part]
 #pragma unroll
-  for (int b = 0; b < LO_RB; ++b) acc[b] = d4zero();
+  for (int i = 0; i < LO_RBW; ++i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[i][c] = d4zero();
   const int nchunk = (M + 15) / 16;
   load(0);
   store(0);
@@ -132,27 +134,38 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const int rr = 4 * s4 + lk;
-      const double2 bv = sB[buf][rr][16 * half + lr];
-      const double b = part ? bv.y : bv.x;
+      const double2 b0 = sB[buf][rr][lr];
+      const double2 b1 = sB[buf][rr][16 + lr];
 #pragma unroll
-      for (int rb = 0; rb < LO_RB; ++rb) {
-        if (rb < nrb) acc[rb] = mfma16(sA[buf][16 * rb + lr][rr], b, acc[rb]);
+      for (int i = 0; i < LO_RBW; ++i) {
+        const int rb = wv + 4 * i;
+        if (rb < nrb) {
+          const double a = sA[buf][16 * rb + lr][rr];
+          acc[i][0] = mfma16(a, b0.x, acc[i][0]);
+          acc[i][1] = mfma16(a, b0.y, acc[i][1]);
+          acc[i][2] = mfma16(a, b1.x, acc[i][2]);
+          acc[i][3] = mfma16(a, b1.y, acc[i][3]);
+        }
       }
     }
     if (c + 1 < nchunk) store(buf ^ 1);
     __syncthreads();
   }
   // D[row][walker]: lane holds rows 4v + lk of each block, walker 16*half + lr
-  const int64_t w = w0 + 16 * half + lr;
-  if (w < nw) {
-    double* q = reinterpret_cast<double*>(qbar);
 #pragma unroll
-    for (int rb = 0; rb < LO_RB; ++rb) {
-      if (rb < nrb) {
+  for (int h = 0; h < 2; ++h) {
+    const int64_t w = w0 + 16 * h + lr;
+    if (w < nw) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int lrow = 16 * rb + 4 * v + lk;
-          if (lrow < nrows) q[((size_t)(row0 + lrow) * nw + w) * 2 + part] = acc[rb][v];
+      for (int i = 0; i < LO_RBW; ++i) {
+        const int rb = wv + 4 * i;
+        if (rb < nrb) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lrow = 16 * rb + 4 * v + lk;
+            if (lrow < nrows)
+              qbar[(size_t)(row0 + lrow) * nw + w] = make_double2(acc[i][2 * h][v], acc[i][2 * h + 1][v]);
+          }
         }
       }
     }

@@ -72,36 +72,32 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
 #pragma unroll
   for (int p = 0; p < PPW; ++p) { accR[p] = d4zero(); accI[p] = d4zero(); }
 
-  double2 preP[C::PER];
-  double preS[C::PER];
-  auto load_slab = [&](int c) {
+  // slab c is loaded into registers two iterations before it is consumed
+  // (three register sets), stored to LDS one iteration before, double-buffered
+  double2 pP0[C::PER], pP1[C::PER], pP2[C::PER];
+  double pS0[C::PER], pS1[C::PER], pS2[C::PER];
+  auto load_slab = [&](int c, double2 (&dP)[C::PER], double (&dS)[C::PER]) {
 #pragma unroll
     for (int q = 0; q < C::PER; ++q) {
       const int s = tid + 256 * q;
       const int rr = s / NP, j = s % NP;
       const int r = C::KC * c + rr;
       const bool ok = s < C::PH_SLOTS && r < M && j < n;
-      preP[q] = ok ? ph[(size_t)r * n + j] : make_double2(0.0, 0.0);
-      preS[q] = ok ? trial[(size_t)r * n + j] : 0.0;
+      dP[q] = ok ? ph[(size_t)r * n + j] : make_double2(0.0, 0.0);
+      dS[q] = ok ? trial[(size_t)r * n + j] : 0.0;
     }
   };
-  auto store_slab = [&](int buf) {
+  auto store_slab = [&](int buf, const double2 (&sP)[C::PER], const double (&sS)[C::PER]) {
 #pragma unroll
     for (int q = 0; q < C::PER; ++q) {
       const int s = tid + 256 * q;
       if (s < C::PH_SLOTS) {
-        sPh[buf * C::PH_SLOTS + s] = preP[q];
-        sPs[buf * C::PH_SLOTS + s] = preS[q];
+        sPh[buf * C::PH_SLOTS + s] = sP[q];
+        sPs[buf * C::PH_SLOTS + s] = sS[q];
       }
     }
   };
-  const int nslab = (M + C::KC - 1) / C::KC;
-  load_slab(0);
-  store_slab(0);
-  __syncthreads();
-  for (int c = 0; c < nslab; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nslab) load_slab(c + 1);
+  auto mma_slab = [&](int buf) {
     const double2* P = sPh + buf * C::PH_SLOTS;
     const double* S = sPs + buf * C::PH_SLOTS;
 #pragma unroll
@@ -130,8 +126,24 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
         }
       }
     }
-    if (c + 1 < nslab) store_slab(buf ^ 1);
+  };
+  const int nslab = (M + C::KC - 1) / C::KC;
+  // iteration c: issue slab c+2, multiply slab c, store slab c+1
+  auto iter = [&](int c, double2 (&nP)[C::PER], double (&nS)[C::PER], const double2 (&sP)[C::PER],
+                  const double (&sS)[C::PER]) {
+    if (c + 2 < nslab) load_slab(c + 2, nP, nS);
+    mma_slab(c & 1);
+    if (c + 1 < nslab) store_slab((c + 1) & 1, sP, sS);
     __syncthreads();
+  };
+  load_slab(0, pP0, pS0);
+  if (nslab > 1) load_slab(1, pP1, pS1);
+  store_slab(0, pP0, pS0);
+  __syncthreads();
+  for (int c = 0; c < nslab; c += 3) {
+    iter(c, pP2, pS2, pP1, pS1);
+    if (c + 1 < nslab) iter(c + 1, pP0, pS0, pP2, pS2);
+    if (c + 2 < nslab) iter(c + 2, pP1, pS1, pP0, pS0);
   }
 
   // phase-1 staging is dead; the same LDS now holds O, then O^{-1}
@@ -163,26 +175,35 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
   }
   __syncthreads();
 
-  bool used = lane >= n;     // lane <-> row index, replicated in every wave
+  // pivot bookkeeping, replicated in every lane: lane l tracks rows
+  // (l & 15) + 16 m, m < NB, as bit m of `used`
+  unsigned used = 0u;
+#pragma unroll
+  for (int m = 0; m < NB; ++m)
+    if ((lr + 16 * m) >= n) used |= 1u << m;
   int zero = 0;
   for (int k = 0; k < n; ++k) {
     const double2* col = sColBuf + (k & 1) * NP;
-    // pivot search, identical in every wave: key = |re|+|im| (46 leading
-    // bits, monotone as an integer) with 63 - row in the low 6 bits
-    const double2 cv = (lane < NP) ? col[lane] : make_double2(0.0, 0.0);
+    // pivot search, identical in every 16-lane row of every wave: key =
+    // |re|+|im| (46 leading bits, monotone as an integer) with 63 - row in the
+    // low 6 bits; max over the lane's NB rows, then over the 16 lanes (DPP)
     unsigned long long key = 0ull;
-    if (!used) {
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+      const double2 cv = col[lr + 16 * m];
       const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(cv.x) + fabs(cv.y));
-      key = (mb & ~63ull) | (unsigned long long)(63 - lane);
+      const unsigned long long km = (used >> m & 1u) ? 0ull : ((mb & ~63ull) | (unsigned long long)(63 - (lr + 16 * m)));
+      key = km > key ? km : key;
     }
-    key = wave_max_u64(key);
+    key = row16_max_u64(key);
     const int p = __builtin_amdgcn_readfirstlane(63 - (int)(key & 63ull));
     if ((key >> 6) == 0ull) { zero = k + 1; break; }
-    used = used || (lane == p);
-    double2 piv;
-    piv.x = __shfl(cv.x, p, 64);
-    piv.y = __shfl(cv.y, p, 64);
-    const double2 inv = crecip(piv);
+    if ((p & 15) == lr) used |= 1u << (p >> 4);
+    const double2 piv = col[p];                 // uniform LDS address: broadcast read
+    // 1/piv = conj(piv) / |piv|^2 (O is an overlap of normalised orbitals, far
+    // from the over/underflow range of |piv|^2)
+    const double rn = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+    const double2 inv = make_double2(piv.x * rn, -piv.y * rn);
     if (tid == 0) {
       sPiv[k] = p;
       sPivV[k] = piv;
@@ -196,27 +217,50 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
         }
     }
     __syncthreads();
-    // exchange step on pivot (p, k); the owners of column k+1 publish it
-    double2* ncol = sColBuf + ((k + 1) & 1) * NP;
+    // exchange step on pivot (p, k); all LDS reads issued first.  With
+    // c'_i = A[i][k] + [i == p] every element takes the same update
+    //   A[i][j] -= c'_i R[j],  R[j] = A[p][j] / pivot,
+    // which gives A[i][j] - A[i][k] R[j] off the pivot row and -R[j] on it
+    // (the exchange operator); column k is then overwritten by its owners
+    // with A[i][k] / pivot (1 / pivot on the pivot row).
+    double2 cik[NB], rpj[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) cik[a] = col[ty + 16 * a];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) rpj[b] = sRow[tx + 16 * b];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
-      const int i = ty + 16 * a;
-      const double2 cik = col[i];
+      double2 c = cik[a];
+      c.x += ((ty + 16 * a) == p) ? 1.0 : 0.0;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const int j = tx + 16 * b;
-        const double2 rpj = sRow[j];
+        const double2 r = rpj[b];
         double2 v = e[a][b];
-        if (i == p) {
-          v = (j == k) ? inv : make_double2(-rpj.x, -rpj.y);
-        } else if (j == k) {
-          v = cmul(cik, inv);
-        } else {
-          v = csub(v, cmul(cik, rpj));
-        }
+        v.x = fma(-c.x, r.x, fma(c.y, r.y, v.x));
+        v.y = fma(-c.x, r.y, fma(-c.y, r.x, v.y));
         e[a][b] = v;
-        if (j == k + 1) ncol[i] = v;
       }
+    }
+    if (tx == (k & 15)) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (b == (k >> 4)) {
+#pragma unroll
+          for (int a = 0; a < NB; ++a) {
+            const double2 cc = ((ty + 16 * a) == p) ? make_double2(1.0, 0.0) : cik[a];
+            e[a][b] = cmul(cc, inv);
+          }
+        }
+    }
+    // the owners of column k+1 publish it for the next step
+    if (k + 1 < n && tx == ((k + 1) & 15)) {
+      double2* ncol = sColBuf + ((k + 1) & 1) * NP;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (b == ((k + 1) >> 4)) {
+#pragma unroll
+          for (int a = 0; a < NB; ++a) ncol[ty + 16 * a] = e[a][b];
+        }
     }
     __syncthreads();
   }
