@@ -110,7 +110,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=16, help="walkers timed on the CPU reference")
+    ap.add_argument("--cpu-sample", type=int, default=256,
+                    help="walkers timed on the CPU reference (about 10 s of host work at the default)")
+    ap.add_argument("--eps", type=str, default="",
+                    help="comma-separated LO thresholds to run instead of the workload's sweep")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -161,7 +164,8 @@ def main():
 
     sweep = []
     factors = {}
-    for eps in cfg.epsilons:
+    epsilons = [float(e) for e in args.eps.split(",")] if args.eps else list(cfg.epsilons)
+    for eps in epsilons:
         t = time.perf_counter()
         f = ctx.build_lo_factors(lbar, eps)
         t_build = time.perf_counter() - t

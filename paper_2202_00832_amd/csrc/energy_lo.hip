@@ -88,14 +88,20 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
   constexpr int B_PER = (16 * LO_WT + 255) / 256;          // 2
   double pa[A_PER];
   double2 pb[B_PER];
+  // the gathered factor rows of this thread, resolved once (a row index read
+  // inside the slab loop would put a dependent global load on every slab)
+  const double* arow[A_PER];
+#pragma unroll
+  for (int q = 0; q < A_PER; ++q) {
+    const int row = (tid + 256 * q) >> 4;
+    arow[q] = row < nrows ? rows + (size_t)rowidx[row0 + row] * M : nullptr;
+  }
   auto load = [&](int c) {
     const int rbase = 16 * c;
 #pragma unroll
     for (int q = 0; q < A_PER; ++q) {
-      const int e = tid + 256 * q;
-      const int row = e >> 4, rr = e & 15;
-      const int r = rbase + rr;
-      pa[q] = (row < nrows && r < M) ? rows[(size_t)rowidx[row0 + row] * M + r] : 0.0;
+      const int r = rbase + ((tid + 256 * q) & 15);
+      pa[q] = (arow[q] != nullptr && r < M) ? arow[q][r] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < B_PER; ++q) {

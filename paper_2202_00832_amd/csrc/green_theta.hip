@@ -1,21 +1,23 @@
 // Green's-function intermediate Q = theta = phi (Psi_T^T phi)^{-1} (Eq. 15)
-// for a batch of walkers, FP64.  One workgroup (4 waves) per walker:
-//   1. O = Psi_T^T phi on MFMA (real trial x complex walker -> two real
-//      16x16 blocks per block pair).  16-row slabs of phi and Psi_T are
-//      staged in LDS with coalesced loads, double-buffered.
-//   2. In-place Gauss-Jordan exchange with partial pivoting (largest
-//      |re|+|im| among the rows not yet used as pivots, compared to 46 bits,
-//      lowest row on ties), 4x4 register blocks per thread.  Every wave
-//      repeats the pivot search (a DPP max over a 64-bit key) on the published
-//      column, so a step needs two barriers.  Gives O^{-1}, the pivots (for
-//      log det O, summed afterwards in parallel) and the zero-pivot index.
-//   3. theta = phi O^{-1} on MFMA with three real products per complex block
-//      (re = P1 - P2, im = P3 - P1 - P2 with P1 = a_re b_re, P2 = a_im b_im,
-//      P3 = (a_re + a_im)(b_re + b_im)), O^{-1} from LDS, the next half slab
-//      of phi prefetched into registers while the current one is multiplied.
-//      theta is written walker-major [w][r][j] or, with the orbital-major
-//      flag, as [j][r][w]; then consecutive walkers are placed on the same XCD
-//      so that the interleaved 16-byte stores meet in one L2.
+// for a batch of walkers, FP64, as three kernels so that the latency-bound
+// elimination does not hold the MFMA work back:
+//   1. overlap_kernel: O_w = Psi_T^T phi_w on v_mfma_f64_16x16x4_f64 (real
+//      trial x complex walker -> two real 16x16 blocks per block pair);
+//      16-row slabs of phi_w and Psi_T are staged in LDS with coalesced loads,
+//      prefetched two slabs ahead.  One workgroup per walker.
+//   2. invert_kernel: in-place Gauss-Jordan exchange with partial pivoting
+//      (largest |re|+|im| among the rows not yet used as pivots, compared to
+//      46 bits, lowest row on ties), 4x4 complex register blocks per thread,
+//      two barriers per step, the pivot argmax a DPP max inside 16-lane rows.
+//      Gives O^{-1}, log det O and the zero-pivot index.  Needs little LDS,
+//      so several walkers share a compute unit.
+//   3. apply_kernel: theta = phi O^{-1} on MFMA with three real products per
+//      complex block (re = P1 - P2, im = P3 - P1 - P2 with P1 = a_re b_re,
+//      P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im)); one workgroup per
+//      walker with O^{-1} in LDS, one wave per 16-row block.  theta is written
+//      walker-major [w][r][j] or, with the orbital-major flag, as [j][r][w];
+//      walkers 8g .. 8g+7 then run on the same XCD so that their interleaved
+//      16-byte stores meet in one L2.
 #include "common.h"
 #include "kernels.h"
 
@@ -24,56 +26,35 @@ namespace lofqmc {
 template <int NB>
 struct GtCfg {
   static constexpr int NP = 16 * NB;
-  static constexpr int KC = 16;                                    // rows of r per phase-1 slab
-  static constexpr int PH_SLOTS = KC * NP;                         // complex slots of a phi slab
-  static constexpr int PER = (PH_SLOTS + 255) / 256;
-  static constexpr size_t P1_BYTES = 2 * PH_SLOTS * sizeof(double2) + 2 * PH_SLOTS * sizeof(double);
-  static constexpr size_t P2_BYTES = (size_t)(NP * NP + 3 * NP) * sizeof(double2);
-  static constexpr size_t LDS = P1_BYTES > P2_BYTES ? P1_BYTES : P2_BYTES;
-  static constexpr int NKS = NP / 4;                               // max K-steps of phase 3
-  static constexpr int NKH = NKS / 2;                              // K-steps per prefetched half slab
+  static constexpr int KC = 16;                // rows of r per overlap slab
+  static constexpr int SLOTS = KC * NP;        // complex slots of a phi slab
+  static constexpr int PER = (SLOTS + 255) / 256;
+  static constexpr int NKS = NP / 4;           // K-steps of theta = phi O^{-1}
 };
 
+// ---------------------------------------------------------------------------
+// 1. O_w = Psi_T^T phi_w, written as a padded NP x NP complex block per walker
+// ---------------------------------------------------------------------------
 template <int NB>
-__global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const double* __restrict__ trial,
-                                                             const double2* __restrict__ phi,
-                                                             double2* __restrict__ theta,
-                                                             double2* __restrict__ logov, int* __restrict__ info,
-                                                             int orbital_major, int64_t nw) {
+__global__ __launch_bounds__(256) void overlap_kernel(int M, int n, const double* __restrict__ trial,
+                                                      const double2* __restrict__ phi,
+                                                      double2* __restrict__ O) {
   using C = GtCfg<NB>;
   constexpr int NP = C::NP;
-  extern __shared__ double4 smem_raw[];
-  char* smem = reinterpret_cast<char*>(smem_raw);
-  __shared__ int sPiv[NP];
-  __shared__ int sPinv[NP];
-  __shared__ double2 sPivV[NP];
-
+  __shared__ double2 sPh[2][C::SLOTS];
+  __shared__ double sPs[2][C::SLOTS];
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wv = tid >> 6;
-  const int lr = lane & 15;   // row of A / column of B and D within a 16-block
-  const int lk = lane >> 4;   // k index of A and B, row group of D
-  // orbital-major output: walkers w..w+7 share 128-byte lines of theta, so
-  // keep consecutive walkers on one XCD (workgroups go round-robin over 8 XCDs)
-  size_t w = blockIdx.x;
-  if (orbital_major) {
-    const size_t per = (nw + 7) / 8;
-    w = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (w >= (size_t)nw) return;
-  }
+  const int lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const size_t w = blockIdx.x;
   const double2* ph = phi + w * (size_t)M * n;
 
-  // ---------------------------------------------------------------- phase 1
-  double2* sPh = reinterpret_cast<double2*>(smem);                          // [2][KC][NP]
-  double* sPs = reinterpret_cast<double*>(smem + 2 * C::PH_SLOTS * sizeof(double2));  // [2][KC][NP]
   constexpr int NPAIR = NB * NB;
   constexpr int PPW = (NPAIR + 3) / 4;
   d4 accR[PPW], accI[PPW];
 #pragma unroll
   for (int p = 0; p < PPW; ++p) { accR[p] = d4zero(); accI[p] = d4zero(); }
 
-  // slab c is loaded into registers two iterations before it is consumed
-  // (three register sets), stored to LDS one iteration before, double-buffered
   double2 pP0[C::PER], pP1[C::PER], pP2[C::PER];
   double pS0[C::PER], pS1[C::PER], pS2[C::PER];
   auto load_slab = [&](int c, double2 (&dP)[C::PER], double (&dS)[C::PER]) {
@@ -82,7 +63,7 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
       const int s = tid + 256 * q;
       const int rr = s / NP, j = s % NP;
       const int r = C::KC * c + rr;
-      const bool ok = s < C::PH_SLOTS && r < M && j < n;
+      const bool ok = s < C::SLOTS && r < M && j < n;
       dP[q] = ok ? ph[(size_t)r * n + j] : make_double2(0.0, 0.0);
       dS[q] = ok ? trial[(size_t)r * n + j] : 0.0;
     }
@@ -91,24 +72,22 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
 #pragma unroll
     for (int q = 0; q < C::PER; ++q) {
       const int s = tid + 256 * q;
-      if (s < C::PH_SLOTS) {
-        sPh[buf * C::PH_SLOTS + s] = sP[q];
-        sPs[buf * C::PH_SLOTS + s] = sS[q];
+      if (s < C::SLOTS) {
+        sPh[buf][s] = sP[q];
+        sPs[buf][s] = sS[q];
       }
     }
   };
   auto mma_slab = [&](int buf) {
-    const double2* P = sPh + buf * C::PH_SLOTS;
-    const double* S = sPs + buf * C::PH_SLOTS;
 #pragma unroll
     for (int s4 = 0; s4 < C::KC / 4; ++s4) {
       const int row = (4 * s4 + lk) * NP;
       if constexpr (NB == 4) {
         // wave q owns the pairs (I, q): one B fragment per K-step
-        const double2 b = P[row + 16 * wv + lr];
+        const double2 b = sPh[buf][row + 16 * wv + lr];
 #pragma unroll
         for (int p = 0; p < PPW; ++p) {
-          const double a = S[row + 16 * p + lr];
+          const double a = sPs[buf][row + 16 * p + lr];
           accR[p] = mfma16(a, b.x, accR[p]);
           accI[p] = mfma16(a, b.y, accI[p]);
         }
@@ -118,8 +97,8 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
           const int bp = wv + 4 * p;
           if (bp < NPAIR) {
             const int I = bp / NB, J = bp % NB;
-            const double a = S[row + 16 * I + lr];
-            const double2 b = P[row + 16 * J + lr];
+            const double a = sPs[buf][row + 16 * I + lr];
+            const double2 b = sPh[buf][row + 16 * J + lr];
             accR[p] = mfma16(a, b.x, accR[p]);
             accI[p] = mfma16(a, b.y, accI[p]);
           }
@@ -145,45 +124,56 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
     if (c + 1 < nslab) iter(c + 1, pP0, pS0, pP2, pS2);
     if (c + 2 < nslab) iter(c + 2, pP1, pS1, pP0, pS0);
   }
-
-  // phase-1 staging is dead; the same LDS now holds O, then O^{-1}
-  double2* sO = reinterpret_cast<double2*>(smem);   // [NP][NP]
-  double2* sColBuf = sO + NP * NP;                 // two column buffers
-  double2* sRow = sColBuf + 2 * NP;                // pivot row scaled by 1/pivot
+  double2* Ow = O + w * (size_t)NP * NP;
 #pragma unroll
   for (int p = 0; p < PPW; ++p) {
     const int bp = wv + 4 * p;
     if (bp < NPAIR) {
       const int I = bp / NB, J = bp % NB;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sO[(16 * I + 4 * v + lk) * NP + 16 * J + lr] = make_double2(accR[p][v], accI[p][v]);
+      for (int v = 0; v < 4; ++v) Ow[(16 * I + 4 * v + lk) * NP + 16 * J + lr] = make_double2(accR[p][v], accI[p][v]);
     }
   }
-  __syncthreads();
+}
 
-  // ---------------------------------------------------------------- phase 2
+// ---------------------------------------------------------------------------
+// 2. O_w -> O_w^{-1} in place (padded rows/columns zero), log det, info
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256) void invert_kernel(int n, double2* __restrict__ O,
+                                                     double2* __restrict__ logov, int* __restrict__ info) {
+  constexpr int NP = 16 * NB;
+  __shared__ double2 sColBuf[2][NP];
+  __shared__ double2 sRow[NP];
+  __shared__ int sPiv[NP];
+  __shared__ int sPinv[NP];
+  __shared__ double2 sPivV[NP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15;
+  const size_t w = blockIdx.x;
+  double2* Ow = O + w * (size_t)NP * NP;
+
   const int ty = tid >> 4, tx = tid & 15;   // owns rows ty+16a, cols tx+16b
   double2 e[NB][NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) e[a][b] = sO[(ty + 16 * a) * NP + tx + 16 * b];
-  // publish column 0
+    for (int b = 0; b < NB; ++b) e[a][b] = Ow[(ty + 16 * a) * NP + tx + 16 * b];
   if (tx == 0) {
 #pragma unroll
-    for (int a = 0; a < NB; ++a) sColBuf[ty + 16 * a] = e[a][0];
+    for (int a = 0; a < NB; ++a) sColBuf[0][ty + 16 * a] = e[a][0];
   }
   __syncthreads();
 
-  // pivot bookkeeping, replicated in every lane: lane l tracks rows
-  // (l & 15) + 16 m, m < NB, as bit m of `used`
+  // lane l tracks rows (l & 15) + 16 m, m < NB, as bit m of `used`
   unsigned used = 0u;
 #pragma unroll
   for (int m = 0; m < NB; ++m)
     if ((lr + 16 * m) >= n) used |= 1u << m;
   int zero = 0;
   for (int k = 0; k < n; ++k) {
-    const double2* col = sColBuf + (k & 1) * NP;
+    const double2* col = sColBuf[k & 1];
     // pivot search, identical in every 16-lane row of every wave: key =
     // |re|+|im| (46 leading bits, monotone as an integer) with 63 - row in the
     // low 6 bits; max over the lane's NB rows, then over the 16 lanes (DPP)
@@ -192,7 +182,8 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
     for (int m = 0; m < NB; ++m) {
       const double2 cv = col[lr + 16 * m];
       const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(cv.x) + fabs(cv.y));
-      const unsigned long long km = (used >> m & 1u) ? 0ull : ((mb & ~63ull) | (unsigned long long)(63 - (lr + 16 * m)));
+      const unsigned long long km =
+          (used >> m & 1u) ? 0ull : ((mb & ~63ull) | (unsigned long long)(63 - (lr + 16 * m)));
       key = km > key ? km : key;
     }
     key = row16_max_u64(key);
@@ -254,18 +245,17 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
     }
     // the owners of column k+1 publish it for the next step
     if (k + 1 < n && tx == ((k + 1) & 15)) {
-      double2* ncol = sColBuf + ((k + 1) & 1) * NP;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
         if (b == ((k + 1) >> 4)) {
 #pragma unroll
-          for (int a = 0; a < NB; ++a) ncol[ty + 16 * a] = e[a][b];
+          for (int a = 0; a < NB; ++a) sColBuf[(k + 1) & 1][ty + 16 * a] = e[a][b];
         }
     }
     __syncthreads();
   }
 
-  // un-permute: O^{-1}[k][p_m] = R[p_k][m]
+  // un-permute: O^{-1}[k][p_m] = R[p_k][m]; padded rows/columns stay zero
   if (!zero && tid < n) sPinv[sPiv[tid]] = tid;
   __syncthreads();
   if (!zero) {
@@ -275,13 +265,9 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int m = tx + 16 * b;
-        if (i < n && m < n) sO[sPinv[i] * NP + sPiv[m]] = e[a][b];
+        if (i < n && m < n) Ow[sPinv[i] * NP + sPiv[m]] = e[a][b];
       }
     }
-  }
-  for (int idx = tid; idx < NP * NP; idx += 256) {
-    const int row = idx / NP, col = idx % NP;
-    if (row >= n || col >= n) sO[idx] = make_double2(0.0, 0.0);
   }
   if (wv == 0) {
     // log det O = sum_k log(pivot_k) + i pi (parity of k -> p_k)
@@ -317,41 +303,64 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
       }
     }
   }
-  __syncthreads();
+}
 
-  // ---------------------------------------------------------------- phase 3
-  const int nrb = (M + 15) / 16;
+// ---------------------------------------------------------------------------
+// 3. theta_w = phi_w O_w^{-1}; one 512-thread workgroup per walker, O_w^{-1}
+//    staged once in LDS, wave q takes the 16-row blocks q, q+8, ...
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, const double2* __restrict__ phi,
+                                                    const double2* __restrict__ Oinv, const int* __restrict__ info,
+                                                    double2* __restrict__ theta, int orbital_major) {
+  using C = GtCfg<NB>;
+  constexpr int NP = C::NP;
+  __shared__ double2 sB[NP * NP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // workgroups go round-robin over the 8 XCDs; walkers 8g .. 8g+7 share an
+  // XCD so that their interleaved orbital-major 16-byte stores meet in one L2
+  int64_t w;
+  {
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b & 7, slot = b >> 3;
+    w = 8 * (xcd + 8 * (slot >> 3)) + (slot & 7);
+    if (w >= nw) return;
+  }
+  const double2* Bw = Oinv + w * (size_t)NP * NP;
+  for (int e = tid; e < NP * NP; e += 512) sB[e] = Bw[e];
+  __syncthreads();
   const int ksteps = (n + 3) / 4;
-  double2 fa[C::NKH], fb[C::NKH];
-  auto load_half = [&](int rb, int h, double2* f) {
+  const double2* ph = phi + w * (size_t)M * n;
+  const bool bad = info[w] != 0;
+  const double nan = __builtin_nan("");
+  const int nrb = (M + 15) / 16;
+  for (int rb = wv; rb < nrb; rb += 8) {
     const int r = 16 * rb + lr;
+    d4 P1[NB], P2[NB], P3[NB];
 #pragma unroll
-    for (int q = 0; q < C::NKH; ++q) {
-      const int kk = 4 * (C::NKH * h + q) + lk;
-      f[q] = (rb < nrb && r < M && kk < n) ? ph[(size_t)r * n + kk] : make_double2(0.0, 0.0);
+    for (int J = 0; J < NB; ++J) { P1[J] = d4zero(); P2[J] = d4zero(); P3[J] = d4zero(); }
+    double2 av[C::NKS];
+#pragma unroll
+    for (int ks = 0; ks < C::NKS; ++ks) {
+      const int kk = 4 * ks + lk;
+      av[ks] = (ks < ksteps && r < M && kk < n) ? ph[(size_t)r * n + kk] : make_double2(0.0, 0.0);
     }
-  };
-  d4 P1[NB], P2[NB], P3[NB];
-  auto mult_half = [&](int h, const double2* f) {
 #pragma unroll
-    for (int q = 0; q < C::NKH; ++q) {
-      const int ks = C::NKH * h + q;
+    for (int ks = 0; ks < C::NKS; ++ks) {
       if (ks < ksteps) {
-        const double2 av = f[q];
-        const double as = av.x + av.y;
         const int kk = 4 * ks + lk;
+        const double as = av[ks].x + av[ks].y;
 #pragma unroll
         for (int J = 0; J < NB; ++J) {
-          const double2 bv = sO[kk * NP + 16 * J + lr];
-          P1[J] = mfma16(av.x, bv.x, P1[J]);
-          P2[J] = mfma16(av.y, bv.y, P2[J]);
+          const double2 bv = sB[kk * NP + 16 * J + lr];
+          P1[J] = mfma16(av[ks].x, bv.x, P1[J]);
+          P2[J] = mfma16(av[ks].y, bv.y, P2[J]);
           P3[J] = mfma16(as, bv.x + bv.y, P3[J]);
         }
       }
     }
-  };
-  const double nan = __builtin_nan("");
-  auto store_rows = [&](int rb) {
 #pragma unroll
     for (int J = 0; J < NB; ++J) {
       const int j = 16 * J + lr;
@@ -361,7 +370,7 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
         if (row < M && j < n) {
           const double re = P1[J][v] - P2[J][v];
           const double im = P3[J][v] - P1[J][v] - P2[J][v];
-          const double2 val = zero ? make_double2(nan, nan) : make_double2(re, im);
+          const double2 val = bad ? make_double2(nan, nan) : make_double2(re, im);
           if (orbital_major)
             theta[((size_t)j * M + row) * nw + w] = val;
           else
@@ -369,39 +378,37 @@ __global__ __launch_bounds__(256, 2) void green_theta_kernel(int M, int n, const
         }
       }
     }
-  };
-  if (wv < nrb) load_half(wv, 0, fa);
-  for (int rb = wv; rb < nrb; rb += 4) {
-    load_half(rb, 1, fb);
-#pragma unroll
-    for (int J = 0; J < NB; ++J) { P1[J] = d4zero(); P2[J] = d4zero(); P3[J] = d4zero(); }
-    mult_half(0, fa);
-    load_half(rb + 4, 0, fa);
-    mult_half(1, fb);
-    store_rows(rb);
   }
+}
+
+size_t green_theta_workspace(int n, int64_t nw) {
+  const size_t NP = 16 * (size_t)((n + 15) / 16);
+  return sizeof(double2) * NP * NP * (size_t)nw;
 }
 
 template <int NB>
 static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                            double* theta, double* logov, int* info, int orbital_major) {
-  const size_t lds = GtCfg<NB>::LDS;
-  hipError_t e = hipFuncSetAttribute((const void*)green_theta_kernel<NB>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                            double* theta, double* logov, int* info, int orbital_major, double* work) {
+  double2* O = reinterpret_cast<double2*>(work);
+  hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nw), dim3(256), 0, s, M, n, trial, (const double2*)phi, O);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t grid = orbital_major ? 8 * ((nw + 7) / 8) : nw;
-  hipLaunchKernelGGL(green_theta_kernel<NB>, dim3((unsigned)grid), dim3(256), lds, s, M, n, trial,
-                     (const double2*)phi, (double2*)theta, (double2*)logov, info, orbital_major, nw);
+  hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nw), dim3(256), 0, s, n, O, (double2*)logov, info);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t grid = 64 * ((nw + 63) / 64);
+  hipLaunchKernelGGL(apply_kernel<NB>, dim3((unsigned)grid), dim3(512), 0, s, M, n, nw, (const double2*)phi,
+                     (const double2*)O, info, (double2*)theta, orbital_major);
   return hipGetLastError();
 }
 
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                              double* theta, double* logov, int* info, int orbital_major) {
+                              double* theta, double* logov, int* info, int orbital_major, double* work) {
   if (nw <= 0) return hipSuccess;
-  if (n <= 16) return launch_gt<1>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major);
-  if (n <= 32) return launch_gt<2>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major);
-  if (n <= 48) return launch_gt<3>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major);
-  return launch_gt<4>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major);
+  if (n <= 16) return launch_gt<1>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work);
+  if (n <= 32) return launch_gt<2>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work);
+  if (n <= 48) return launch_gt<3>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work);
+  return launch_gt<4>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work);
 }
 
 }  // namespace lofqmc

@@ -7,8 +7,10 @@
 namespace lofqmc {
 
 // ---- per-walker path
+// work: device workspace of green_theta_workspace(n, nw) bytes (the overlap matrices)
+size_t green_theta_workspace(int n, int64_t nw);
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                              double* theta, double* logov, int* info, int orbital_major);
+                              double* theta, double* logov, int* info, int orbital_major, double* work);
 
 int full_num_chunks(int64_t X, int64_t nw);
 hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* lbar,

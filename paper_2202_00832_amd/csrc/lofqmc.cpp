@@ -475,8 +475,10 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   if (nw == 0) return LO_OK;
   if (!trial || !phi || !theta || !info) return fail(ctx, LO_EINVAL, "null array");
+  int rc = ensure_ws(ctx, align256(lofqmc::green_theta_workspace((int)n_occ, nw)));
+  if (rc) return rc;
   HIP_OR_FAIL(ctx, lofqmc::launch_green_theta(ctx->stream, (int)M, (int)n_occ, nw, trial, phi, theta, log_ovlp,
-                                              info, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0));
+                                              info, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0, (double*)ctx->ws));
   return LO_OK;
 }
 
