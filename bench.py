@@ -39,48 +39,78 @@ def log(msg):
 T0 = time.perf_counter()
 
 
-def green_theta_work(M, n, nw):
-    """Algorithmic FP64 flops and HBM bytes of green_theta for nw walkers."""
-    flops = nw * (4.0 * M * n * n + 8.0 * M * n * n + 8.0 * n ** 3)
-    nbytes = nw * (16.0 * M * n * 2 + 16.0 + 4.0) + 8.0 * M * n
-    return flops, nbytes
+def kernel_work(M, n, nw, X=0, n_out=0, total_rows=0, pair_rows=0):
+    """Algorithmic FP64 work per launch of each kernel of the two routes.
+
+    {kernel: (bound, flops, bytes)}; flops count a real multiply-add as 2 and a
+    complex one as 8 (a real x complex one as 4); bytes count every operand once.
+    """
+    c16, r8 = 16.0, 8.0
+    return {
+        # O = Psi^T phi: real x complex, M n^2 MACs
+        "overlap_kernel": ("mfma", 4.0 * M * n * n * nw, nw * c16 * (M * n + n * n) + r8 * M * n),
+        # Gauss-Jordan inverse: n^3 complex MACs, O in and O^-1 out
+        "invert_kernel": ("alu", 8.0 * n ** 3 * nw, nw * 2 * c16 * n * n),
+        # theta = phi O^-1: M n^2 complex MACs; phi in, theta out, O^-1 in
+        "apply_kernel": ("mfma", 8.0 * M * n * n * nw, nw * c16 * (2 * M * n + n * n)),
+        # each output row: one factor row (real) times Q_o (complex)
+        "lo_pass1_kernel": ("mfma", 4.0 * M * n_out * nw, r8 * total_rows * M + c16 * nw * (M * n + n_out)),
+        # pair dot products: J and X per stored pair, 2 complex MACs per rank
+        "lo_pass2_kernel": ("hbm", 16.0 * pair_rows * nw, c16 * nw * n_out),
+        # T = Lbar^T theta per Cholesky vector + the trace epilogue
+        "energy_full_kernel": ("mfma", nw * X * (4.0 * n * n * M + 8.0 * n * n),
+                               r8 * X * M * n + c16 * nw * M * n),
+        "theta_transpose_kernel": ("hbm", 0.0, 2 * c16 * nw * M * n),
+    }
 
 
-def full_work(M, n, X, nw):
-    flops = nw * X * (4.0 * n * n * M + 8.0 * n * n)
-    nbytes = 8.0 * X * M * n + 16.0 * nw * M * n + 32.0 * nw
-    return flops, nbytes
+def roofline_of(name, work, ms_per_launch):
+    bound, flops, nbytes = work[name]
+    sec = ms_per_launch * 1e-3
+    if bound == "hbm":
+        ach = nbytes / sec / 1e9
+        peak, unit = PEAK_HBM_GBS, "GB/s"
+    else:
+        ach = flops / sec / 1e12
+        peak, unit = PEAK_FP64_TFLOPS, "TFLOP/s"
+    return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit, "frac": round(ach / peak, 4),
+            "kernel": name, "us_per_launch": round(ms_per_launch * 1e3, 2),
+            "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes}
 
 
-def lo_work(M, n, nw, n_out_rows, total_rows, npairs_rows):
-    """Pass 1: each output row is one factor row times Q_o (complex): 4 M flops per walker."""
-    flops = nw * (4.0 * M * n_out_rows + 8.0 * npairs_rows)
-    nbytes = 8.0 * total_rows * M + 16.0 * nw * M * n + 32.0 * nw
-    return flops, nbytes
+def time_route(torch, ctx, step, steps, warmup, marks):
+    """`warmup` untimed steps, `steps` timed steps, then `steps` more with events.
 
-
-def time_route(torch, step, steps, warmup, marks):
-    """Runs `warmup` untimed steps, then `steps` timed steps bracketed by syncs.
-
-    `step(ev)` enqueues one pass and records events into the dict `ev` for the
-    per-call split.  Returns (total ms, {name: [ms per step]}).
+    The first timed region holds nothing but the steps between two events and
+    gives the throughput.  In the second one, `step(ev)` also records the
+    per-call events of the dict `ev`, and the library records an event on its
+    stream before each of its kernels; it gives the per-call split and the
+    per-kernel durations.  Returns (total ms of region 1,
+    {call: [ms per step]}, {kernel: (launches, total ms)}).
     """
     for _ in range(warmup):
         step(None)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    evs = [{m: torch.cuda.Event(enable_timing=True) for m in marks} for _ in range(steps)]
     start.record()
-    for k in range(steps):
-        step(evs[k])
+    for _ in range(steps):
+        step(None)
     stop.record()
     torch.cuda.synchronize()
     total = start.elapsed_time(stop)
+
+    evs = [{m: torch.cuda.Event(enable_timing=True) for m in marks} for _ in range(steps)]
+    ctx.profile_enable(True)
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    kernels = ctx.profile_summary()
+    ctx.profile_enable(False)
     split = {}
     for a, b in zip(marks[:-1], marks[1:]):
         split[a + "->" + b] = [e[a].elapsed_time(e[b]) for e in evs]
-    return total, split
+    return total, split, kernels
 
 
 def cpu_baseline(cfg, system, eps, sample):
@@ -194,18 +224,15 @@ def main():
     eps_h = head["epsilon"]
 
     energy = torch.empty((nw, 2), dtype=torch.complex128, device="cuda")
-    # the LO route keeps theta orbital-major (walkers contiguous), the layout
-    # its per-orbital products read directly
-    theta_om = torch.empty((n, M, nw), dtype=torch.complex128, device="cuda")
 
     def lo_step_for(f):
         def step(ev):
             if ev is not None:
                 ev["a"].record()
-            ctx.green_theta(trial_d, phi_d, theta_om, logov, info, orbital_major=True)
+            ctx.green_theta(trial_d, phi_d, theta, logov, info)
             if ev is not None:
                 ev["b"].record()
-            ctx.local_energy_lo(f, theta_om, info, energy, orbital_major=True)
+            ctx.local_energy_lo(f, theta, info, energy)
             if ev is not None:
                 ev["c"].record()
         return step
@@ -223,7 +250,10 @@ def main():
     marks = ["a", "b", "c"]
     results = {}
     for s in sweep:
-        tot, split = time_route(torch, lo_step_for(factors[s["epsilon"]]), args.steps, args.warmup, marks)
+        tot, split, kern = time_route(torch, ctx, lo_step_for(factors[s["epsilon"]]), args.steps, args.warmup,
+                                      marks)
+        s["_kernels"] = kern
+        s["kernel_us"] = {k: round(t / c * 1e3, 2) for k, (c, t) in kern.items()}
         s["ms_per_step"] = tot / args.steps
         s["walker_energies_per_s"] = nw / (tot / args.steps / 1e3)
         s["green_theta_ms"] = float(np.mean(split["a->b"]))
@@ -232,29 +262,21 @@ def main():
         log("LO eps=%g: %.3f ms/step (green_theta %.3f, LO %.3f)" % (s["epsilon"], s["ms_per_step"],
                                                                      s["green_theta_ms"], s["local_energy_lo_ms"]))
     full_steps = max(1, min(args.steps, 10))
-    tot_f, split_f = time_route(torch, full_step, full_steps, min(args.warmup, 2), marks)
+    tot_f, split_f, kern_f = time_route(torch, ctx, full_step, full_steps, min(args.warmup, 2), marks)
     full_ms = tot_f / full_steps
     full_energy_ms = float(np.mean(split_f["b->c"]))
     log("full: %.3f ms/step (local_energy_full %.3f)" % (full_ms, full_energy_ms))
 
-    # roofline of the dominant kernel of the headline step
-    gt_ms = head["green_theta_ms"]
-    lo_ms = head["local_energy_lo_ms"]
-    gt_flops, gt_bytes = green_theta_work(M, n, nw)
-    lo_flops, lo_bytes = lo_work(M, n, nw, head["_n_out"], head["_total_rows"], head["_n_out"] // 2)
-    if gt_ms >= lo_ms:
-        dom = {"kernel": "green_theta_kernel<4>", "bound": "mfma", "achieved": gt_flops / (gt_ms * 1e-3) / 1e12,
-               "flops_per_launch": gt_flops}
-    else:
-        dom = {"kernel": "local_energy_lo (4 kernels)", "bound": "mfma", "achieved": lo_flops / (lo_ms * 1e-3) / 1e12,
-               "flops_per_launch": lo_flops}
-    roofline = {"bound": dom["bound"], "achieved": round(dom["achieved"], 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(dom["achieved"] / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                "kernel": dom["kernel"], "algorithmic_flops_per_launch": dom["flops_per_launch"]}
-    ff, fb = full_work(M, n, X, nw)
-    full_roof = {"kernel": "energy_full_kernel<4>", "bound": "mfma",
-                 "achieved": round(ff / (full_energy_ms * 1e-3) / 1e12, 3), "peak": PEAK_FP64_TFLOPS,
-                 "unit": "TFLOP/s", "frac": round(ff / (full_energy_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+    # roofline of the dominant kernel of the headline step (largest summed
+    # duration in the timed region), from the library's per-kernel events
+    work = kernel_work(M, n, nw, X, head["_n_out"], head["_total_rows"], head["_n_out"] // 2)
+    kern = head["_kernels"]
+    per_kernel = {k: roofline_of(k, work, t / c) for k, (c, t) in kern.items() if k in work}
+    dom = max(kern, key=lambda k: kern[k][1])
+    roofline = dict(per_kernel[dom])
+    roofline["traffic"] = None
+    full_kernels = {k: roofline_of(k, work, t / c) for k, (c, t) in kern_f.items() if k in work}
+    full_roof = full_kernels["energy_full_kernel"]
 
     log("CPU reference baseline (%d walkers)" % args.cpu_sample)
     cpu = cpu_baseline(cfg, system, eps_h, args.cpu_sample)
@@ -268,10 +290,11 @@ def main():
         "config": {"workload": cfg.name, "M": M, "n_occ": n, "n_chol": X, "walkers": nw, "sigma": cfg.sigma,
                    "cholesky_tol": cfg.chol_tol, "route": "LO", "epsilon": eps_h},
         "full": {"value": round(nw / (full_ms * 1e-3), 1), "unit": "walker-energies/s", "ms_per_step": round(full_ms, 4),
-                 "steps": full_steps, "roofline": full_roof},
+                 "steps": full_steps, "roofline": full_roof, "kernels": full_kernels},
         "lo_vs_full_speedup": round(full_ms / head["ms_per_step"], 2),
         "eps_sweep": [{k: v for k, v in s.items() if not k.startswith("_")} for s in sweep],
         "roofline": roofline,
+        "kernels": per_kernel,
         "cpu_baseline": cpu,
         "setup_s": {"half_rotation": round(t_half, 3)},
     }

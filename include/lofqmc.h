@@ -74,6 +74,26 @@ int lo_destroy(lo_ctx* ctx);
 /* Last error message of this context (never NULL; "" after success). */
 const char* lo_last_error(const lo_ctx* ctx);
 
+/* Kernel timing (diagnostics, not part of the method).  While enabled, every
+ * kernel that the per-walker calls launch is preceded by a HIP event recorded
+ * on the context's stream, and each call ends with one more, so each kernel's
+ * duration is measured on the stream it runs on (a few microseconds of
+ * overhead per launch).  lo_profile_enable(ctx, 0 or 1) discards earlier
+ * records and switches recording off or on.  Records accumulate until
+ * lo_profile_summary, so call it every few thousand launches. */
+int lo_profile_enable(lo_ctx* ctx, int enable);
+
+/* Synchronises the context's stream and reports, per kernel name (sorted by
+ * name), the number of launches and their summed duration in milliseconds
+ * since the last enable or summary; then clears the sums.
+ *   names    : host char[max_kernels][64], NUL-terminated kernel names
+ *   launches : host int64[max_kernels]
+ *   total_ms : host double[max_kernels]
+ *   count    : receives the number of distinct kernels (entries beyond
+ *              max_kernels are not written). */
+int lo_profile_summary(lo_ctx* ctx, int max_kernels, char* names, int64_t* launches, double* total_ms,
+                       int* count);
+
 /* ------------------------------------------------------------- set-up calls */
 
 /* Half-rotated Cholesky vectors (Sec. 2.2, the definition below Eq. 15):

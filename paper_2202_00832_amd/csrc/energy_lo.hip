@@ -16,64 +16,48 @@
 
 namespace lofqmc {
 
-// theta[w][r][j] -> thetaT[j][r][w] (complex); tile of 32 walkers x 32 orbitals.
-__global__ __launch_bounds__(256) void theta_transpose_kernel(int M, int n, int64_t nw,
-                                                              const double2* __restrict__ theta,
-                                                              double2* __restrict__ thetaT) {
-  __shared__ double2 t[32][33];
-  const int j0 = blockIdx.x * 32;
-  const int64_t w0 = (int64_t)blockIdx.y * 32;
-  const int r = blockIdx.z;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  for (int yy = ty; yy < 32; yy += 8) {
-    const int64_t w = w0 + yy;
-    const int j = j0 + tx;
-    t[yy][tx] = (w < nw && j < n) ? theta[((size_t)w * M + r) * n + j] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int yy = ty; yy < 32; yy += 8) {
-    const int j = j0 + yy;
-    const int64_t w = w0 + tx;
-    if (w < nw && j < n) thetaT[((size_t)j * M + r) * nw + w] = t[tx][yy];
-  }
-}
-
-hipError_t launch_theta_transpose(hipStream_t s, int M, int n, int64_t nw, const double* theta, double* thetaT) {
-  if (nw <= 0) return hipSuccess;
-  dim3 grid((n + 31) / 32, (unsigned)((nw + 31) / 32), M);
-  hipLaunchKernelGGL(theta_transpose_kernel, grid, dim3(256), 0, s, M, n, nw, (const double2*)theta,
-                     (double2*)thetaT);
-  return hipGetLastError();
-}
-
 // Pass 1: tile = up to LO_TILE_ROWS output rows of one orbital o x 32
 // walkers.  Per 16-row slab of r the factor rows (gathered through rowidx)
 // and Q_o of the 32 walkers are staged in LDS (double-buffered).  Wave q
 // owns the 16-row blocks q, q+4, q+8 of the tile against all four column
 // blocks (two 16-walker halves, real and imaginary part), so every factor
 // fragment is read from LDS once and feeds four MFMAs.
+//
+// theta element (o, r, w) is read at theta[o * so + r * sr + w * sw], which
+// serves both layouts: walker-major [w][r][o] and orbital-major [o][r][w].
+// Work units (block of LO_OBLK orbitals, walker tile) go round-robin over the
+// 8 XCDs (workgroups are dispatched round-robin over XCDs) and the tiles of
+// one unit run side by side on one XCD: with walker-major theta the orbitals
+// of a block share cache lines, which that XCD's L2 then fetches once.
 constexpr int LO_TILE_ROWS = 192;
 constexpr int LO_RB = LO_TILE_ROWS / 16;     // 12 row blocks per tile
 constexpr int LO_RBW = LO_RB / 4;            // 3 per wave
 constexpr int LO_WT = 32;
+constexpr int LO_OBLK = 8;
 
 __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
                                                           const int* __restrict__ rowidx,
                                                           const int* __restrict__ tile_orb,
                                                           const int* __restrict__ tile_row0,
                                                           const int* __restrict__ tile_nrows,
-                                                          const double2* __restrict__ thetaT,
-                                                          double2* __restrict__ qbar, int ntiles, int nwt) {
+                                                          const int* __restrict__ blk, int nblk, int tmax,
+                                                          const double2* __restrict__ theta, int64_t so,
+                                                          int64_t sr, int64_t sw, double2* __restrict__ qbar,
+                                                          int nwt) {
   __shared__ double sA[2][LO_TILE_ROWS][17];   // [row][r], padded against bank conflicts
   __shared__ double2 sB[2][16][LO_WT];         // [r][walker]
-  // XCD-aware order: workgroups go round-robin over the 8 XCDs; every walker
-  // tile of row tile t runs on XCD t % 8, so its factor rows are read into
-  // one L2 once and reused by all walker tiles.
-  const int xcd = blockIdx.x & 7;
-  const int slot = blockIdx.x >> 3;
-  const int t = xcd + 8 * (slot / nwt);
-  if (t >= ntiles) return;
-  const int64_t w0 = (int64_t)(slot % nwt) * LO_WT;
+  int t;
+  int64_t w0;
+  {
+    const int xcd = blockIdx.x & 7;
+    const int slot = blockIdx.x >> 3;
+    const int64_t u = 8 * (int64_t)(slot / tmax) + xcd;
+    if (u >= (int64_t)nblk * nwt) return;
+    const int b = (int)(u / nwt);
+    t = blk[b] + slot % tmax;
+    if (t >= blk[b + 1]) return;
+    w0 = (u % nwt) * LO_WT;
+  }
   const int o = tile_orb[t];
   const int row0 = tile_row0[t];
   const int nrows = tile_nrows[t];
@@ -81,7 +65,7 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const double2* tho = thetaT + (size_t)o * M * nw;
+  const double2* tho = theta + o * so;
 
   // staging: A = nrows x 16 doubles (each row 128 contiguous bytes), B = 16 x 32 complex
   constexpr int A_PER = (LO_TILE_ROWS * 16 + 255) / 256;   // 12
@@ -109,7 +93,7 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
       const int rr = e / LO_WT, ww = e % LO_WT;
       const int r = rbase + rr;
       const int64_t w = w0 + ww;
-      pb[q] = (r < M && w < nw) ? tho[(size_t)r * nw + w] : make_double2(0.0, 0.0);
+      pb[q] = (r < M && w < nw) ? tho[r * sr + w * sw] : make_double2(0.0, 0.0);
     }
   };
   auto store = [&](int buf) {
@@ -179,18 +163,23 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
 }
 
 int lo_tile_rows() { return LO_TILE_ROWS; }
+int lo_orbital_block() { return LO_OBLK; }
 
-hipError_t launch_lo_pass1(hipStream_t s, int M, int64_t nw, int ntiles, const double* rows, const int* rowidx,
-                           const int* tile_orb, const int* tile_row0, const int* tile_nrows, const double* thetaT,
-                           double* qbar) {
+hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
+                           const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
+                           const double* theta, int orbital_major, double* qbar) {
   if (nw <= 0 || ntiles <= 0) return hipSuccess;
   const int nwt = (int)((nw + LO_WT - 1) / LO_WT);
-  const int64_t grid = (int64_t)8 * ((ntiles + 7) / 8) * nwt;
-  hipLaunchKernelGGL(lo_pass1_kernel, dim3((unsigned)grid), dim3(256), 0, s, M, nw, rows, rowidx, tile_orb, tile_row0,
-                     tile_nrows, (const double2*)thetaT, (double2*)qbar, ntiles, nwt);
+  const int64_t units = (int64_t)nblk * nwt;
+  const int64_t grid = (int64_t)8 * ((units + 7) / 8) * tmax;
+  const int64_t so = orbital_major ? (int64_t)M * nw : 1;
+  const int64_t sr = orbital_major ? nw : n;
+  const int64_t sw = orbital_major ? 1 : (int64_t)M * n;
+  hipLaunchKernelGGL(lo_pass1_kernel, dim3((unsigned)grid), dim3(256), 0, s, M, nw, rows, rowidx, tiles,
+                     tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax, (const double2*)theta, so, sr, sw,
+                     (double2*)qbar, nwt);
   return hipGetLastError();
 }
-
 // Pass 2: one thread per walker, a contiguous chunk of pairs per grid row.
 __global__ __launch_bounds__(64) void lo_pass2_kernel(int64_t nw, int npairs, int per_chunk,
                                                       const int* __restrict__ pK, const int64_t* __restrict__ offI,

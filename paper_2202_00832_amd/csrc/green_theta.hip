@@ -388,27 +388,32 @@ size_t green_theta_workspace(int n, int64_t nw) {
 
 template <int NB>
 static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                            double* theta, double* logov, int* info, int orbital_major, double* work) {
+                            double* theta, double* logov, int* info, int orbital_major, double* work,
+                            const ProfHook* prof) {
   double2* O = reinterpret_cast<double2*>(work);
+  prof_mark(prof, "overlap_kernel");
   hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nw), dim3(256), 0, s, M, n, trial, (const double2*)phi, O);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  prof_mark(prof, "invert_kernel");
   hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nw), dim3(256), 0, s, n, O, (double2*)logov, info);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t grid = 64 * ((nw + 63) / 64);
+  prof_mark(prof, "apply_kernel");
   hipLaunchKernelGGL(apply_kernel<NB>, dim3((unsigned)grid), dim3(512), 0, s, M, n, nw, (const double2*)phi,
                      (const double2*)O, info, (double2*)theta, orbital_major);
   return hipGetLastError();
 }
 
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                              double* theta, double* logov, int* info, int orbital_major, double* work) {
+                              double* theta, double* logov, int* info, int orbital_major, double* work,
+                              const ProfHook* prof) {
   if (nw <= 0) return hipSuccess;
-  if (n <= 16) return launch_gt<1>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work);
-  if (n <= 32) return launch_gt<2>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work);
-  if (n <= 48) return launch_gt<3>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work);
-  return launch_gt<4>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work);
+  if (n <= 16) return launch_gt<1>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 32) return launch_gt<2>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 48) return launch_gt<3>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
+  return launch_gt<4>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
 }
 
 }  // namespace lofqmc

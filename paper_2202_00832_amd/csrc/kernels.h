@@ -6,11 +6,23 @@
 
 namespace lofqmc {
 
+// Optional per-kernel timing: when set, mark(ctx, name) is called on the host
+// right before each kernel launch named `name` (it records a HIP event on the
+// launch stream); mark(ctx, nullptr) closes the last interval.
+struct ProfHook {
+  void* ctx;
+  void (*mark)(void* ctx, const char* name);
+};
+inline void prof_mark(const ProfHook* h, const char* name) {
+  if (h && h->mark) h->mark(h->ctx, name);
+}
+
 // ---- per-walker path
 // work: device workspace of green_theta_workspace(n, nw) bytes (the overlap matrices)
 size_t green_theta_workspace(int n, int64_t nw);
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                              double* theta, double* logov, int* info, int orbital_major, double* work);
+                              double* theta, double* logov, int* info, int orbital_major, double* work,
+                              const ProfHook* prof);
 
 int full_num_chunks(int64_t X, int64_t nw);
 hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* lbar,
@@ -18,12 +30,15 @@ hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw
 hipError_t launch_reduce_partials(hipStream_t s, int64_t nw, int nchunk, const double* partial, const int* info,
                                   double* energy);
 
-hipError_t launch_theta_transpose(hipStream_t s, int M, int n, int64_t nw, const double* theta, double* thetaT);
-hipError_t launch_lo_pass1(hipStream_t s, int M, int64_t nw, int ntiles, const double* rows, const int* rowidx,
-                           const int* tile_orb, const int* tile_row0, const int* tile_nrows, const double* thetaT,
-                           double* qbar);
-int lo_pass2_chunks(int npairs);
+// tiles: device int [3][ntiles] (orbital, first output row, row count), tiles
+// sorted by orbital; blk: device int [nblk + 1], first tile of each block of
+// lo_orbital_block() orbitals; tmax: most tiles in one block.
+hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
+                           const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
+                           const double* theta, int orbital_major, double* qbar);
 int lo_tile_rows();
+int lo_orbital_block();
+int lo_pass2_chunks(int npairs);
 hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int npairs, int nchunk, const int* pK, const int64_t* offI,
                            const int64_t* offJ, const double* pw, const double* qbar, double* partial);
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,11 @@ struct lo_ctx {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   rocblas_handle blas = nullptr;
+  // kernel timing (lo_profile_*): events recorded before each launch, in order
+  bool prof_on = false;
+  std::vector<std::pair<const char*, hipEvent_t>> prof_marks;
+  std::vector<hipEvent_t> prof_pool;
+  std::map<std::string, std::pair<int64_t, double>> prof_acc;   // name -> (launches, ms)
 };
 
 struct lo_factors {
@@ -32,9 +38,10 @@ struct lo_factors {
   std::vector<int32_t> ranks;          // [n][n]
   std::vector<double> first_dropped;   // [n][n]
   std::vector<int64_t> row_offset;     // [n][n], -1 for i > j
-  int ntiles = 0, npairs = 0;
+  int ntiles = 0, npairs = 0, nblk = 0, tmax = 0;
   int* d_rowidx = nullptr;             // [n_out_rows]
-  int* d_tiles = nullptr;              // [3][ntiles]: orbital, first output row, row count
+  int* d_tiles = nullptr;              // [3][ntiles]: orbital, first output row, row count;
+                                       // then [nblk + 1]: first tile of each orbital block
   int* d_pK = nullptr;                 // [npairs]
   int64_t* d_off = nullptr;            // [2][npairs]: output rows of the pair for orbital i and j
   double* d_pw = nullptr;              // [npairs]
@@ -109,6 +116,54 @@ void free_factors(lo_factors* f) {
   delete f;
 }
 
+// Records an event on the context stream that opens the interval of kernel
+// `name` (nullptr closes the previous one).  Timing failures are not errors
+// of the computation: a mark that cannot be recorded is dropped.
+void prof_record(void* vctx, const char* name) {
+  lo_ctx* c = (lo_ctx*)vctx;
+  if (!c->prof_on) return;
+  hipEvent_t ev = nullptr;
+  if (!c->prof_pool.empty()) {
+    ev = c->prof_pool.back();
+    c->prof_pool.pop_back();
+  } else if (hipEventCreate(&ev) != hipSuccess) {
+    return;
+  }
+  if (hipEventRecord(ev, c->stream) != hipSuccess) {
+    c->prof_pool.push_back(ev);
+    return;
+  }
+  c->prof_marks.emplace_back(name, ev);
+}
+
+// Turns the recorded marks into per-kernel sums (synchronises the stream).
+int prof_collect(lo_ctx* c) {
+  if (c->prof_marks.empty()) return LO_OK;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i + 1 < c->prof_marks.size(); ++i) {
+    const char* name = c->prof_marks[i].first;
+    if (!name) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->prof_marks[i].second, c->prof_marks[i + 1].second) != hipSuccess) continue;
+    auto& a = c->prof_acc[name];
+    a.first += 1;
+    a.second += ms;
+  }
+  for (auto& m : c->prof_marks) c->prof_pool.push_back(m.second);
+  c->prof_marks.clear();
+  return LO_OK;
+}
+
+// RAII: closes the last kernel interval of a call on every return path.
+struct ProfScope {
+  lo_ctx* c;
+  lofqmc::ProfHook hook;
+  explicit ProfScope(lo_ctx* ctx) : c(ctx), hook{ctx, ctx->prof_on ? prof_record : nullptr} {}
+  const lofqmc::ProfHook* get() const { return &hook; }
+  void mark(const char* name) const { lofqmc::prof_mark(&hook, name); }
+  ~ProfScope() { mark(nullptr); }
+};
+
 }  // namespace
 
 extern "C" {
@@ -138,16 +193,50 @@ int lo_synchronize(lo_ctx* ctx) {
 
 int lo_destroy(lo_ctx* ctx) {
   if (!ctx) return LO_OK;
-  if (ctx->ws) {
-    (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(ctx->ws);
-  }
+  if (ctx->ws || !ctx->prof_marks.empty()) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  for (auto& m : ctx->prof_marks) (void)hipEventDestroy(m.second);
+  for (auto ev : ctx->prof_pool) (void)hipEventDestroy(ev);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   delete ctx;
   return LO_OK;
 }
 
 const char* lo_last_error(const lo_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int lo_profile_enable(lo_ctx* ctx, int enable) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!ctx->prof_marks.empty()) {
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto& m : ctx->prof_marks) ctx->prof_pool.push_back(m.second);
+    ctx->prof_marks.clear();
+  }
+  ctx->prof_acc.clear();
+  ctx->prof_on = enable != 0;
+  return LO_OK;
+}
+
+int lo_profile_summary(lo_ctx* ctx, int max_kernels, char* names, int64_t* launches, double* total_ms,
+                       int* count) {
+  if (!ctx || max_kernels < 0 || !count || (max_kernels > 0 && (!names || !launches || !total_ms)))
+    return ctx ? fail(ctx, LO_EINVAL, "bad summary arguments") : LO_EINVAL;
+  ctx->err.clear();
+  int rc = prof_collect(ctx);
+  if (rc) return rc;
+  int k = 0;
+  for (const auto& kv : ctx->prof_acc) {
+    if (k < max_kernels) {
+      std::snprintf(names + 64 * k, 64, "%s", kv.first.c_str());
+      launches[k] = kv.second.first;
+      total_ms[k] = kv.second.second;
+    }
+    ++k;
+  }
+  *count = k;
+  ctx->prof_acc.clear();
+  return LO_OK;
+}
 
 // ------------------------------------------------------------------ set-up
 
@@ -404,6 +493,20 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
   tiles.insert(tiles.end(), t_orb.begin(), t_orb.end());
   tiles.insert(tiles.end(), t_row0.begin(), t_row0.end());
   tiles.insert(tiles.end(), t_nrows.begin(), t_nrows.end());
+  // orbital blocks of pass 1: first tile of each block (tiles are sorted by orbital)
+  const int ob = lofqmc::lo_orbital_block();
+  f->nblk = (int)((n + ob - 1) / ob);
+  {
+    std::vector<int> blk(f->nblk + 1, f->ntiles);
+    int t = 0;
+    for (int b = 0; b < f->nblk; ++b) {
+      while (t < f->ntiles && t_orb[t] < b * ob) ++t;
+      blk[b] = t;
+    }
+    f->tmax = 0;
+    for (int b = 0; b < f->nblk; ++b) f->tmax = std::max(f->tmax, blk[b + 1] - blk[b]);
+    tiles.insert(tiles.end(), blk.begin(), blk.end());
+  }
   std::vector<int> pK;
   std::vector<int64_t> off;
   std::vector<double> pw;
@@ -477,8 +580,10 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   if (!trial || !phi || !theta || !info) return fail(ctx, LO_EINVAL, "null array");
   int rc = ensure_ws(ctx, align256(lofqmc::green_theta_workspace((int)n_occ, nw)));
   if (rc) return rc;
+  ProfScope prof(ctx);
   HIP_OR_FAIL(ctx, lofqmc::launch_green_theta(ctx->stream, (int)M, (int)n_occ, nw, trial, phi, theta, log_ovlp,
-                                              info, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0, (double*)ctx->ws));
+                                              info, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0, (double*)ctx->ws,
+                                              prof.get()));
   return LO_OK;
 }
 
@@ -501,10 +606,13 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
   int rc = ensure_ws(ctx, pbytes);
   if (rc) return rc;
   double* partial = (double*)ctx->ws;
+  ProfScope prof(ctx);
   if (n_chol > 0) {
+    prof.mark("energy_full_kernel");
     HIP_OR_FAIL(ctx, lofqmc::launch_energy_full(ctx->stream, (int)M, (int)n_occ, n_chol, nw, lbar, theta, partial,
                                                 nchunk));
   }
+  prof.mark("reduce_partials_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nchunk, partial, info, energy));
   return LO_OK;
 }
@@ -523,23 +631,22 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
   const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
   const int64_t M = f->M, n = f->n;
   const int nchunk = lofqmc::lo_pass2_chunks(f->npairs);
-  const size_t tbytes = orbital_major ? 0 : align256(sizeof(double) * 2 * (size_t)n * M * nw);
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
   const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
-  int rc = ensure_ws(ctx, tbytes + qbytes + pbytes);
+  int rc = ensure_ws(ctx, qbytes + pbytes);
   if (rc) return rc;
   char* base = (char*)ctx->ws;
-  const double* thetaT = theta;
-  double* qbar = (double*)(base + tbytes);
-  double* partial = (double*)(base + tbytes + qbytes);
-  if (!orbital_major) {
-    thetaT = (double*)base;
-    HIP_OR_FAIL(ctx, lofqmc::launch_theta_transpose(ctx->stream, (int)M, (int)n, nw, theta, (double*)base));
-  }
-  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, nw, f->ntiles, f->rows, f->d_rowidx, f->d_tiles,
-                                           f->d_tiles + f->ntiles, f->d_tiles + 2 * f->ntiles, thetaT, qbar));
+  double* qbar = (double*)base;
+  double* partial = (double*)(base + qbytes);
+  ProfScope prof(ctx);
+  prof.mark("lo_pass1_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
+                                           f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
+                                           orbital_major ? 1 : 0, qbar));
+  prof.mark("lo_pass2_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->npairs, nchunk, f->d_pK, f->d_off,
                                            f->d_off + f->npairs, f->d_pw, qbar, partial));
+  prof.mark("reduce_partials_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nchunk, partial, info, energy));
   return LO_OK;
 }

@@ -30,6 +30,8 @@ _SIGS = {
     "lo_synchronize": (ctypes.c_int, [_c_p]),
     "lo_destroy": (ctypes.c_int, [_c_p]),
     "lo_last_error": (ctypes.c_char_p, [_c_p]),
+    "lo_profile_enable": (ctypes.c_int, [_c_p, ctypes.c_int]),
+    "lo_profile_summary": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, ctypes.POINTER(ctypes.c_int)]),
     "build_half_rotated_chol": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p]),
     "build_lo_factors": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, ctypes.c_double, ctypes.POINTER(_c_p)]),
     "lo_factors_destroy": (ctypes.c_int, [_c_p]),
@@ -187,6 +189,24 @@ class Context:
 
     def synchronize(self):
         self._check(self._lib.lo_synchronize(self._h))
+
+    # -- kernel timing (diagnostics) --------------------------------------------
+    def profile_enable(self, enable: bool = True):
+        self._check(self._lib.lo_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_summary(self, max_kernels: int = 32) -> dict:
+        """{kernel name: (launches, total ms)} since the last enable/summary."""
+        names = ctypes.create_string_buffer(64 * max_kernels)
+        launches = np.zeros(max_kernels, dtype=np.int64)
+        total = np.zeros(max_kernels, dtype=np.float64)
+        count = ctypes.c_int(0)
+        self._check(self._lib.lo_profile_summary(self._h, max_kernels, ctypes.addressof(names),
+                                                 launches.ctypes.data, total.ctypes.data, ctypes.byref(count)))
+        out = {}
+        for k in range(min(count.value, max_kernels)):
+            name = names.raw[64 * k:64 * (k + 1)].split(b"\0", 1)[0].decode()
+            out[name] = (int(launches[k]), float(total[k]))
+        return out
 
     # -- set-up ---------------------------------------------------------------
     def build_half_rotated_chol(self, chol, trial, lbar=None):
