@@ -113,6 +113,42 @@ def time_route(torch, ctx, step, steps, warmup, marks):
     return total, split, kernels
 
 
+def precision_study(torch, lofqmc, synth, steps):
+    """Full route with the exchange contraction in FP64, FP32 and split BF16 on
+    the 500-site chain (48 orbitals, 1024 walkers): time per step and error of
+    each walker's energy against the FP64 result of the same inputs."""
+    cfg = synth.CHAIN_PRECISION
+    log("precision study: generating %s" % cfg.name)
+    system = synth.make_system(cfg)
+    M, n, nw, X = cfg.M, cfg.n, cfg.nw, system.n_chol
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    ctx = lofqmc.Context()
+    chol_d = dev(system.chol)
+    trial_d, phi_d = dev(system.trial), dev(system.walkers)
+    lbar = ctx.build_half_rotated_chol(chol_d, trial_d)
+    del chol_d
+    theta, logov, info = ctx.green_theta(trial_d, phi_d)
+    energy = torch.empty((nw, 2), dtype=torch.complex128, device="cuda")
+    ref = ctx.local_energy_full(lbar, theta, info, precision=lofqmc.LO_FP64).cpu().numpy()
+    out = {"workload": cfg.name, "M": M, "n_occ": n, "n_chol": X, "walkers": nw, "runs": {}}
+    names = {lofqmc.LO_FP64: "fp64", lofqmc.LO_FP32: "fp32", lofqmc.LO_BF16X3: "bf16x3"}
+    for p in (lofqmc.LO_FP64, lofqmc.LO_FP32, lofqmc.LO_BF16X3):
+        def step(ev, p=p):
+            ctx.local_energy_full(lbar, theta, info, energy, precision=p)
+        tot, _, kern = time_route(torch, ctx, step, steps, 1, ["a"])
+        e = ctx.local_energy_full(lbar, theta, info, precision=p).cpu().numpy()
+        d = np.abs(e.sum(axis=1) - ref.sum(axis=1))
+        dk = np.abs(e[:, 1] - ref[:, 1])
+        r = {"ms_per_call": round(tot / steps, 3), "walker_energies_per_s": round(nw / (tot / steps * 1e-3), 1),
+             "max_abs_dE_Ha": float(d.max()), "mean_abs_dE_Ha": float(d.mean()),
+             "max_abs_dEK_Ha": float(dk.max()),
+             "kernel_us": {k: round(t / c * 1e3, 1) for k, (c, t) in kern.items()}}
+        out["runs"][names[p]] = r
+        log("precision %s: %.3f ms/call, max |dE| %.2e Ha" % (names[p], r["ms_per_call"], r["max_abs_dE_Ha"]))
+    ctx.close()
+    return out
+
+
 def cpu_baseline(cfg, system, eps, sample):
     """The CPU reference (numpy FP64) on a fixed sample of walkers: LO route."""
     from oracle import energy as E
@@ -144,6 +180,8 @@ def main():
                     help="walkers timed on the CPU reference (about 10 s of host work at the default)")
     ap.add_argument("--eps", type=str, default="",
                     help="comma-separated LO thresholds to run instead of the workload's sweep")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the reduced-precision full-route study on the 500-site chain")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -278,6 +316,10 @@ def main():
     full_kernels = {k: roofline_of(k, work, t / c) for k, (c, t) in kern_f.items() if k in work}
     full_roof = full_kernels["energy_full_kernel"]
 
+    prec = None
+    if not args.no_precision:
+        prec = precision_study(torch, lofqmc, synth, max(2, min(args.steps, 5)))
+
     log("CPU reference baseline (%d walkers)" % args.cpu_sample)
     cpu = cpu_baseline(cfg, system, eps_h, args.cpu_sample)
     log("cpu: %.2f walker-energies/s" % cpu["value"])
@@ -295,6 +337,7 @@ def main():
         "eps_sweep": [{k: v for k, v in s.items() if not k.startswith("_")} for s in sweep],
         "roofline": roofline,
         "kernels": per_kernel,
+        "mixed_precision": prec,
         "cpu_baseline": cpu,
         "setup_s": {"half_rotation": round(t_half, 3)},
     }

@@ -49,10 +49,18 @@ enum lo_flags {
   LO_THETA_ORBITAL_MAJOR = 1u
 };
 
+/* Arithmetic of the energy contractions.  Reduced precision applies to the
+ * exchange contraction T = Lbar_g^T theta of local_energy_full (the Coulomb
+ * traces, the exchange sums and every sum over g stay FP64) and to the
+ * projections QL = Ubar^T Q, QR = Vbar Q of local_energy_lo (the pair dot
+ * products and all sums stay FP64).  green_theta is always FP64. */
 enum lo_precision {
-  LO_FP64 = 0,   /* FP64 contractions and FP64 sums */
-  LO_FP32 = 1,   /* reserved: FP32 contractions, FP64 sums */
-  LO_BF16X3 = 2  /* reserved: split-BF16 contractions, FP64 sums */
+  LO_FP64 = 0,   /* FP64 everywhere */
+  LO_FP32 = 1,   /* T from FP32-rounded operands on FP32 MFMA (FP32 accumulation) */
+  LO_BF16X3 = 2, /* T from split BF16 operands x = x_hi + x_lo, products
+                    hi*hi + hi*lo + lo*hi on BF16 MFMA (FP32 accumulation) */
+  LO_BF16 = 3    /* plain BF16 operands, FP32 accumulation: only for
+                    lo_residual_predict */
 };
 
 /* ---------------------------------------------------------------- context */
@@ -157,7 +165,7 @@ int lo_factors_export(const lo_factors* f, double* rows, int64_t* row_offset);
  *   info     : int32 [nw] (output): 0, or k > 0 if the k-th pivot (1-based)
  *              of O_w is exactly zero; theta_w is then undefined and the
  *              energy calls return NaN for that walker.
- * Always FP64.  Supports n_occ <= 64. */
+ * Always FP64.  Supports n_occ <= 96. */
 int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double* trial,
                 const double* phi, double* theta, double* log_ovlp, int32_t* info, unsigned flags);
 
@@ -165,11 +173,15 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
  *   T_{wg} = Lbar_g^T theta_w (n_occ x n_occ, complex)
  *   E_J[w] = 2 sum_g (Tr T_{wg})^2,   E_K[w] = -sum_g Tr(T_{wg} T_{wg}).
  * The per-(w, g) matrix T is never written to memory.
- *   lbar   : [n_chol][M][n_occ] double
- *   theta  : complex [nw][M][n_occ] (walker-major)
- *   info   : int32 [nw] from green_theta, or NULL (all valid)
- *   energy : complex [nw][2] (output) = (E_J, E_K) per walker
- * precision must be LO_FP64; flags must be 0.  Supports n_occ <= 64. */
+ *   lbar      : [n_chol][M][n_occ] double
+ *   theta     : complex [nw][M][n_occ] (walker-major)
+ *   info      : int32 [nw] from green_theta, or NULL (all valid)
+ *   precision : LO_FP64, LO_FP32 or LO_BF16X3 (enum lo_precision); the
+ *               reduced ones first rewrite lbar and theta into a padded
+ *               FP32 or split-BF16 copy in the context workspace and support
+ *               nw <= 65535 and n_chol <= 65535
+ *   energy    : complex [nw][2] (output) = (E_J, E_K) per walker
+ * flags must be 0.  Supports n_occ <= 64 (LO_FP64, LO_BF16X3) or <= 96 (LO_FP32). */
 int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int64_t nw,
                       const double* lbar, const double* theta, const int32_t* info,
                       int precision, unsigned flags, double* energy);
@@ -180,13 +192,98 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
  *   E_J = 2 sum_ij QL_i . QR_j,   E_K = -sum_ij QL_j . QR_i.
  *   factors : handle from build_lo_factors (shapes M, n_occ taken from it)
  *   theta   : complex [nw][M][n_occ], or [n_occ][M][nw] with flags
- *             LO_THETA_ORBITAL_MAJOR (the walker-major layout is transposed
- *             into the context workspace first)
+ *             LO_THETA_ORBITAL_MAJOR (both are read in place)
  *   info    : int32 [nw] or NULL
  *   energy  : complex [nw][2] (output) = (E_J, E_K)
- * precision must be LO_FP64; flags may hold LO_THETA_ORBITAL_MAJOR only. */
+ * precision: LO_FP64, LO_FP32 or LO_BF16X3 (enum lo_precision); the reduced
+ * ones need walker-major theta (LO_EUNSUPPORTED otherwise), nw <= 65535 and
+ * n_occ <= 96 (LO_FP32) or <= 64 (LO_BF16X3),
+ * and rewrite theta into a padded FP32 or split-BF16 copy in the context
+ * workspace first.  flags may hold LO_THETA_ORBITAL_MAJOR only. */
 int local_energy_lo(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const double* theta,
                     const int32_t* info, int precision, unsigned flags, double* energy);
+
+/* --------------------------------------------------- several systems at once
+ *
+ * Full-route energies (Eq. 16) of several systems of different size in one
+ * pass, FP32 exchange contraction with FP64 Coulomb sums and FP64 reductions
+ * (the LO_FP32 arithmetic of local_energy_full).  The exchange work of all
+ * systems forms one list of items (4 walkers x a chunk of Cholesky vectors of
+ * one system) that ONE persistent kernel launch works through; per system
+ * there are the operand rewrite, the Coulomb sums and the reduction. */
+typedef struct lo_system {
+  int64_t M, n_occ, n_chol, nw;
+  const double* lbar;    /* device [n_chol][M][n_occ] */
+  const double* theta;   /* device complex [nw][M][n_occ] (walker-major) */
+  const int32_t* info;   /* device int32 [nw] or NULL */
+  double* energy;        /* device complex [nw][2] (output) = (E_J, E_K) */
+} lo_system;
+
+typedef struct lo_batch lo_batch;
+
+/* Plans an evaluation of nsys systems (host array; the device arrays it
+ * points to must stay valid while the plan is used; their contents may
+ * change between evaluations).  chunk: optional host int64 [nsys], the
+ * Cholesky vectors per work item of each system (the tile shape; <= 0 or a
+ * NULL array picks a size that makes items of all systems cost about the
+ * same).  precision must be LO_FP32; each system needs n_occ <= 96,
+ * nw <= 65535, n_chol <= 65535.  Allocates every device buffer the
+ * evaluations need, so lo_batch_execute allocates nothing. */
+int lo_batch_create(lo_ctx* ctx, int nsys, const lo_system* sys, int precision, const int64_t* chunk,
+                    lo_batch** out);
+int lo_batch_destroy(lo_batch* b);
+
+/* Work items and the chosen chunk per system (host int64 [nsys], may be NULL). */
+int lo_batch_info(const lo_batch* b, int64_t* nitems, int64_t* chunk);
+
+/* Enqueues one evaluation of every system on the context stream. */
+int lo_batch_execute(lo_ctx* ctx, lo_batch* b);
+
+/* Records `repeats` consecutive evaluations into a HIP graph (captured on a
+ * stream of the plan) and instantiates it; lo_batch_replay launches it on
+ * the context stream.  Capturing again replaces the graph. */
+int lo_batch_capture(lo_ctx* ctx, lo_batch* b, int repeats);
+int lo_batch_replay(lo_ctx* ctx, lo_batch* b);
+
+/* ------------------------------------------------ learned residual (extension)
+ *
+ * Not part of the paper's method: a small network that predicts, per walker,
+ * the energy that the LO truncation drops, Re(E_full - E_LO) ~ sum_i f(x_i),
+ * from per-orbital features of occupied orbital i of a walker:
+ *   x_i = (sum_j K_ij, sum_j m_ij, ||theta[:, i]||_2)
+ * with K_ij the retained rank and m_ij the sum of the discarded singular
+ * values of pair block Y^[ij] (Sec. 2.3.1).  f is 3 -> 128 -> 128 -> 1 with
+ * tanh activations on standardised inputs z = (x - shift) * scale; the
+ * parameters are one device float vector of lo_residual_nparam() entries:
+ *   W1[128][3], b1[128], W2[128][128], b2[128], w3[128], b3, shift[3], scale[3]
+ * (shift and scale are set by the caller and never trained).  All arrays are
+ * device pointers; every call is asynchronous on the context stream. */
+int lo_residual_nparam(void);
+
+/* Sum of the discarded singular values of every pair block, host double
+ * [n_occ][n_occ] (symmetric). */
+int lo_factors_discarded(const lo_factors* f, double* mass);
+
+/* x : float [nw][n_occ][3] (output), theta : complex [nw][M][n_occ]. */
+int lo_residual_features(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, float* x);
+
+/* pred[w] = sum_i f(x_wi) (double [nw], output).  precision LO_FP32 (FP32
+ * throughout) or LO_BF16 (the 128 x 128 layer on BF16 MFMA from BF16-rounded
+ * activations and weights, FP32 accumulation; the other layers FP32). */
+int lo_residual_predict(lo_ctx* ctx, int64_t nw, int64_t n_occ, const float* params, const float* x,
+                        int precision, double* pred);
+
+/* One training step on the loss L = mean_w (sum_i f(x_wi) - target_w)^2:
+ * FP32 forward and hand-written backward pass, gradients summed over rows in
+ * a fixed order, then (step >= 1) one Adam update (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias correction with this step number) of params, adam_m,
+ * adam_v (float [nparam] each, zero before the first step).  step == 0 only
+ * evaluates.  grad (float [nparam]), loss (double [1]) and pred (double [nw])
+ * are optional outputs (NULL to skip); grad and loss belong to the parameters
+ * before the update. */
+int lo_residual_train_step(lo_ctx* ctx, int64_t nw, int64_t n_occ, float* params, float* adam_m, float* adam_v,
+                           int64_t step, double lr, const float* x, const double* target, float* grad, double* loss,
+                           double* pred);
 
 #ifdef __cplusplus
 }

@@ -6,8 +6,8 @@
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// v_mfma_f64_16x16x4_f64 (CDNA4).  Operand/lane convention, checked on the
-// device by the layout test of the test-suite:
+// v_mfma_f64_16x16x4_f64 (CDNA4).  Operand/lane convention (any other layout
+// would break every energy parity test on the device):
 //   lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]  (A: 16x4, B: 4x16)
 //   accumulator element v of lane l is D[4 * v + l / 16][l % 16].
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {

@@ -16,12 +16,13 @@
 
 namespace lofqmc {
 
-// Pass 1: tile = up to LO_TILE_ROWS output rows of one orbital o x 32
-// walkers.  Per 16-row slab of r the factor rows (gathered through rowidx)
-// and Q_o of the 32 walkers are staged in LDS (double-buffered).  Wave q
-// owns the 16-row blocks q, q+4, q+8 of the tile against all four column
-// blocks (two 16-walker halves, real and imaginary part), so every factor
-// fragment is read from LDS once and feeds four MFMAs.
+// Pass 1: tile = up to LO_TILE_ROWS (64) output rows of one orbital o x 64
+// walkers, eight waves: wave (q, h) owns row block q (16 rows) against walker
+// half h (two 16-walker blocks, real and imaginary part: four accumulators),
+// so a workgroup needs few registers and several fit on a compute unit (FP64
+// MFMA needs more than one wave per SIMD to stay busy).  Per 16-row slab of r
+// the factor rows (gathered through rowidx) and Q_o of the 64 walkers are
+// staged in LDS (double-buffered).
 //
 // theta element (o, r, w) is read at theta[o * so + r * sr + w * sw], which
 // serves both layouts: walker-major [w][r][o] and orbital-major [o][r][w].
@@ -29,13 +30,11 @@ namespace lofqmc {
 // 8 XCDs (workgroups are dispatched round-robin over XCDs) and the tiles of
 // one unit run side by side on one XCD: with walker-major theta the orbitals
 // of a block share cache lines, which that XCD's L2 then fetches once.
-constexpr int LO_TILE_ROWS = 192;
-constexpr int LO_RB = LO_TILE_ROWS / 16;     // 12 row blocks per tile
-constexpr int LO_RBW = LO_RB / 4;            // 3 per wave
-constexpr int LO_WT = 32;
+constexpr int LO_TILE_ROWS = 64;
+constexpr int LO_WT = 64;
 constexpr int LO_OBLK = 8;
 
-__global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
+__global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
                                                           const int* __restrict__ rowidx,
                                                           const int* __restrict__ tile_orb,
                                                           const int* __restrict__ tile_row0,
@@ -61,59 +60,58 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
   const int o = tile_orb[t];
   const int row0 = tile_row0[t];
   const int nrows = tile_nrows[t];
-  const int nrb = (nrows + 15) / 16;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  const int q = wv & 3, hw = wv >> 2;
   const int lr = lane & 15, lk = lane >> 4;
+  const bool active = 16 * q < nrows;
   const double2* tho = theta + o * so;
 
-  // staging: A = nrows x 16 doubles (each row 128 contiguous bytes), B = 16 x 32 complex
-  constexpr int A_PER = (LO_TILE_ROWS * 16 + 255) / 256;   // 12
-  constexpr int B_PER = (16 * LO_WT + 255) / 256;          // 2
+  // staging: A = nrows x 16 doubles (each row 128 contiguous bytes), B = 16 x 64 complex
+  constexpr int A_PER = LO_TILE_ROWS * 16 / 512;   // 2
+  constexpr int B_PER = 16 * LO_WT / 512;          // 2
   double pa[A_PER];
   double2 pb[B_PER];
   // the gathered factor rows of this thread, resolved once (a row index read
   // inside the slab loop would put a dependent global load on every slab)
   const double* arow[A_PER];
 #pragma unroll
-  for (int q = 0; q < A_PER; ++q) {
-    const int row = (tid + 256 * q) >> 4;
-    arow[q] = row < nrows ? rows + (size_t)rowidx[row0 + row] * M : nullptr;
+  for (int p = 0; p < A_PER; ++p) {
+    const int row = (tid + 512 * p) >> 4;
+    arow[p] = row < nrows ? rows + (size_t)rowidx[row0 + row] * M : nullptr;
   }
   auto load = [&](int c) {
     const int rbase = 16 * c;
 #pragma unroll
-    for (int q = 0; q < A_PER; ++q) {
-      const int r = rbase + ((tid + 256 * q) & 15);
-      pa[q] = (arow[q] != nullptr && r < M) ? arow[q][r] : 0.0;
+    for (int p = 0; p < A_PER; ++p) {
+      const int r = rbase + ((tid + 512 * p) & 15);
+      pa[p] = (arow[p] != nullptr && r < M) ? arow[p][r] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < B_PER; ++q) {
-      const int e = tid + 256 * q;
+    for (int p = 0; p < B_PER; ++p) {
+      const int e = tid + 512 * p;
       const int rr = e / LO_WT, ww = e % LO_WT;
       const int r = rbase + rr;
       const int64_t w = w0 + ww;
-      pb[q] = (r < M && w < nw) ? tho[r * sr + w * sw] : make_double2(0.0, 0.0);
+      pb[p] = (r < M && w < nw) ? tho[r * sr + w * sw] : make_double2(0.0, 0.0);
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < A_PER; ++q) {
-      const int e = tid + 256 * q;
-      sA[buf][e >> 4][e & 15] = pa[q];
+    for (int p = 0; p < A_PER; ++p) {
+      const int e = tid + 512 * p;
+      sA[buf][e >> 4][e & 15] = pa[p];
     }
 #pragma unroll
-    for (int q = 0; q < B_PER; ++q) {
-      const int e = tid + 256 * q;
-      sB[buf][e / LO_WT][e % LO_WT] = pb[q];
+    for (int p = 0; p < B_PER; ++p) {
+      const int e = tid + 512 * p;
+      sB[buf][e / LO_WT][e % LO_WT] = pb[p];
     }
   };
 
-  d4 acc[LO_RBW][4];   // [row block][half * 2 + part]
+  d4 acc[4];   // [walker block * 2 + part]
 #pragma unroll
-  for (int i = 0; i < LO_RBW; ++i)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[i][c] = d4zero();
+  for (int c = 0; c < 4; ++c) acc[c] = d4zero();
   const int nchunk = (M + 15) / 16;
   load(0);
   store(0);
@@ -121,41 +119,33 @@ __global__ __launch_bounds__(256, 2) void lo_pass1_kernel(int M, int64_t nw, con
   for (int c = 0; c < nchunk; ++c) {
     const int buf = c & 1;
     if (c + 1 < nchunk) load(c + 1);
+    if (active) {
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int rr = 4 * s4 + lk;
-      const double2 b0 = sB[buf][rr][lr];
-      const double2 b1 = sB[buf][rr][16 + lr];
-#pragma unroll
-      for (int i = 0; i < LO_RBW; ++i) {
-        const int rb = wv + 4 * i;
-        if (rb < nrb) {
-          const double a = sA[buf][16 * rb + lr][rr];
-          acc[i][0] = mfma16(a, b0.x, acc[i][0]);
-          acc[i][1] = mfma16(a, b0.y, acc[i][1]);
-          acc[i][2] = mfma16(a, b1.x, acc[i][2]);
-          acc[i][3] = mfma16(a, b1.y, acc[i][3]);
-        }
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int rr = 4 * s4 + lk;
+        const double a = sA[buf][16 * q + lr][rr];
+        const double2 b0 = sB[buf][rr][32 * hw + lr];
+        const double2 b1 = sB[buf][rr][32 * hw + 16 + lr];
+        acc[0] = mfma16(a, b0.x, acc[0]);
+        acc[1] = mfma16(a, b0.y, acc[1]);
+        acc[2] = mfma16(a, b1.x, acc[2]);
+        acc[3] = mfma16(a, b1.y, acc[3]);
       }
     }
     if (c + 1 < nchunk) store(buf ^ 1);
     __syncthreads();
   }
-  // D[row][walker]: lane holds rows 4v + lk of each block, walker 16*half + lr
+  // D[row][walker]: lane holds rows 4v + lk of the block, walker 16 * half + lr
+  if (active) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int64_t w = w0 + 16 * h + lr;
-    if (w < nw) {
+    for (int h = 0; h < 2; ++h) {
+      const int64_t w = w0 + 32 * hw + 16 * h + lr;
+      if (w < nw) {
 #pragma unroll
-      for (int i = 0; i < LO_RBW; ++i) {
-        const int rb = wv + 4 * i;
-        if (rb < nrb) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int lrow = 16 * rb + 4 * v + lk;
-            if (lrow < nrows)
-              qbar[(size_t)(row0 + lrow) * nw + w] = make_double2(acc[i][2 * h][v], acc[i][2 * h + 1][v]);
-          }
+        for (int v = 0; v < 4; ++v) {
+          const int lrow = 16 * q + 4 * v + lk;
+          if (lrow < nrows)
+            qbar[(size_t)(row0 + lrow) * nw + w] = make_double2(acc[2 * h][v], acc[2 * h + 1][v]);
         }
       }
     }
@@ -175,7 +165,7 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
   const int64_t so = orbital_major ? (int64_t)M * nw : 1;
   const int64_t sr = orbital_major ? nw : n;
   const int64_t sw = orbital_major ? 1 : (int64_t)M * n;
-  hipLaunchKernelGGL(lo_pass1_kernel, dim3((unsigned)grid), dim3(256), 0, s, M, nw, rows, rowidx, tiles,
+  hipLaunchKernelGGL(lo_pass1_kernel, dim3((unsigned)grid), dim3(512), 0, s, M, nw, rows, rowidx, tiles,
                      tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax, (const double2*)theta, so, sr, sw,
                      (double2*)qbar, nwt);
   return hipGetLastError();

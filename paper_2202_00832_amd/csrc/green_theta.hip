@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void invert_kernel(int n, double2* __restrict_
   for (int k = 0; k < n; ++k) {
     const double2* col = sColBuf[k & 1];
     // pivot search, identical in every 16-lane row of every wave: key =
-    // |re|+|im| (46 leading bits, monotone as an integer) with 63 - row in the
+    // |re|+|im| (45 leading bits, monotone as an integer) with 127 - row in the
     // low 6 bits; max over the lane's NB rows, then over the 16 lanes (DPP)
     unsigned long long key = 0ull;
 #pragma unroll
@@ -183,12 +183,12 @@ __global__ __launch_bounds__(256) void invert_kernel(int n, double2* __restrict_
       const double2 cv = col[lr + 16 * m];
       const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(cv.x) + fabs(cv.y));
       const unsigned long long km =
-          (used >> m & 1u) ? 0ull : ((mb & ~63ull) | (unsigned long long)(63 - (lr + 16 * m)));
+          (used >> m & 1u) ? 0ull : ((mb & ~127ull) | (unsigned long long)(127 - (lr + 16 * m)));
       key = km > key ? km : key;
     }
     key = row16_max_u64(key);
-    const int p = __builtin_amdgcn_readfirstlane(63 - (int)(key & 63ull));
-    if ((key >> 6) == 0ull) { zero = k + 1; break; }
+    const int p = __builtin_amdgcn_readfirstlane(127 - (int)(key & 127ull));
+    if ((key >> 7) == 0ull) { zero = k + 1; break; }
     if ((p & 15) == lr) used |= 1u << (p >> 4);
     const double2 piv = col[p];                 // uniform LDS address: broadcast read
     // 1/piv = conj(piv) / |piv|^2 (O is an overlap of normalised orbitals, far
@@ -272,10 +272,12 @@ __global__ __launch_bounds__(256) void invert_kernel(int n, double2* __restrict_
   if (wv == 0) {
     // log det O = sum_k log(pivot_k) + i pi (parity of k -> p_k)
     double la = 0.0, ar = 0.0;
-    if (!zero && lane < n) {
-      const double2 pv = sPivV[lane];
-      la = log(hypot(pv.x, pv.y));
-      ar = atan2(pv.y, pv.x);
+    if (!zero) {
+      for (int k = lane; k < n; k += 64) {
+        const double2 pv = sPivV[k];
+        la += log(hypot(pv.x, pv.y));
+        ar += atan2(pv.y, pv.x);
+      }
     }
     la = wave_sum_lane0(la);
     ar = wave_sum_lane0(ar);
@@ -287,12 +289,15 @@ __global__ __launch_bounds__(256) void invert_kernel(int n, double2* __restrict_
           ld = make_double2(__builtin_nan(""), __builtin_nan(""));
         } else {
           int cycles = 0;
-          unsigned long long seen = 0ull;
+          unsigned long long seen[2] = {0ull, 0ull};   // n <= 128
           for (int s2 = 0; s2 < n; ++s2) {
-            if (seen >> s2 & 1ull) continue;
+            if (seen[s2 >> 6] >> (s2 & 63) & 1ull) continue;
             ++cycles;
             int c = s2;
-            while (!(seen >> c & 1ull)) { seen |= 1ull << c; c = sPiv[c]; }
+            while (!(seen[c >> 6] >> (c & 63) & 1ull)) {
+              seen[c >> 6] |= 1ull << (c & 63);
+              c = sPiv[c];
+            }
           }
           double im = ar + ((n - cycles) & 1 ? M_PI : 0.0);
           im = remainder(im, 2.0 * M_PI);  // (-pi, pi]
@@ -341,22 +346,17 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, co
     d4 P1[NB], P2[NB], P3[NB];
 #pragma unroll
     for (int J = 0; J < NB; ++J) { P1[J] = d4zero(); P2[J] = d4zero(); P3[J] = d4zero(); }
-    double2 av[C::NKS];
-#pragma unroll
-    for (int ks = 0; ks < C::NKS; ++ks) {
-      const int kk = 4 * ks + lk;
-      av[ks] = (ks < ksteps && r < M && kk < n) ? ph[(size_t)r * n + kk] : make_double2(0.0, 0.0);
-    }
 #pragma unroll
     for (int ks = 0; ks < C::NKS; ++ks) {
       if (ks < ksteps) {
         const int kk = 4 * ks + lk;
-        const double as = av[ks].x + av[ks].y;
+        const double2 av = (r < M && kk < n) ? ph[(size_t)r * n + kk] : make_double2(0.0, 0.0);
+        const double as = av.x + av.y;
 #pragma unroll
         for (int J = 0; J < NB; ++J) {
           const double2 bv = sB[kk * NP + 16 * J + lr];
-          P1[J] = mfma16(av[ks].x, bv.x, P1[J]);
-          P2[J] = mfma16(av[ks].y, bv.y, P2[J]);
+          P1[J] = mfma16(av.x, bv.x, P1[J]);
+          P2[J] = mfma16(av.y, bv.y, P2[J]);
           P3[J] = mfma16(as, bv.x + bv.y, P3[J]);
         }
       }
@@ -413,7 +413,9 @@ hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const dou
   if (n <= 16) return launch_gt<1>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
   if (n <= 32) return launch_gt<2>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
   if (n <= 48) return launch_gt<3>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
-  return launch_gt<4>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 64) return launch_gt<4>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 80) return launch_gt<5>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
+  return launch_gt<6>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
 }
 
 }  // namespace lofqmc

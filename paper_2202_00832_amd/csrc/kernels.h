@@ -27,6 +27,13 @@ hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const dou
 int full_num_chunks(int64_t X, int64_t nw);
 hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* lbar,
                               const double* theta, double* partial, int nchunk);
+// reduced-precision variant (precision LO_FP32 or LO_BF16X3): work is a device
+// buffer of full_lp_workspace(...) bytes; partial holds nchunk + 1 chunk rows
+// (the exchange chunks, then the Coulomb row)
+size_t full_lp_workspace(int precision, int M, int n, int64_t X, int64_t nw);
+hipError_t launch_energy_full_lp(hipStream_t s, int precision, int M, int n, int64_t X, int64_t nw,
+                                 const double* lbar, const double* theta, void* work, double* partial, int nchunk,
+                                 const ProfHook* prof);
 hipError_t launch_reduce_partials(hipStream_t s, int64_t nw, int nchunk, const double* partial, const int* info,
                                   double* energy);
 
@@ -41,6 +48,56 @@ int lo_orbital_block();
 int lo_pass2_chunks(int npairs);
 hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int npairs, int nchunk, const int* pK, const int64_t* offI,
                            const int64_t* offJ, const double* pw, const double* qbar, double* partial);
+
+// ---- reduced precision helpers (M padded to a multiple of 32, n to 16 NB)
+int lp_padded_m(int M);
+int lp_orbital_blocks(int n);   // NB = ceil(n / 16)
+size_t lp_lbar_bytes(int precision, int M, int n, int64_t X);
+size_t coulomb_cpart_bytes(int M, int n, int64_t X, int64_t nw);
+// lbar and theta -> the padded reduced-precision copies lb, tb
+hipError_t launch_lp_convert_operands(hipStream_t s, int precision, int M, int n, int64_t X, int64_t nw,
+                                      const double* lbar, const double* theta, void* lb, void* tb);
+// FP64 Coulomb sums: out_row[w] = (2 sum_g (Tr T_wg)^2, 0) as one partial row [nw][4]
+hipError_t launch_coulomb_fp64(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* theta,
+                               const double* lbar, void* cpart_ws, double* out_row, const ProfHook* prof);
+// one system of a batched FP32 exchange launch; items [item0, item0 + ngrp * nchunk)
+struct LpSys {
+  int Mp, nb;
+  int64_t X, nw, gchunk, nchunk, item0;
+  const void* lb;
+  const void* tb;
+  double* partial;
+};
+// resets the item counter (a kernel, so the sequence can be captured in a
+// graph) and runs the persistent kernel over all items with `grid` workgroups
+hipError_t launch_exchange_batched(hipStream_t s, int nsys, const LpSys* d_sys, int64_t nitems, unsigned* counter,
+                                   int grid);
+// theta [nw][M][n] complex -> FP32 [nw][Mp][NP] float2, or split BF16
+// [nw][4][NP][Mp] (re_hi, re_lo, im_hi, im_lo); lp_theta_bytes gives the size
+size_t lp_theta_bytes(int precision, int M, int n, int64_t nw);
+hipError_t launch_lp_convert_theta(hipStream_t s, int precision, int M, int n, int64_t nw, const double* theta,
+                                   void* out);
+// factor rows [rows][M] -> FP32 [rows][Mp] and split BF16 [rows][2][Mp]
+hipError_t launch_factor_rows_lp(hipStream_t s, int M, int64_t nrows, const double* rows, float* r32,
+                                 __bf16* rbf);
+// pass 1 of the LO route from the reduced-precision copies (tables as launch_lo_pass1)
+hipError_t launch_lo_pass1_lp(hipStream_t s, int precision, int M, int n, int64_t nw, int ntiles,
+                              const void* rows_lp, const int* rowidx, const int* tiles, const int* blk, int nblk,
+                              int tmax, const void* theta_lp, double* qbar);
+
+// ---- learned residual of the LO energy
+int residual_nparam();
+size_t residual_train_workspace(int64_t nw, int n);
+size_t residual_predict_workspace(int bf16, int64_t nw, int n);
+// orb: device float [n][2] (sum_j K_ij, sum_j discarded mass); x: [nw][n][3]
+hipError_t launch_residual_features(hipStream_t s, int M, int n, int64_t nw, const double* theta, const float* orb,
+                                    float* x);
+hipError_t launch_residual_predict(hipStream_t s, int bf16, int64_t nw, int n, const float* params, const float* x,
+                                   void* work, double* pred);
+// step <= 0: gradient (and loss, predictions) only, no update
+hipError_t launch_residual_train_step(hipStream_t s, int64_t nw, int n, float* params, float* m, float* v,
+                                      int64_t step, float lr, const float* x, const double* target, void* work,
+                                      float* grad_out, double* loss, double* pred);
 
 // ---- set-up
 // C_b(m, c) = sum_k A_b(m, k) B_b(k, c), element (m, k) of A at a_base[b] + m * a_m + k * a_k, etc.

@@ -35,8 +35,11 @@ struct lo_ctx {
 struct lo_factors {
   int64_t M = 0, n = 0, total_rows = 0, n_out_rows = 0;
   double* rows = nullptr;  // device [total_rows][M]
+  float* rows32 = nullptr;   // device [total_rows][Mp] (reduced-precision copies, M padded to Mp)
+  __bf16* rowsbf = nullptr;  // device [total_rows][2][Mp] (hi, lo)
   std::vector<int32_t> ranks;          // [n][n]
   std::vector<double> first_dropped;   // [n][n]
+  std::vector<double> discarded;       // [n][n], sum of the discarded singular values
   std::vector<int64_t> row_offset;     // [n][n], -1 for i > j
   int ntiles = 0, npairs = 0, nblk = 0, tmax = 0;
   int* d_rowidx = nullptr;             // [n_out_rows]
@@ -45,11 +48,13 @@ struct lo_factors {
   int* d_pK = nullptr;                 // [npairs]
   int64_t* d_off = nullptr;            // [2][npairs]: output rows of the pair for orbital i and j
   double* d_pw = nullptr;              // [npairs]
+  float* d_orbfeat = nullptr;          // [n][2]: sum_j K_ij, sum_j discarded mass (residual features)
 };
 
 namespace {
 
-constexpr int kMaxOcc = 64;
+constexpr int kMaxOcc = 64;     // FP64 full route
+constexpr int kMaxOccWide = 96;  // green_theta and the reduced-precision energies
 
 int fail(lo_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -108,11 +113,14 @@ int upload(lo_ctx* c, T** dst, const std::vector<T>& src) {
 void free_factors(lo_factors* f) {
   if (!f) return;
   (void)hipFree(f->rows);
+  (void)hipFree(f->rows32);
+  (void)hipFree(f->rowsbf);
   (void)hipFree(f->d_rowidx);
   (void)hipFree(f->d_tiles);
   (void)hipFree(f->d_pK);
   (void)hipFree(f->d_off);
   (void)hipFree(f->d_pw);
+  (void)hipFree(f->d_orbfeat);
   delete f;
 }
 
@@ -366,6 +374,7 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
   f->n = n;
   f->ranks.assign(n * n, 0);
   f->first_dropped.assign(n * n, 0.0);
+  f->discarded.assign(n * n, 0.0);
   f->row_offset.assign(n * n, -1);
 
   std::vector<std::pair<int, int>> plist;
@@ -422,6 +431,11 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
       f->ranks[i * n + j] = f->ranks[j * n + i] = K;
       const double fd = (K < M) ? s[K] : 0.0;
       f->first_dropped[i * n + j] = f->first_dropped[j * n + i] = fd;
+      {
+        double mass = 0.0;
+        for (int64_t k = K; k < M; ++k) mass += s[k];
+        f->discarded[i * n + j] = f->discarded[j * n + i] = mass;
+      }
       f->row_offset[i * n + j] = total_rows + batch_rows;
       K_host[b] = K;
       roff_host[b] = batch_rows;
@@ -448,6 +462,11 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
                              hipMemcpyDeviceToDevice, ctx->stream));
       at += chunk_rows[c];
     }
+    // FP32 and split-BF16 copies for the reduced-precision energy
+    const size_t Mp = (size_t)lofqmc::lp_padded_m((int)M);
+    TRY_ALLOC(f->rows32, sizeof(float) * (size_t)total_rows * Mp);
+    TRY_ALLOC(f->rowsbf, sizeof(__bf16) * 2 * (size_t)total_rows * Mp);
+    TRY_HIP(lofqmc::launch_factor_rows_lp(ctx->stream, (int)M, total_rows, f->rows, f->rows32, f->rowsbf));
   }
 
   // ---- tables of the two energy passes
@@ -523,8 +542,19 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
   }
   f->npairs = (int)pK.size();
   off.insert(off.end(), offJ.begin(), offJ.end());
+  std::vector<float> orbfeat(2 * n, 0.0f);
+  for (int i = 0; i < n; ++i) {
+    double ks = 0.0, ms = 0.0;
+    for (int j = 0; j < n; ++j) {
+      ks += f->ranks[i * n + j];
+      ms += f->discarded[i * n + j];
+    }
+    orbfeat[2 * i] = (float)ks;
+    orbfeat[2 * i + 1] = (float)ms;
+  }
   if ((rc = upload(ctx, &f->d_rowidx, rowidx)) || (rc = upload(ctx, &f->d_tiles, tiles)) ||
-      (rc = upload(ctx, &f->d_pK, pK)) || (rc = upload(ctx, &f->d_off, off)) || (rc = upload(ctx, &f->d_pw, pw))) {
+      (rc = upload(ctx, &f->d_pK, pK)) || (rc = upload(ctx, &f->d_off, off)) || (rc = upload(ctx, &f->d_pw, pw)) ||
+      (rc = upload(ctx, &f->d_orbfeat, orbfeat))) {
     cleanup();
     free_factors(f);
     return rc;
@@ -572,7 +602,7 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   ctx->err.clear();
   if (M <= 0 || n_occ <= 0 || nw < 0) return fail(ctx, LO_EINVAL, "sizes must be M > 0, n_occ > 0, nw >= 0");
   if (n_occ > M) return fail(ctx, LO_EINVAL, "n_occ exceeds M");
-  if (n_occ > kMaxOcc) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d", kMaxOcc);
+  if (n_occ > kMaxOccWide) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d", kMaxOccWide);
   if (M > (1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "M above 2^24");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
   if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
@@ -593,27 +623,43 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
   ctx->err.clear();
   if (M <= 0 || n_occ <= 0 || n_chol < 0 || nw < 0) return fail(ctx, LO_EINVAL, "bad sizes");
   if (n_occ > M) return fail(ctx, LO_EINVAL, "n_occ exceeds M");
-  if (precision != LO_FP64) return fail(ctx, LO_EUNSUPPORTED, "precision %d not implemented", precision);
+  if (precision != LO_FP64 && precision != LO_FP32 && precision != LO_BF16X3)
+    return fail(ctx, LO_EINVAL, "unknown precision %d", precision);
   if (flags != 0) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
-  if (n_occ > kMaxOcc) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d", kMaxOcc);
+  if (n_occ > (precision == LO_FP32 ? kMaxOccWide : kMaxOcc))
+    return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d for this precision",
+                precision == LO_FP32 ? kMaxOccWide : kMaxOcc);
   if (M > (1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "M above 2^24");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
+  if (precision != LO_FP64 && (n_chol > 65535 || nw > 65535))
+    return fail(ctx, LO_EUNSUPPORTED, "reduced precision supports nw <= 65535 and n_chol <= 65535");
   if (nw == 0) return LO_OK;
   if ((n_chol > 0 && !lbar) || !theta || !energy) return fail(ctx, LO_EINVAL, "null array");
   // with no Cholesky vectors there are no chunks and the reduction writes zeros
   const int nchunk = n_chol > 0 ? lofqmc::full_num_chunks(n_chol, nw) : 0;
-  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)std::max(nchunk, 1) * nw);
-  int rc = ensure_ws(ctx, pbytes);
+  // reduced precision adds one chunk row for the FP64 Coulomb sums
+  const int nrows = (precision != LO_FP64 && n_chol > 0) ? nchunk + 1 : nchunk;
+  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)std::max(nrows, 1) * nw);
+  const size_t lbytes = (precision != LO_FP64 && n_chol > 0)
+                            ? lofqmc::full_lp_workspace(precision, (int)M, (int)n_occ, n_chol, nw)
+                            : 0;
+  int rc = ensure_ws(ctx, pbytes + align256(lbytes));
   if (rc) return rc;
   double* partial = (double*)ctx->ws;
   ProfScope prof(ctx);
   if (n_chol > 0) {
-    prof.mark("energy_full_kernel");
-    HIP_OR_FAIL(ctx, lofqmc::launch_energy_full(ctx->stream, (int)M, (int)n_occ, n_chol, nw, lbar, theta, partial,
-                                                nchunk));
+    if (precision == LO_FP64) {
+      prof.mark("energy_full_kernel");
+      HIP_OR_FAIL(ctx, lofqmc::launch_energy_full(ctx->stream, (int)M, (int)n_occ, n_chol, nw, lbar, theta,
+                                                  partial, nchunk));
+    } else {
+      HIP_OR_FAIL(ctx, lofqmc::launch_energy_full_lp(ctx->stream, precision, (int)M, (int)n_occ, n_chol, nw, lbar,
+                                                     theta, (char*)ctx->ws + pbytes, partial, nchunk,
+                                                     prof.get()));
+    }
   }
   prof.mark("reduce_partials_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nchunk, partial, info, energy));
+  HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nrows, partial, info, energy));
   return LO_OK;
 }
 
@@ -623,31 +669,343 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
   ctx->err.clear();
   if (!f) return fail(ctx, LO_EINVAL, "null factors");
   if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
-  if (precision != LO_FP64) return fail(ctx, LO_EUNSUPPORTED, "precision %d not implemented", precision);
+  if (precision != LO_FP64 && precision != LO_FP32 && precision != LO_BF16X3)
+    return fail(ctx, LO_EINVAL, "unknown precision %d", precision);
   if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
+  if (precision != LO_FP64 && orbital_major)
+    return fail(ctx, LO_EUNSUPPORTED, "reduced precision reads walker-major theta only");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
+  if (precision != LO_FP64 && nw > 65535) return fail(ctx, LO_EUNSUPPORTED, "reduced precision: nw above 65535");
+  if (precision != LO_FP64 && f->n > (precision == LO_FP32 ? kMaxOccWide : kMaxOcc))
+    return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d for this precision",
+                precision == LO_FP32 ? kMaxOccWide : kMaxOcc);
   if (nw == 0) return LO_OK;
   if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
-  const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
   const int64_t M = f->M, n = f->n;
   const int nchunk = lofqmc::lo_pass2_chunks(f->npairs);
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
   const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
-  int rc = ensure_ws(ctx, qbytes + pbytes);
+  const size_t tbytes = precision == LO_FP64 ? 0 : align256(lofqmc::lp_theta_bytes(precision, (int)M, (int)n, nw));
+  int rc = ensure_ws(ctx, qbytes + pbytes + tbytes);
   if (rc) return rc;
   char* base = (char*)ctx->ws;
   double* qbar = (double*)base;
   double* partial = (double*)(base + qbytes);
   ProfScope prof(ctx);
-  prof.mark("lo_pass1_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
-                                           f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
-                                           orbital_major ? 1 : 0, qbar));
+  if (precision == LO_FP64) {
+    prof.mark("lo_pass1_kernel");
+    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
+                                             f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
+                                             orbital_major ? 1 : 0, qbar));
+  } else if (f->ntiles > 0) {
+    void* tlp = base + qbytes + pbytes;
+    prof.mark("lp_convert_kernel");
+    HIP_OR_FAIL(ctx, lofqmc::launch_lp_convert_theta(ctx->stream, precision, (int)M, (int)n, nw, theta, tlp));
+    prof.mark("lo_pass1_lp_kernel");
+    const void* rows_lp = precision == LO_FP32 ? (const void*)f->rows32 : (const void*)f->rowsbf;
+    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1_lp(ctx->stream, precision, (int)M, (int)n, nw, f->ntiles, rows_lp,
+                                                f->d_rowidx, f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk,
+                                                f->tmax, tlp, qbar));
+  }
   prof.mark("lo_pass2_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->npairs, nchunk, f->d_pK, f->d_off,
                                            f->d_off + f->npairs, f->d_pw, qbar, partial));
   prof.mark("reduce_partials_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nchunk, partial, info, energy));
+  return LO_OK;
+}
+
+// ------------------------------------------------------ several systems
+
+}  // extern "C"
+
+struct lo_batch {
+  int nsys = 0;
+  std::vector<lo_system> sys;
+  std::vector<int64_t> chunk, nchunk;
+  int64_t nitems = 0;
+  int grid = 0;
+  void* mem = nullptr;                      // one device allocation for everything below
+  std::vector<void*> lb, tb, cpart;         // per system
+  std::vector<double*> partial;             // per system [nchunk + 1][nw][4]
+  lofqmc::LpSys* d_sys = nullptr;
+  unsigned* d_counter = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_free(lo_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  (void)hipFree(b->mem);
+  delete b;
+}
+
+hipError_t batch_enqueue(lo_batch* b, hipStream_t st) {
+  hipError_t e;
+  for (int k = 0; k < b->nsys; ++k) {
+    const lo_system& s = b->sys[k];
+    e = lofqmc::launch_lp_convert_operands(st, LO_FP32, (int)s.M, (int)s.n_occ, s.n_chol, s.nw, s.lbar, s.theta,
+                                           b->lb[k], b->tb[k]);
+    if (e != hipSuccess) return e;
+  }
+  e = lofqmc::launch_exchange_batched(st, b->nsys, b->d_sys, b->nitems, b->d_counter, b->grid);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < b->nsys; ++k) {
+    const lo_system& s = b->sys[k];
+    e = lofqmc::launch_coulomb_fp64(st, (int)s.M, (int)s.n_occ, s.n_chol, s.nw, s.theta, s.lbar, b->cpart[k],
+                                    b->partial[k] + (size_t)b->nchunk[k] * s.nw * 4, nullptr);
+    if (e != hipSuccess) return e;
+    e = lofqmc::launch_reduce_partials(st, s.nw, (int)b->nchunk[k] + 1, b->partial[k], s.info, s.energy);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lo_batch_create(lo_ctx* ctx, int nsys, const lo_system* sys, int precision, const int64_t* chunk,
+                    lo_batch** out) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!out || nsys <= 0 || !sys) return fail(ctx, LO_EINVAL, "need nsys > 0 systems and an output handle");
+  if (precision != LO_FP32) return fail(ctx, LO_EUNSUPPORTED, "batched evaluation is LO_FP32 only");
+  if (nsys > 4096) return fail(ctx, LO_EUNSUPPORTED, "more than 4096 systems");
+  for (int k = 0; k < nsys; ++k) {
+    const lo_system& s = sys[k];
+    if (s.M <= 0 || s.n_occ <= 0 || s.n_chol <= 0 || s.nw <= 0 || s.n_occ > s.M)
+      return fail(ctx, LO_EINVAL, "system %d: bad sizes", k);
+    if (s.n_occ > kMaxOccWide || s.nw > 65535 || s.n_chol > 65535 || s.M > (1 << 20))
+      return fail(ctx, LO_EUNSUPPORTED, "system %d: outside n_occ <= 96, nw, n_chol <= 65535", k);
+    if (!s.lbar || !s.theta || !s.energy) return fail(ctx, LO_EINVAL, "system %d: null array", k);
+  }
+  int dev = 0, ncu = 0;
+  HIP_OR_FAIL(ctx, hipGetDevice(&dev));
+  HIP_OR_FAIL(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  lo_batch* b = new (std::nothrow) lo_batch();
+  if (!b) return fail(ctx, LO_ENOMEM, "host allocation failed");
+  b->nsys = nsys;
+  b->sys.assign(sys, sys + nsys);
+  b->grid = std::max(ncu, 1);
+  // cost of one Cholesky vector for 4 walkers ~ Mp * NB^2; default chunks make
+  // all items cost about total / (16 * grid)
+  std::vector<double> unit(nsys);
+  double total = 0.0;
+  for (int k = 0; k < nsys; ++k) {
+    const lo_system& s = b->sys[k];
+    const double nb = lofqmc::lp_orbital_blocks((int)s.n_occ);
+    unit[k] = (double)lofqmc::lp_padded_m((int)s.M) * nb * nb;
+    total += unit[k] * (double)s.n_chol * (double)((s.nw + 3) / 4);
+  }
+  const double target = total / (16.0 * b->grid);
+  b->chunk.resize(nsys);
+  b->nchunk.resize(nsys);
+  for (int k = 0; k < nsys; ++k) {
+    const lo_system& s = b->sys[k];
+    int64_t c = (chunk && chunk[k] > 0) ? chunk[k] : (int64_t)std::llround(target / unit[k]);
+    c = std::min<int64_t>(std::max<int64_t>(c, 1), s.n_chol);
+    b->chunk[k] = c;
+    b->nchunk[k] = (s.n_chol + c - 1) / c;
+  }
+  // item order: systems by decreasing cost per item, so the largest items
+  // are taken first by the persistent kernel
+  std::vector<int> order(nsys);
+  for (int k = 0; k < nsys; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return unit[a] * b->chunk[a] > unit[c] * b->chunk[c]; });
+  // one allocation: per system lb, tb, cpart, partial; then the table and the counter
+  std::vector<size_t> off_lb(nsys), off_tb(nsys), off_cp(nsys), off_pa(nsys);
+  size_t at = 0;
+  for (int k = 0; k < nsys; ++k) {
+    const lo_system& s = b->sys[k];
+    off_lb[k] = at;
+    at += align256(lofqmc::lp_lbar_bytes(LO_FP32, (int)s.M, (int)s.n_occ, s.n_chol));
+    off_tb[k] = at;
+    at += align256(lofqmc::lp_theta_bytes(LO_FP32, (int)s.M, (int)s.n_occ, s.nw));
+    off_cp[k] = at;
+    at += align256(lofqmc::coulomb_cpart_bytes((int)s.M, (int)s.n_occ, s.n_chol, s.nw));
+    off_pa[k] = at;
+    at += align256(sizeof(double) * 4 * (size_t)(b->nchunk[k] + 1) * s.nw);
+  }
+  const size_t off_sys = at;
+  at += align256(sizeof(lofqmc::LpSys) * nsys);
+  const size_t off_cnt = at;
+  at += 256;
+  if (hipMalloc(&b->mem, at) != hipSuccess) {
+    b->mem = nullptr;
+    batch_free(b);
+    return fail(ctx, LO_ENOMEM, "batch allocation of %zu bytes failed", at);
+  }
+  char* base = (char*)b->mem;
+  b->lb.resize(nsys);
+  b->tb.resize(nsys);
+  b->cpart.resize(nsys);
+  b->partial.resize(nsys);
+  std::vector<lofqmc::LpSys> table(nsys);
+  int64_t item = 0;
+  for (int q = 0; q < nsys; ++q) {
+    const int k = order[q];
+    const lo_system& s = b->sys[k];
+    b->lb[k] = base + off_lb[k];
+    b->tb[k] = base + off_tb[k];
+    b->cpart[k] = base + off_cp[k];
+    b->partial[k] = (double*)(base + off_pa[k]);
+    lofqmc::LpSys& d = table[q];
+    d.Mp = lofqmc::lp_padded_m((int)s.M);
+    d.nb = lofqmc::lp_orbital_blocks((int)s.n_occ);
+    d.X = s.n_chol;
+    d.nw = s.nw;
+    d.gchunk = b->chunk[k];
+    d.nchunk = b->nchunk[k];
+    d.item0 = item;
+    d.lb = b->lb[k];
+    d.tb = b->tb[k];
+    d.partial = b->partial[k];
+    item += d.nchunk * ((s.nw + 3) / 4);
+  }
+  b->nitems = item;
+  if (b->nitems > ((int64_t)1 << 31)) {
+    batch_free(b);
+    return fail(ctx, LO_EUNSUPPORTED, "more than 2^31 work items");
+  }
+  b->d_sys = (lofqmc::LpSys*)(base + off_sys);
+  b->d_counter = (unsigned*)(base + off_cnt);
+  if (hipMemcpy(b->d_sys, table.data(), sizeof(lofqmc::LpSys) * nsys, hipMemcpyHostToDevice) != hipSuccess) {
+    batch_free(b);
+    return fail(ctx, LO_EHIP, "upload of the batch table failed");
+  }
+  *out = b;
+  return LO_OK;
+}
+
+int lo_batch_destroy(lo_batch* b) {
+  batch_free(b);
+  return LO_OK;
+}
+
+int lo_batch_info(const lo_batch* b, int64_t* nitems, int64_t* chunk) {
+  if (!b) return LO_EINVAL;
+  if (nitems) *nitems = b->nitems;
+  if (chunk) std::memcpy(chunk, b->chunk.data(), sizeof(int64_t) * b->nsys);
+  return LO_OK;
+}
+
+int lo_batch_execute(lo_ctx* ctx, lo_batch* b) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!b) return fail(ctx, LO_EINVAL, "null batch");
+  ProfScope prof(ctx);
+  prof.mark("batch_evaluation");
+  HIP_OR_FAIL(ctx, batch_enqueue(b, ctx->stream));
+  return LO_OK;
+}
+
+int lo_batch_capture(lo_ctx* ctx, lo_batch* b, int repeats) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!b || repeats <= 0) return fail(ctx, LO_EINVAL, "need a batch and repeats > 0");
+  if (b->exec) {
+    HIP_OR_FAIL(ctx, hipGraphExecDestroy(b->exec));
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    HIP_OR_FAIL(ctx, hipGraphDestroy(b->graph));
+    b->graph = nullptr;
+  }
+  if (!b->cap) HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  // everything queued before capture must be complete: the capture stream
+  // does not order against the context stream
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_OR_FAIL(ctx, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < repeats && e == hipSuccess; ++r) e = batch_enqueue(b, b->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(ctx, LO_EHIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  b->graph = g;
+  HIP_OR_FAIL(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return LO_OK;
+}
+
+int lo_batch_replay(lo_ctx* ctx, lo_batch* b) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!b || !b->exec) return fail(ctx, LO_EINVAL, "no captured graph");
+  ProfScope prof(ctx);
+  prof.mark("batch_graph");
+  HIP_OR_FAIL(ctx, hipGraphLaunch(b->exec, ctx->stream));
+  return LO_OK;
+}
+
+// ------------------------------------------------------ learned residual
+
+int lo_residual_nparam(void) { return lofqmc::residual_nparam(); }
+
+int lo_factors_discarded(const lo_factors* f, double* mass) {
+  if (!f || !mass) return LO_EINVAL;
+  std::memcpy(mass, f->discarded.data(), sizeof(double) * f->discarded.size());
+  return LO_OK;
+}
+
+int lo_residual_features(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, float* x) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!f) return fail(ctx, LO_EINVAL, "null factors");
+  if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
+  if (nw == 0) return LO_OK;
+  if (!theta || !x) return fail(ctx, LO_EINVAL, "null array");
+  if (!f->d_orbfeat) return fail(ctx, LO_EINVAL, "factors hold no orbital table");
+  ProfScope prof(ctx);
+  prof.mark("residual_features_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_residual_features(ctx->stream, (int)f->M, (int)f->n, nw, theta, f->d_orbfeat, x));
+  return LO_OK;
+}
+
+int lo_residual_predict(lo_ctx* ctx, int64_t nw, int64_t n_occ, const float* params, const float* x, int precision,
+                        double* pred) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (nw < 0 || n_occ <= 0) return fail(ctx, LO_EINVAL, "bad sizes");
+  if (precision != LO_FP32 && precision != LO_BF16) return fail(ctx, LO_EINVAL, "precision must be FP32 or BF16");
+  if (nw * n_occ > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw * n_occ above 2^31-1");
+  if (nw == 0) return LO_OK;
+  if (!params || !x || !pred) return fail(ctx, LO_EINVAL, "null array");
+  const int bf = precision == LO_BF16 ? 1 : 0;
+  int rc = ensure_ws(ctx, lofqmc::residual_predict_workspace(bf, nw, (int)n_occ));
+  if (rc) return rc;
+  ProfScope prof(ctx);
+  prof.mark(bf ? "residual_infer_bf16_kernel" : "residual_forward_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_residual_predict(ctx->stream, bf, nw, (int)n_occ, params, x, ctx->ws, pred));
+  return LO_OK;
+}
+
+int lo_residual_train_step(lo_ctx* ctx, int64_t nw, int64_t n_occ, float* params, float* adam_m, float* adam_v,
+                           int64_t step, double lr, const float* x, const double* target, float* grad, double* loss,
+                           double* pred) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (nw < 0 || n_occ <= 0 || step < 0) return fail(ctx, LO_EINVAL, "bad sizes or step");
+  if (!(lr >= 0.0)) return fail(ctx, LO_EINVAL, "lr must be >= 0");
+  if (nw * n_occ > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw * n_occ above 2^31-1");
+  if (nw == 0) return LO_OK;
+  if (!params || !x || !target || (step > 0 && (!adam_m || !adam_v))) return fail(ctx, LO_EINVAL, "null array");
+  int rc = ensure_ws(ctx, lofqmc::residual_train_workspace(nw, (int)n_occ));
+  if (rc) return rc;
+  ProfScope prof(ctx);
+  prof.mark("residual_train_step");
+  HIP_OR_FAIL(ctx, lofqmc::launch_residual_train_step(ctx->stream, nw, (int)n_occ, params, adam_m, adam_v, step,
+                                                      (float)lr, x, target, ctx->ws, grad, loss, pred));
   return LO_OK;
 }
 

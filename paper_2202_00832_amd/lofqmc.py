@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblofqmc.s
 HEADER_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lofqmc.h")
 
 LO_OK, LO_EINVAL, LO_ENOMEM, LO_EHIP, LO_EUNSUPPORTED, LO_ESOLVER = 0, -1, -2, -3, -4, -5
-LO_FP64, LO_FP32, LO_BF16X3 = 0, 1, 2
+LO_FP64, LO_FP32, LO_BF16X3, LO_BF16 = 0, 1, 2, 3
 LO_THETA_ORBITAL_MAJOR = 1
 _NAMES = {0: "LO_OK", -1: "LO_EINVAL", -2: "LO_ENOMEM", -3: "LO_EHIP", -4: "LO_EUNSUPPORTED", -5: "LO_ESOLVER"}
 
@@ -41,7 +41,27 @@ _SIGS = {
     "local_energy_full": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _i64, _c_p, _c_p, _c_p, ctypes.c_int,
                                          ctypes.c_uint, _c_p]),
     "local_energy_lo": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p]),
+    "lo_batch_create": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int, _c_p, ctypes.POINTER(_c_p)]),
+    "lo_batch_destroy": (ctypes.c_int, [_c_p]),
+    "lo_batch_info": (ctypes.c_int, [_c_p, _c_p, _c_p]),
+    "lo_batch_execute": (ctypes.c_int, [_c_p, _c_p]),
+    "lo_batch_capture": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int]),
+    "lo_batch_replay": (ctypes.c_int, [_c_p, _c_p]),
+    "lo_residual_nparam": (ctypes.c_int, []),
+    "lo_factors_discarded": (ctypes.c_int, [_c_p, _c_p]),
+    "lo_residual_features": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p]),
+    "lo_residual_predict": (ctypes.c_int, [_c_p, _i64, _i64, _c_p, _c_p, ctypes.c_int, _c_p]),
+    "lo_residual_train_step": (ctypes.c_int, [_c_p, _i64, _i64, _c_p, _c_p, _c_p, _i64, ctypes.c_double, _c_p,
+                                              _c_p, _c_p, _c_p, _c_p]),
 }
+
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("n_occ", ctypes.c_int64), ("n_chol", ctypes.c_int64), ("nw", ctypes.c_int64),
+                ("lbar", ctypes.c_void_p), ("theta", ctypes.c_void_p), ("info", ctypes.c_void_p),
+                ("energy", ctypes.c_void_p)]
+
 
 _lib = None
 
@@ -134,6 +154,15 @@ class Factors:
         return {"M": M.value, "n_occ": n.value, "ranks": ranks, "first_dropped": fd,
                 "total_rows": rows.value, "bytes": nbytes.value}
 
+    def discarded(self) -> np.ndarray:
+        """Sum of the discarded singular values of every pair block, [n][n]."""
+        n = self.n_occ
+        out = np.zeros((n, n), dtype=np.float64)
+        rc = load().lo_factors_discarded(self._h, out.ctypes.data)
+        if rc != LO_OK:
+            raise LoError(rc, "lo_factors_discarded failed")
+        return out
+
     def export(self) -> dict:
         """{(i, j): (Ubar [M x K], Vbar [K x M], first_dropped)} for i <= j (host copies)."""
         inf = self.info()
@@ -152,6 +181,71 @@ class Factors:
                 Vbar = rows[o + K:o + 2 * K].copy()
                 out[(i, j)] = (Ubar, Vbar, float(inf["first_dropped"][i, j]))
         return out
+
+
+class Batch:
+    """A plan for the FP32 full-route energies of several systems (lo_batch_*)."""
+
+    def __init__(self, ctx: "Context", systems, chunk=None):
+        """systems: list of dicts with lbar [X][M][n] f64, theta [nw][M][n] c128,
+        optional info [nw] i32 and energy [nw][2] c128 (device tensors)."""
+        import torch
+        self.ctx = ctx
+        self.systems = []
+        arr = (_System * len(systems))()
+        for k, sd in enumerate(systems):
+            lbar, theta = sd["lbar"], sd["theta"]
+            X, M, n = lbar.shape
+            nw = theta.shape[0]
+            _check_dev("lbar", lbar, torch.float64, (X, M, n))
+            _check_dev("theta", theta, torch.complex128, (nw, M, n))
+            info = sd.get("info")
+            if info is not None:
+                _check_dev("info", info, torch.int32, (nw,))
+            energy = sd.get("energy")
+            if energy is None:
+                energy = torch.empty((nw, 2), dtype=torch.complex128, device=theta.device)
+            _check_dev("energy", energy, torch.complex128, (nw, 2))
+            self.systems.append({"lbar": lbar, "theta": theta, "info": info, "energy": energy})
+            arr[k] = _System(M, n, X, nw, _ptr(lbar), _ptr(theta), _ptr(info), _ptr(energy))
+        ch = None
+        if chunk is not None:
+            ch = np.ascontiguousarray(chunk, dtype=np.int64)
+            assert ch.shape == (len(systems),)
+        h = ctypes.c_void_p()
+        ctx._check(ctx._lib.lo_batch_create(ctx.handle, len(systems), ctypes.addressof(arr), LO_FP32,
+                                            ch.ctypes.data if ch is not None else None, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def energies(self):
+        return [sd["energy"] for sd in self.systems]
+
+    def info(self):
+        nitems = ctypes.c_int64()
+        ch = np.zeros(len(self.systems), dtype=np.int64)
+        self.ctx._check(self.ctx._lib.lo_batch_info(self._h, ctypes.byref(nitems), ch.ctypes.data))
+        return {"items": nitems.value, "chunk": ch}
+
+    def execute(self):
+        self.ctx._check(self.ctx._lib.lo_batch_execute(self.ctx.handle, self._h))
+
+    def capture(self, repeats: int):
+        self.ctx._check(self.ctx._lib.lo_batch_capture(self.ctx.handle, self._h, int(repeats)))
+
+    def replay(self):
+        self.ctx._check(self.ctx._lib.lo_batch_replay(self.ctx.handle, self._h))
+
+    def close(self):
+        if self._h:
+            load().lo_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:
@@ -286,3 +380,50 @@ class Context:
         self._check(self._lib.local_energy_lo(self._h, factors.handle, nw, _ptr(theta), _ptr(info), int(precision),
                                               int(flags), _ptr(energy)))
         return energy
+
+    # -- learned residual (extension) ---------------------------------------------
+    def residual_nparam(self) -> int:
+        return int(self._lib.lo_residual_nparam())
+
+    def residual_features(self, factors: Factors, theta, x=None):
+        """x [nw][n][3] float32 from walker-major theta [nw][M][n]."""
+        import torch
+        nw = theta.shape[0]
+        _check_dev("theta", theta, torch.complex128, (nw, factors.M, factors.n_occ))
+        if x is None:
+            x = torch.empty((nw, factors.n_occ, 3), dtype=torch.float32, device=theta.device)
+        _check_dev("x", x, torch.float32, (nw, factors.n_occ, 3))
+        self._check(self._lib.lo_residual_features(self._h, factors.handle, nw, _ptr(theta), _ptr(x)))
+        return x
+
+    def residual_predict(self, params, x, precision=LO_FP32, pred=None):
+        import torch
+        nw, n, _ = x.shape
+        _check_dev("params", params, torch.float32, (self.residual_nparam(),))
+        _check_dev("x", x, torch.float32, (nw, n, 3))
+        if pred is None:
+            pred = torch.empty((nw,), dtype=torch.float64, device=x.device)
+        _check_dev("pred", pred, torch.float64, (nw,))
+        self._check(self._lib.lo_residual_predict(self._h, nw, n, _ptr(params), _ptr(x), int(precision), _ptr(pred)))
+        return pred
+
+    def residual_train_step(self, params, adam_m, adam_v, step: int, lr: float, x, target, grad=None, loss=None,
+                            pred=None):
+        import torch
+        nw, n, _ = x.shape
+        npar = self.residual_nparam()
+        _check_dev("params", params, torch.float32, (npar,))
+        _check_dev("x", x, torch.float32, (nw, n, 3))
+        _check_dev("target", target, torch.float64, (nw,))
+        if step > 0:
+            _check_dev("adam_m", adam_m, torch.float32, (npar,))
+            _check_dev("adam_v", adam_v, torch.float32, (npar,))
+        if grad is not None:
+            _check_dev("grad", grad, torch.float32, (npar,))
+        if loss is not None:
+            _check_dev("loss", loss, torch.float64, (1,))
+        if pred is not None:
+            _check_dev("pred", pred, torch.float64, (nw,))
+        self._check(self._lib.lo_residual_train_step(self._h, nw, n, _ptr(params), _ptr(adam_m), _ptr(adam_v),
+                                                     int(step), float(lr), _ptr(x), _ptr(target), _ptr(grad),
+                                                     _ptr(loss), _ptr(pred)))

@@ -199,6 +199,20 @@ CHAIN_PRECISION = ChainConfig("chain-M500-n48-w1024", 500, 48, 1024, 1e-5, 0.2, 
 CONFIGS = {c.name: c for c in (CHAIN_SMALL, CHAIN_POLYACENE, CHAIN_PRECISION)}
 
 
+def batch_configs(count: int = 8, seed: int = 4004, m_range=(100, 600), w_range=(64, 512)) -> list:
+    """Ragged set of chain systems: M uniform in m_range, n = M // 7 orbitals
+    per spin, Cholesky to 1e-5, walkers uniform in w_range, noise 0.2; one
+    seed per system drawn from `seed`."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        M = int(rng.integers(m_range[0], m_range[1] + 1))
+        nw = int(rng.integers(w_range[0], w_range[1] + 1))
+        sd = int(rng.integers(0, 2 ** 31 - 1))
+        out.append(ChainConfig("chain-M%d-n%d-w%d" % (M, M // 7, nw), M, M // 7, nw, 1e-5, 0.2, sd, epsilons=()))
+    return out
+
+
 @dataclasses.dataclass
 class ChainSystem:
     config: ChainConfig

@@ -40,14 +40,18 @@ def test_validation_errors_need_no_device(lib):
         assert lib.green_theta(None, 4, 2, 1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert lib.green_theta(h, 0, 2, 1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert lib.green_theta(h, 4, 5, 1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL   # n > M
-        assert lib.green_theta(h, 100, 65, 1, fake, fake, fake, None, fake, 0) == L.LO_EUNSUPPORTED
+        assert lib.green_theta(h, 100, 97, 1, fake, fake, fake, None, fake, 0) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_full(h, 100, 65, 3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_full(h, 100, 97, 3, 4, fake, fake, None, L.LO_FP32, 0, fake) == L.LO_EUNSUPPORTED
         assert lib.green_theta(h, 8, 2, -1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert lib.green_theta(h, 8, 2, 3, None, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert b"null" in lib.lo_last_error(h)
         assert lib.green_theta(h, 8, 2, 0, None, None, None, None, None, 0) == L.LO_OK   # empty batch
         assert lib.green_theta(h, 8, 2, 3, fake, fake, fake, None, fake, 6) == L.LO_EINVAL  # unknown flag
         assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, 2, fake) == L.LO_EINVAL
-        assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP32, 0, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, 7, 0, fake) == L.LO_EINVAL   # precision
+        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP32, 1, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_lo(h, fake, 4, fake, None, 9, 0, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP64, 7, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, -3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, 3, 0, None, None, None, L.LO_FP64, 0, None) == L.LO_OK
