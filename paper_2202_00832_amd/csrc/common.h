@@ -16,6 +16,19 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 
 __device__ __forceinline__ d4 d4zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
 
+// v_mfma_f64_4x4x4f64 (four independent 4x4x4 blocks per instruction).  Lane
+// convention, read off one-hot inputs on the device:
+//   lane l supplies A_b[l % 4][l / 16] and B_b[l / 16][l % 4] of block b = (l / 4) % 4,
+//   and receives D_b[l / 16][l % 4].
+// Four of them with A rows 4q + l % 4 (q = 0..3) and B = the 16x16x4 B
+// fragment (B[l / 16][l % 16]) leave accumulator q of lane l holding
+// D[4q + l / 16][l % 16]: the same element as element q of the 16x16x4
+// accumulator.  On this chip the 4x4x4 form sustains close to the FP64 peak
+// from one wave per SIMD, the 16x16x4 form about two thirds of it.
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
 // Complex helpers on double2 (x = re, y = im).
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

@@ -18,7 +18,8 @@ namespace lofqmc {
 
 // Pass 1: tile = up to LO_TILE_ROWS (64) output rows of one orbital o x 64
 // walkers, eight waves: wave (q, h) owns row block q (16 rows) against walker
-// half h (two 16-walker blocks, real and imaginary part: four accumulators),
+// half h (two 16-walker blocks, real and imaginary part), on the FP64 4x4x4
+// MFMA (four instructions per 16x16 block and K-step),
 // so a workgroup needs few registers and several fit on a compute unit (FP64
 // MFMA needs more than one wave per SIMD to stay busy).  Per 16-row slab of r
 // the factor rows (gathered through rowidx) and Q_o of the 64 walkers are
@@ -62,9 +63,9 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
   const int nrows = tile_nrows[t];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int q = wv & 3, hw = wv >> 2;
+  const int qb = wv & 3, hw = wv >> 2;
   const int lr = lane & 15, lk = lane >> 4;
-  const bool active = 16 * q < nrows;
+  const bool active = 16 * qb < nrows;
   const double2* tho = theta + o * so;
 
   // staging: A = nrows x 16 doubles (each row 128 contiguous bytes), B = 16 x 64 complex
@@ -109,9 +110,13 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
     }
   };
 
-  d4 acc[4];   // [walker block * 2 + part]
+  // acc[q][c]: rows 4q + lk of the block, walker column c (half h = c / 2,
+  // part = c % 2) -- one FP64 4x4x4 accumulator each (see mfma4)
+  double acc[4][4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = d4zero();
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[q][c] = 0.0;
   const int nchunk = (M + 15) / 16;
   load(0);
   store(0);
@@ -123,29 +128,32 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const int rr = 4 * s4 + lk;
-        const double a = sA[buf][16 * q + lr][rr];
         const double2 b0 = sB[buf][rr][32 * hw + lr];
         const double2 b1 = sB[buf][rr][32 * hw + 16 + lr];
-        acc[0] = mfma16(a, b0.x, acc[0]);
-        acc[1] = mfma16(a, b0.y, acc[1]);
-        acc[2] = mfma16(a, b1.x, acc[2]);
-        acc[3] = mfma16(a, b1.y, acc[3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double a = sA[buf][16 * qb + 4 * q + (lane & 3)][rr];
+          acc[q][0] = mfma4(a, b0.x, acc[q][0]);
+          acc[q][1] = mfma4(a, b0.y, acc[q][1]);
+          acc[q][2] = mfma4(a, b1.x, acc[q][2]);
+          acc[q][3] = mfma4(a, b1.y, acc[q][3]);
+        }
       }
     }
     if (c + 1 < nchunk) store(buf ^ 1);
     __syncthreads();
   }
-  // D[row][walker]: lane holds rows 4v + lk of the block, walker 16 * half + lr
+  // lane holds rows 4q + lk of the block, walker 16 * half + lr
   if (active) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int64_t w = w0 + 32 * hw + 16 * h + lr;
       if (w < nw) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int lrow = 16 * q + 4 * v + lk;
+        for (int q = 0; q < 4; ++q) {
+          const int lrow = 16 * qb + 4 * q + lk;
           if (lrow < nrows)
-            qbar[(size_t)(row0 + lrow) * nw + w] = make_double2(acc[2 * h][v], acc[2 * h + 1][v]);
+            qbar[(size_t)(row0 + lrow) * nw + w] = make_double2(acc[q][2 * h], acc[q][2 * h + 1]);
         }
       }
     }
