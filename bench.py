@@ -139,12 +139,146 @@ def precision_study(torch, lofqmc, synth, steps):
         e = ctx.local_energy_full(lbar, theta, info, precision=p).cpu().numpy()
         d = np.abs(e.sum(axis=1) - ref.sum(axis=1))
         dk = np.abs(e[:, 1] - ref[:, 1])
+        rel = d / np.maximum(np.abs(ref.sum(axis=1)), 1e-300)
         r = {"ms_per_call": round(tot / steps, 3), "walker_energies_per_s": round(nw / (tot / steps * 1e-3), 1),
              "max_abs_dE_Ha": float(d.max()), "mean_abs_dE_Ha": float(d.mean()),
+             "p99_abs_dE_Ha": float(np.percentile(d, 99)), "max_rel_dE": float(rel.max()),
              "max_abs_dEK_Ha": float(dk.max()),
              "kernel_us": {k: round(t / c * 1e3, 1) for k, (c, t) in kern.items()}}
         out["runs"][names[p]] = r
         log("precision %s: %.3f ms/call, max |dE| %.2e Ha" % (names[p], r["ms_per_call"], r["max_abs_dE_Ha"]))
+    ctx.close()
+    return out
+
+
+def batch_study(torch, lofqmc, synth, evaluations=50):
+    """Eight chain systems of uneven size (M uniform in [100, 600], n = M // 7,
+    64-512 walkers): FP32 full-route energies of all systems per evaluation,
+    one persistent exchange launch per evaluation, `evaluations` evaluations
+    captured in one HIP graph; against the same evaluations as one
+    local_energy_full call per system."""
+    from paper_2202_00832_amd import autotune
+    cfgs = synth.batch_configs()
+    log("batching: %s" % ", ".join(c.name for c in cfgs))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    ctx = lofqmc.Context()
+    systems, total_w = [], 0
+    for c in cfgs:
+        sysm = synth.make_system(c)
+        lbar = ctx.build_half_rotated_chol(dev(sysm.chol), dev(sysm.trial))
+        theta, _, info = ctx.green_theta(dev(sysm.trial), dev(sysm.walkers))
+        systems.append({"lbar": lbar, "theta": theta, "info": info})
+        total_w += c.nw
+        del sysm
+    torch.cuda.synchronize()
+    tuned = autotune.tune(ctx, systems, factors=(0.5, 2.0), reps=2, log=log)
+    b = lofqmc.Batch(ctx, systems, tuned["chunk"])
+    b.capture(evaluations)
+    b.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / evaluations
+    # the same work as separate calls, one per system and evaluation
+    outs = [torch.empty((sd["theta"].shape[0], 2), dtype=torch.complex128, device="cuda") for sd in systems]
+    for sd, o in zip(systems, outs):
+        ctx.local_energy_full(sd["lbar"], sd["theta"], sd["info"], o, precision=lofqmc.LO_FP32)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(evaluations):
+        for sd, o in zip(systems, outs):
+            ctx.local_energy_full(sd["lbar"], sd["theta"], sd["info"], o, precision=lofqmc.LO_FP32)
+    e1.record()
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1) / evaluations
+    maxdiff = max(float((a - o).abs().max()) for a, o in zip(b.energies, outs))
+    info = b.info()
+    b.close()
+    ctx.close()
+    out = {"systems": [c.name for c in cfgs], "walkers": total_w, "evaluations_per_graph": evaluations,
+           "work_items": int(info["items"]), "chunk": [int(x) for x in info["chunk"]],
+           "autotune_ms": {"default": round(tuned["default_ms"], 3), "tuned": round(tuned["ms"], 3),
+                           "trials": len(tuned["trials"])},
+           "graph_ms_per_evaluation": round(graph_ms, 3),
+           "walker_energies_per_s": round(total_w / (graph_ms * 1e-3), 1),
+           "separate_calls_ms_per_evaluation": round(seq_ms, 3),
+           "max_abs_diff_vs_separate_calls_Ha": maxdiff}
+    log("batching: graph %.3f ms/eval (%.0f walker-energies/s), separate calls %.3f ms/eval"
+        % (graph_ms, out["walker_energies_per_s"], seq_ms))
+    return out
+
+
+def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, steps=2000):
+    """Learned correction of the LO energy on the 400-site chain at eps: walker
+    pairs (E_full, E_LO) along random walks from the trial, training on the
+    GPU, held-out error with and without the correction (the held-out pairs
+    are the last steps of the walks), and the checked corrected-LO
+    throughput."""
+    from paper_2202_00832_amd import residual as RES
+    cfg = synth.CHAIN_POLYACENE
+    base = synth.make_system(cfg, nw=1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    ctx = lofqmc.Context()
+    trial_d = dev(base.trial)
+    lbar = ctx.build_half_rotated_chol(dev(base.chol), trial_d)
+    f = ctx.build_lo_factors(lbar, eps)
+    rng = np.random.default_rng(2025)
+    # walker pairs along random walks phi <- QR(phi + 0.02 (Z1 + i Z2)) from the
+    # trial (a stand-in for the propagation), one pair per walker and step
+    nb = 512
+    phi = np.repeat(base.trial[None].astype(np.complex128), nb, axis=0)
+    X, Y, thetas = [], [], []
+    t0 = time.perf_counter()
+    for start in range(0, n_train + n_test, nb):
+        noise = 0.02 * (rng.standard_normal(phi.shape) + 1j * rng.standard_normal(phi.shape))
+        phi = np.stack([np.linalg.qr(p_ + z)[0] for p_, z in zip(phi, noise)])
+        theta, _, info = ctx.green_theta(trial_d, dev(phi))
+        ef = ctx.local_energy_full(lbar, theta, info).sum(dim=1)
+        el = ctx.local_energy_lo(f, theta, info).sum(dim=1)
+        X.append(ctx.residual_features(f, theta))
+        Y.append(((ef - el).real * RES.MHA).contiguous())
+        if start >= n_train:
+            thetas.append(theta)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    x = torch.cat(X)
+    y = torch.cat(Y)
+    xtr, ytr = x[:n_train].contiguous(), y[:n_train].contiguous()
+    xte, yte = x[n_train:].contiguous(), y[n_train:].contiguous()
+    model = RES.ResidualModel(ctx, RES.init_params(xtr.cpu().numpy(), ctx.residual_nparam(), seed=0))
+    t0 = time.perf_counter()
+    losses = model.train(xtr, ytr, steps=steps, lr=1e-3, batch=1024)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    pred = model.predict_mha(xte, lofqmc.LO_BF16)
+    yh, ph = yte.cpu().numpy(), pred.cpu().numpy()
+    est = RES.CorrectedLO(ctx, f, lbar, model, bound_mha=0.2, check_every=10, check_walkers=64)
+    th = thetas[0]
+    est(th)   # first call checks
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        est(th)
+    e1.record()
+    torch.cuda.synchronize()
+    corr_ms = e0.elapsed_time(e1) / reps
+    out = {"workload": cfg.name, "epsilon": eps, "train_pairs": n_train, "test_pairs": n_test,
+           "pair_generation_s": round(gen_s, 2), "train_steps": steps, "train_s": round(train_s, 2),
+           "loss_first_last_mHa2": [float(losses[0]), float(np.mean(losses[-50:]))],
+           "heldout_rms_mHa": {"plain_lo": float(np.sqrt(np.mean(yh ** 2))),
+                               "corrected": float(np.sqrt(np.mean((yh - ph) ** 2)))},
+           "heldout_max_abs_mHa": {"plain_lo": float(np.abs(yh).max()), "corrected": float(np.abs(yh - ph).max())},
+           "check": est.last_check,
+           "corrected_lo_ms_per_call_512_walkers": round(corr_ms, 3)}
+    log("residual: held-out RMS %.3f -> %.3f mHa, mode %s" % (out["heldout_rms_mHa"]["plain_lo"],
+                                                             out["heldout_rms_mHa"]["corrected"], est.mode))
+    f.close()
     ctx.close()
     return out
 
@@ -181,7 +315,11 @@ def main():
     ap.add_argument("--eps", type=str, default="",
                     help="comma-separated LO thresholds to run instead of the workload's sweep")
     ap.add_argument("--no-precision", action="store_true",
-                    help="skip the reduced-precision full-route study on the 500-site chain")
+                    help="skip the reduced-precision study on the 500-site chain")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the multi-system batching study (8 chain systems, captured graph)")
+    ap.add_argument("--no-residual", action="store_true",
+                    help="skip the learned-residual study")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -319,6 +457,12 @@ def main():
     prec = None
     if not args.no_precision:
         prec = precision_study(torch, lofqmc, synth, max(2, min(args.steps, 5)))
+    batch = None
+    if not args.no_batch:
+        batch = batch_study(torch, lofqmc, synth)
+    resid = None
+    if not args.no_residual:
+        resid = residual_study(torch, lofqmc, synth)
 
     log("CPU reference baseline (%d walkers)" % args.cpu_sample)
     cpu = cpu_baseline(cfg, system, eps_h, args.cpu_sample)
@@ -338,6 +482,8 @@ def main():
         "roofline": roofline,
         "kernels": per_kernel,
         "mixed_precision": prec,
+        "batching": batch,
+        "learned_residual": resid,
         "cpu_baseline": cpu,
         "setup_s": {"half_rotation": round(t_half, 3)},
     }

@@ -7,10 +7,9 @@
 //      prefetched two slabs ahead.  One workgroup per walker.
 //   2. invert_kernel: in-place Gauss-Jordan exchange with partial pivoting
 //      (largest |re|+|im| among the rows not yet used as pivots, compared to
-//      46 bits, lowest row on ties), 4x4 complex register blocks per thread,
-//      two barriers per step, the pivot argmax a DPP max inside 16-lane rows.
-//      Gives O^{-1}, log det O and the zero-pivot index.  Needs little LDS,
-//      so several walkers share a compute unit.
+//      45 bits, lowest row on ties); one wave per 16-column panel with a row
+//      per lane, one barrier per elimination step.  Gives O^{-1}, log det O
+//      and the zero-pivot index.
 //   3. apply_kernel: theta = phi O^{-1} on MFMA with three real products per
 //      complex block (re = P1 - P2, im = P3 - P1 - P2 with P1 = a_re b_re,
 //      P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im)); one workgroup per
@@ -137,150 +136,151 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, const double
 }
 
 // ---------------------------------------------------------------------------
-// 2. O_w -> O_w^{-1} in place (padded rows/columns zero), log det, info
+// 2. O_w -> O_w^{-1} in place (padded rows/columns zero), log det, info.
+//    Wave q owns the 16 columns 16q .. 16q+15 of every row; lane l holds rows
+//    l and l + 64.  Step k: the wave owning column k picks the pivot row (its
+//    column is already updated), publishes the column through LDS, and after
+//    one barrier every wave reads the multipliers of its rows and the pivot
+//    row of its own columns (written by its lane p) from LDS, and updates.
 // ---------------------------------------------------------------------------
 template <int NB>
-__global__ __launch_bounds__(256) void invert_kernel(int n, double2* __restrict__ O,
-                                                     double2* __restrict__ logov, int* __restrict__ info) {
+__global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restrict__ O,
+                                                          double2* __restrict__ logov, int* __restrict__ info) {
   constexpr int NP = 16 * NB;
-  __shared__ double2 sColBuf[2][NP];
-  __shared__ double2 sRow[NP];
+  constexpr int RPL = (NP + 63) / 64;        // rows per lane
+  __shared__ double2 sCol[2][NP];
   __shared__ int sPiv[NP];
   __shared__ int sPinv[NP];
   __shared__ double2 sPivV[NP];
+  __shared__ double2 sRowW[NB][16];
+  __shared__ int sZero;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int lr = lane & 15;
   const size_t w = blockIdx.x;
   double2* Ow = O + w * (size_t)NP * NP;
 
-  const int ty = tid >> 4, tx = tid & 15;   // owns rows ty+16a, cols tx+16b
-  double2 e[NB][NB];
+  double2 e[RPL][16];
+  bool used[RPL];
 #pragma unroll
-  for (int a = 0; a < NB; ++a)
+  for (int t = 0; t < RPL; ++t) {
+    const int row = lane + 64 * t;
+    used[t] = row >= n;   // padding rows are never pivots
 #pragma unroll
-    for (int b = 0; b < NB; ++b) e[a][b] = Ow[(ty + 16 * a) * NP + tx + 16 * b];
-  if (tx == 0) {
-#pragma unroll
-    for (int a = 0; a < NB; ++a) sColBuf[0][ty + 16 * a] = e[a][0];
+    for (int j = 0; j < 16; ++j) e[t][j] = row < NP ? Ow[(size_t)row * NP + 16 * wv + j] : make_double2(0.0, 0.0);
   }
+  if (tid == 0) sZero = 0;
   __syncthreads();
 
-  // lane l tracks rows (l & 15) + 16 m, m < NB, as bit m of `used`
-  unsigned used = 0u;
-#pragma unroll
-  for (int m = 0; m < NB; ++m)
-    if ((lr + 16 * m) >= n) used |= 1u << m;
   int zero = 0;
-  for (int k = 0; k < n; ++k) {
-    const double2* col = sColBuf[k & 1];
-    // pivot search, identical in every 16-lane row of every wave: key =
-    // |re|+|im| (45 leading bits, monotone as an integer) with 127 - row in the
-    // low 6 bits; max over the lane's NB rows, then over the 16 lanes (DPP)
-    unsigned long long key = 0ull;
+  for (int kb = 0; kb < NB; ++kb) {
+    // fixed trip count (fully unrolled, so e[][c] stays in registers); the
+    // step conditions are uniform, so the barrier inside is reached by all
 #pragma unroll
-    for (int m = 0; m < NB; ++m) {
-      const double2 cv = col[lr + 16 * m];
-      const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(cv.x) + fabs(cv.y));
-      const unsigned long long km =
-          (used >> m & 1u) ? 0ull : ((mb & ~127ull) | (unsigned long long)(127 - (lr + 16 * m)));
-      key = km > key ? km : key;
-    }
-    key = row16_max_u64(key);
-    const int p = __builtin_amdgcn_readfirstlane(127 - (int)(key & 127ull));
-    if ((key >> 7) == 0ull) { zero = k + 1; break; }
-    if ((p & 15) == lr) used |= 1u << (p >> 4);
-    const double2 piv = col[p];                 // uniform LDS address: broadcast read
-    // 1/piv = conj(piv) / |piv|^2 (O is an overlap of normalised orbitals, far
-    // from the over/underflow range of |piv|^2)
-    const double rn = 1.0 / (piv.x * piv.x + piv.y * piv.y);
-    const double2 inv = make_double2(piv.x * rn, -piv.y * rn);
-    if (tid == 0) {
-      sPiv[k] = p;
-      sPivV[k] = piv;
-    }
-    if (ty == (p & 15)) {
+    for (int c = 0; c < 16; ++c) {
+      const int k = 16 * kb + c;
+      if (k >= n || zero) continue;
+      if (wv == kb) {
+        // pivot: largest |re|+|im| (45 leading bits) among unused rows, lowest row on ties
+        unsigned long long key = 0ull;
 #pragma unroll
-      for (int a = 0; a < NB; ++a)
-        if (a == (p >> 4)) {
-#pragma unroll
-          for (int b = 0; b < NB; ++b) sRow[tx + 16 * b] = cmul(e[a][b], inv);
+        for (int t = 0; t < RPL; ++t) {
+          const int row = lane + 64 * t;
+          const double2 v = e[t][c];
+          const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(v.x) + fabs(v.y));
+          const unsigned long long kt = used[t] ? 0ull : ((mb & ~127ull) | (unsigned long long)(127 - row));
+          key = kt > key ? kt : key;
+          if (row < NP) sCol[k & 1][row] = v;
         }
-    }
-    __syncthreads();
-    // exchange step on pivot (p, k); all LDS reads issued first.  With
-    // c'_i = A[i][k] + [i == p] every element takes the same update
-    //   A[i][j] -= c'_i R[j],  R[j] = A[p][j] / pivot,
-    // which gives A[i][j] - A[i][k] R[j] off the pivot row and -R[j] on it
-    // (the exchange operator); column k is then overwritten by its owners
-    // with A[i][k] / pivot (1 / pivot on the pivot row).
-    double2 cik[NB], rpj[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) cik[a] = col[ty + 16 * a];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) rpj[b] = sRow[tx + 16 * b];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      double2 c = cik[a];
-      c.x += ((ty + 16 * a) == p) ? 1.0 : 0.0;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const double2 r = rpj[b];
-        double2 v = e[a][b];
-        v.x = fma(-c.x, r.x, fma(c.y, r.y, v.x));
-        v.y = fma(-c.x, r.y, fma(-c.y, r.x, v.y));
-        e[a][b] = v;
-      }
-    }
-    if (tx == (k & 15)) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        if (b == (k >> 4)) {
-#pragma unroll
-          for (int a = 0; a < NB; ++a) {
-            const double2 cc = ((ty + 16 * a) == p) ? make_double2(1.0, 0.0) : cik[a];
-            e[a][b] = cmul(cc, inv);
+        key = wave_max_u64(key);
+        if (lane == 0) {
+          if ((key >> 7) == 0ull) {
+            sZero = k + 1;
+          } else {
+            sPiv[k] = 127 - (int)(key & 127ull);
           }
         }
-    }
-    // the owners of column k+1 publish it for the next step
-    if (k + 1 < n && tx == ((k + 1) & 15)) {
+      }
+      __syncthreads();
+      zero = sZero;
+      if (zero) continue;
+      const int p = sPiv[k];
+      const double2 piv = sCol[k & 1][p];
+      const double rn = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+      const double2 inv = make_double2(piv.x * rn, -piv.y * rn);
+      if (wv == 0 && lane == 0) sPivV[k] = piv;
+      // pivot row (own 16 columns): lane p % 64 writes it to this wave's LDS
+      // slot and every lane of the wave reads it back; a wavefront-scope
+      // release/acquire pair around a wave barrier orders the two (without
+      // it the compiler may let the other lanes read before the write)
+      const int pl = p & 63, pt = p >> 6;
+      if (lane == pl) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-        if (b == ((k + 1) >> 4)) {
+        for (int j = 0; j < 16; ++j) sRowW[wv][j] = (RPL > 1 && pt == 1) ? e[RPL - 1][j] : e[0][j];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double2 apj[16];
 #pragma unroll
-          for (int a = 0; a < NB; ++a) sColBuf[(k + 1) & 1][ty + 16 * a] = e[a][b];
+      for (int j = 0; j < 16; ++j) apj[j] = sRowW[wv][j];
+      // uniform exchange update A[i][j] -= m_i A[p][j] with m_i = (A[i][k] + [i == p]) / pivot,
+      // which leaves -A[p][j] / pivot on the pivot row; the owner of column k then
+      // writes A[i][k] / pivot (1 / pivot on row p)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = lane + 64 * t;
+        double2 ci = row < NP ? sCol[k & 1][row] : make_double2(0.0, 0.0);
+        const double2 cc = row == p ? make_double2(1.0, 0.0) : ci;
+        ci.x += row == p ? 1.0 : 0.0;
+        const double2 mi = cmul(ci, inv);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double2 v = e[t][j];
+          v.x = fma(-mi.x, apj[j].x, fma(mi.y, apj[j].y, v.x));
+          v.y = fma(-mi.x, apj[j].y, fma(-mi.y, apj[j].x, v.y));
+          e[t][j] = v;
         }
+        if (wv == kb) e[t][c] = cmul(cc, inv);
+        if (row == p) used[t] = true;
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // un-permute: O^{-1}[k][p_m] = R[p_k][m]; padded rows/columns stay zero
   if (!zero && tid < n) sPinv[sPiv[tid]] = tid;
   __syncthreads();
   if (!zero) {
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      const int i = ty + 16 * a;
+    for (int t = 0; t < RPL; ++t) {
+      const int i = lane + 64 * t;
+      if (i < n) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int m = tx + 16 * b;
-        if (i < n && m < n) Ow[sPinv[i] * NP + sPiv[m]] = e[a][b];
+        for (int j = 0; j < 16; ++j) {
+          const int m = 16 * wv + j;
+          if (m < n) Ow[(size_t)sPinv[i] * NP + sPiv[m]] = e[t][j];
+        }
       }
     }
   }
   if (wv == 0) {
-    // log det O = sum_k log(pivot_k) + i pi (parity of k -> p_k)
+    // log det O = sum_k log(pivot_k) + i pi * parity of the permutation k -> p_k;
+    // the parity is that of its number of inversions, counted by all lanes
     double la = 0.0, ar = 0.0;
+    int inv_count = 0;
     if (!zero) {
       for (int k = lane; k < n; k += 64) {
         const double2 pv = sPivV[k];
         la += log(hypot(pv.x, pv.y));
         ar += atan2(pv.y, pv.x);
+        const int pk = sPiv[k];
+        for (int j = k + 1; j < n; ++j) inv_count += sPiv[j] < pk ? 1 : 0;
       }
     }
     la = wave_sum_lane0(la);
     ar = wave_sum_lane0(ar);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) inv_count += __shfl_down(inv_count, off, 64);
     if (lane == 0) {
       info[w] = zero;
       if (logov) {
@@ -288,18 +288,7 @@ __global__ __launch_bounds__(256) void invert_kernel(int n, double2* __restrict_
         if (zero) {
           ld = make_double2(__builtin_nan(""), __builtin_nan(""));
         } else {
-          int cycles = 0;
-          unsigned long long seen[2] = {0ull, 0ull};   // n <= 128
-          for (int s2 = 0; s2 < n; ++s2) {
-            if (seen[s2 >> 6] >> (s2 & 63) & 1ull) continue;
-            ++cycles;
-            int c = s2;
-            while (!(seen[c >> 6] >> (c & 63) & 1ull)) {
-              seen[c >> 6] |= 1ull << (c & 63);
-              c = sPiv[c];
-            }
-          }
-          double im = ar + ((n - cycles) & 1 ? M_PI : 0.0);
+          double im = ar + ((inv_count & 1) ? M_PI : 0.0);
           im = remainder(im, 2.0 * M_PI);  // (-pi, pi]
           if (im <= -M_PI) im += 2.0 * M_PI;
           ld = make_double2(la, im);
@@ -312,7 +301,8 @@ __global__ __launch_bounds__(256) void invert_kernel(int n, double2* __restrict_
 
 // ---------------------------------------------------------------------------
 // 3. theta_w = phi_w O_w^{-1}; one 512-thread workgroup per walker, O_w^{-1}
-//    staged once in LDS, wave q takes the 16-row blocks q, q+8, ...
+//    staged once in LDS, wave (q, h) takes the 16-row blocks q, q+4, ...
+//    against half h of the column blocks
 // ---------------------------------------------------------------------------
 template <int NB>
 __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, const double2* __restrict__ phi,
@@ -340,34 +330,47 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, co
   const double2* ph = phi + w * (size_t)M * n;
   const bool bad = info[w] != 0;
   const double nan = __builtin_nan("");
+  // wave (q, h): 16-row blocks q, q+4, ... against the column blocks of half
+  // h (JH blocks each), which keeps the accumulators to 3 * JH 16x16 blocks
+  constexpr int JH = (NB + 1) / 2;
+  const int q = wv >> 1, hf = wv & 1;
   const int nrb = (M + 15) / 16;
-  for (int rb = wv; rb < nrb; rb += 8) {
+  for (int rb = q; rb < nrb; rb += 4) {
     const int r = 16 * rb + lr;
-    d4 P1[NB], P2[NB], P3[NB];
+    d4 P1[JH], P2[JH], P3[JH];
 #pragma unroll
-    for (int J = 0; J < NB; ++J) { P1[J] = d4zero(); P2[J] = d4zero(); P3[J] = d4zero(); }
+    for (int J = 0; J < JH; ++J) { P1[J] = d4zero(); P2[J] = d4zero(); P3[J] = d4zero(); }
+    // K-steps in groups of four (bounded prefetch of phi)
+    for (int kg = 0; kg < (ksteps + 3) / 4; ++kg) {
+      double2 av[4];
 #pragma unroll
-    for (int ks = 0; ks < C::NKS; ++ks) {
-      if (ks < ksteps) {
-        const int kk = 4 * ks + lk;
-        const double2 av = (r < M && kk < n) ? ph[(size_t)r * n + kk] : make_double2(0.0, 0.0);
-        const double as = av.x + av.y;
+      for (int u = 0; u < 4; ++u) {
+        const int kk = 16 * kg + 4 * u + lk;
+        av[u] = (r < M && kk < n) ? ph[(size_t)r * n + kk] : make_double2(0.0, 0.0);
+      }
 #pragma unroll
-        for (int J = 0; J < NB; ++J) {
-          const double2 bv = sB[kk * NP + 16 * J + lr];
-          P1[J] = mfma16(av.x, bv.x, P1[J]);
-          P2[J] = mfma16(av.y, bv.y, P2[J]);
-          P3[J] = mfma16(as, bv.x + bv.y, P3[J]);
+      for (int u = 0; u < 4; ++u) {
+        const int kk = 16 * kg + 4 * u + lk;
+        const double as = av[u].x + av[u].y;
+#pragma unroll
+        for (int J = 0; J < JH; ++J) {
+          const int JJ = hf * JH + J;
+          if (JJ < NB) {
+            const double2 bv = kk < NP ? sB[kk * NP + 16 * JJ + lr] : make_double2(0.0, 0.0);
+            P1[J] = mfma16(av[u].x, bv.x, P1[J]);
+            P2[J] = mfma16(av[u].y, bv.y, P2[J]);
+            P3[J] = mfma16(as, bv.x + bv.y, P3[J]);
+          }
         }
       }
     }
 #pragma unroll
-    for (int J = 0; J < NB; ++J) {
-      const int j = 16 * J + lr;
+    for (int J = 0; J < JH; ++J) {
+      const int j = 16 * (hf * JH + J) + lr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * rb + 4 * v + lk;
-        if (row < M && j < n) {
+        if (hf * JH + J < NB && row < M && j < n) {
           const double re = P1[J][v] - P2[J][v];
           const double im = P3[J][v] - P1[J][v] - P2[J][v];
           const double2 val = bad ? make_double2(nan, nan) : make_double2(re, im);
@@ -396,7 +399,7 @@ static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, const doubl
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   prof_mark(prof, "invert_kernel");
-  hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nw), dim3(256), 0, s, n, O, (double2*)logov, info);
+  hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nw), dim3(64 * NB), 0, s, n, O, (double2*)logov, info);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t grid = 64 * ((nw + 63) / 64);

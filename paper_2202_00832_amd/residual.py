@@ -10,8 +10,11 @@ while a periodic full evaluation of a walker sample confirms that the
 corrected energies stay within a stated bound; otherwise the energies fall
 back to plain LO (or to the full route when plain LO also misses its gate).
 
-Host code here only sequences library calls and compares a handful of
-numbers; every array operation runs in the library's kernels.
+Host code here sequences library calls and compares a handful of numbers;
+the network's forward, backward and update run in the library's kernels.
+The standardisation of the target vector, the minibatch gathers and the
+addition of the correction to E_LO are torch element-wise operations on
+[walker]-sized vectors.
 """
 from __future__ import annotations
 
@@ -39,7 +42,12 @@ def init_params(x_host: np.ndarray, nparam: int, seed: int = 0) -> np.ndarray:
 
 
 class ResidualModel:
-    """Parameters and Adam state of the network, on the device."""
+    """Parameters and Adam state of the network, on the device.
+
+    The network is trained on standardised targets (t - mean) / scale, with the
+    mean and scale of the training targets; predictions are mapped back, so
+    the model works in mHa at any size of the dropped energy.
+    """
 
     def __init__(self, ctx: lofqmc.Context, params_host: np.ndarray):
         import torch
@@ -48,25 +56,33 @@ class ResidualModel:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.t = 0
+        self.t_mean = 0.0
+        self.t_scale = 1.0
 
     def train(self, x, target_mha, steps: int, lr: float = 1e-3, batch: int = 256, seed: int = 0):
-        """Adam on minibatches of walkers; returns the loss of every step (mHa^2)."""
+        """Adam on minibatches of walkers; returns the loss of every step
+        (mean squared error of the standardised target)."""
         import torch
         nw = x.shape[0]
+        if self.t == 0:
+            th = target_mha.cpu().numpy()
+            self.t_mean = float(th.mean())
+            self.t_scale = float(th.std()) if th.std() > 0 else 1.0
+        tstd = ((target_mha - self.t_mean) / self.t_scale).contiguous()
         g = torch.Generator(device="cpu").manual_seed(seed)
         loss = torch.zeros(1, dtype=torch.float64, device=x.device)
         losses = torch.zeros(steps, dtype=torch.float64, device=x.device)
         for k in range(steps):
             idx = torch.randperm(nw, generator=g)[:min(batch, nw)].to(x.device)
             xb = x.index_select(0, idx).contiguous()
-            tb = target_mha.index_select(0, idx).contiguous()
+            tb = tstd.index_select(0, idx).contiguous()
             self.t += 1
             self.ctx.residual_train_step(self.params, self.m, self.v, self.t, lr, xb, tb, loss=loss)
             losses[k:k + 1].copy_(loss)
         return losses.cpu().numpy()
 
     def predict_mha(self, x, precision=lofqmc.LO_BF16):
-        return self.ctx.residual_predict(self.params, x, precision)
+        return self.ctx.residual_predict(self.params, x, precision) * self.t_scale + self.t_mean
 
 
 class CorrectedLO:
