@@ -232,12 +232,12 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
     return out
 
 
-def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, steps=2000):
+def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, steps=2000, step_sigma=0.005):
     """Learned correction of the LO energy on the 400-site chain at eps: walker
-    pairs (E_full, E_LO) along random walks from the trial, training on the
-    GPU, held-out error with and without the correction (the held-out pairs
-    are the last steps of the walks), and the checked corrected-LO
-    throughput."""
+    pairs (E_full, E_LO) along 512 random walks from the trial, training on the
+    GPU, held-out error with and without the correction (the held-out pairs are
+    whole walks, so train and test come from the same distribution of walkers),
+    and the checked corrected-LO throughput."""
     from paper_2202_00832_amd import residual as RES
     cfg = synth.CHAIN_POLYACENE
     base = synth.make_system(cfg, nw=1)
@@ -247,28 +247,31 @@ def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, s
     lbar = ctx.build_half_rotated_chol(dev(base.chol), trial_d)
     f = ctx.build_lo_factors(lbar, eps)
     rng = np.random.default_rng(2025)
-    # walker pairs along random walks phi <- QR(phi + 0.02 (Z1 + i Z2)) from the
+    # walker pairs along random walks phi <- QR(phi + s (Z1 + i Z2)) from the
     # trial (a stand-in for the propagation), one pair per walker and step
     nb = 512
+    nsteps = -(-(n_train + n_test) // nb)
     phi = np.repeat(base.trial[None].astype(np.complex128), nb, axis=0)
-    X, Y, thetas = [], [], []
+    X, Y = [], []
     t0 = time.perf_counter()
-    for start in range(0, n_train + n_test, nb):
-        noise = 0.02 * (rng.standard_normal(phi.shape) + 1j * rng.standard_normal(phi.shape))
+    for _ in range(nsteps):
+        noise = step_sigma * (rng.standard_normal(phi.shape) + 1j * rng.standard_normal(phi.shape))
         phi = np.stack([np.linalg.qr(p_ + z)[0] for p_, z in zip(phi, noise)])
         theta, _, info = ctx.green_theta(trial_d, dev(phi))
         ef = ctx.local_energy_full(lbar, theta, info).sum(dim=1)
         el = ctx.local_energy_lo(f, theta, info).sum(dim=1)
         X.append(ctx.residual_features(f, theta))
         Y.append(((ef - el).real * RES.MHA).contiguous())
-        if start >= n_train:
-            thetas.append(theta)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
-    x = torch.cat(X)
-    y = torch.cat(Y)
-    xtr, ytr = x[:n_train].contiguous(), y[:n_train].contiguous()
-    xte, yte = x[n_train:].contiguous(), y[n_train:].contiguous()
+    x = torch.stack(X)          # [step][walker][orbital][3]
+    y = torch.stack(Y)          # [step][walker]
+    n_test_walks = -(-n_test // nsteps)
+    tr, te = slice(0, nb - n_test_walks), slice(nb - n_test_walks, nb)
+    xtr = x[:, tr].reshape(-1, *x.shape[2:]).contiguous()
+    ytr = y[:, tr].reshape(-1).contiguous()
+    xte = x[:, te].reshape(-1, *x.shape[2:]).contiguous()
+    yte = y[:, te].reshape(-1).contiguous()
     model = RES.ResidualModel(ctx, RES.init_params(xtr.cpu().numpy(), ctx.residual_nparam(), seed=0))
     t0 = time.perf_counter()
     losses = model.train(xtr, ytr, steps=steps, lr=1e-3, batch=1024)
@@ -277,7 +280,7 @@ def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, s
     pred = model.predict_mha(xte, lofqmc.LO_BF16)
     yh, ph = yte.cpu().numpy(), pred.cpu().numpy()
     est = RES.CorrectedLO(ctx, f, lbar, model, bound_mha=0.2, check_every=10, check_walkers=64)
-    th = thetas[0]
+    th = theta   # the last step of every walk
     est(th)   # first call checks
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -288,9 +291,10 @@ def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, s
     e1.record()
     torch.cuda.synchronize()
     corr_ms = e0.elapsed_time(e1) / reps
-    out = {"workload": cfg.name, "epsilon": eps, "train_pairs": n_train, "test_pairs": n_test,
+    out = {"workload": cfg.name, "epsilon": eps, "walks": nb, "walk_steps": nsteps, "step_sigma": step_sigma,
+           "train_pairs": int(ytr.numel()), "test_pairs": int(yte.numel()), "test_walks": n_test_walks,
            "pair_generation_s": round(gen_s, 2), "train_steps": steps, "train_s": round(train_s, 2),
-           "loss_first_last_mHa2": [float(losses[0]), float(np.mean(losses[-50:]))],
+           "loss_first_last_standardised": [float(losses[0]), float(np.mean(losses[-50:]))],
            "heldout_rms_mHa": {"plain_lo": float(np.sqrt(np.mean(yh ** 2))),
                                "corrected": float(np.sqrt(np.mean((yh - ph) ** 2)))},
            "heldout_max_abs_mHa": {"plain_lo": float(np.abs(yh).max()), "corrected": float(np.abs(yh - ph).max())},

@@ -29,20 +29,9 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-// Complex helpers on double2 (x = re, y = im).
+// Complex product on double2 (x = re, y = im).
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-// 1/z by Smith's algorithm (avoids overflow of |z|^2).
-__device__ __forceinline__ double2 crecip(double2 z) {
-  if (fabs(z.x) >= fabs(z.y)) {
-    double r = z.y / z.x, d = z.x + z.y * r;
-    return make_double2(1.0 / d, -r / d);
-  }
-  double r = z.x / z.y, d = z.y + z.x * r;
-  return make_double2(r / d, -1.0 / d);
 }
 
 // Deterministic wave64 sum: a fixed shuffle-down tree; the result is valid in
@@ -53,38 +42,38 @@ __device__ __forceinline__ double wave_sum_lane0(double v) {
   return v;
 }
 
-// Wave64 maximum of a 64-bit unsigned key, returned in every lane.  Row-local
-// butterflies use DPP (quad permutes and the row mirrors); the two cross-row
-// steps use lane shuffles.  Max is associative and exact, so all lanes agree.
-__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v, int ctrl) {
+// Wave64 maximum of a 64-bit unsigned key, returned as a wave-uniform
+// (scalar) value.  Inside each row of 16 lanes: DPP quad permutes and the two
+// row mirrors leave every lane with its row's maximum; across rows: the GFX9
+// row broadcasts (lane 15 of each row into the next row, then lane 31 into
+// rows 2 and 3) leave the maximum of all 64 lanes in lane 63, which is read
+// into scalar registers.  Max is exact and associative, so the result does
+// not depend on the order of the steps.
+__device__ __forceinline__ unsigned long long u64_of(int lo, int hi) {
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v) {
   const int lo = (int)(unsigned)(v & 0xffffffffull), hi = (int)(unsigned)(v >> 32);
-  int olo, ohi;
-  switch (ctrl) {
-    case 0: olo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false); ohi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false); break;
-    case 1: olo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false); ohi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;
-    case 2: olo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false); ohi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false); break;
-    default: olo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false); ohi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false); break;
-  }
-  const unsigned long long o = ((unsigned long long)(unsigned)ohi << 32) | (unsigned)olo;
+  // rows outside the row mask keep their own value (old operand)
+  const unsigned long long o = u64_of(__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false),
+                                      __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false));
   return o > v ? o : v;
 }
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  v = dpp_max_u64(v, 0);   // quad_perm [1,0,3,2]
-  v = dpp_max_u64(v, 1);   // quad_perm [2,3,0,1]
-  v = dpp_max_u64(v, 2);   // row_half_mirror
-  v = dpp_max_u64(v, 3);   // row_mirror
-  unsigned long long o = __shfl_xor(v, 16, 64);
-  v = o > v ? o : v;
-  o = __shfl_xor(v, 32, 64);
-  return o > v ? o : v;
+  v = dpp_max_u64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_max_u64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_max_u64<0x141, 0xF>(v);   // row_half_mirror
+  v = dpp_max_u64<0x140, 0xF>(v);   // row_mirror
+  v = dpp_max_u64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_max_u64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return u64_of(__builtin_amdgcn_readlane((int)(unsigned)(v & 0xffffffffull), 63),
+                __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63));
 }
 
-// Maximum of a 64-bit key over each row of 16 lanes (DPP only, no LDS-path
-// shuffles); every lane of the row receives its row's maximum.
-__device__ __forceinline__ unsigned long long row16_max_u64(unsigned long long v) {
-  v = dpp_max_u64(v, 0);   // quad_perm [1,0,3,2]
-  v = dpp_max_u64(v, 1);   // quad_perm [2,3,0,1]
-  v = dpp_max_u64(v, 2);   // row_half_mirror
-  v = dpp_max_u64(v, 3);   // row_mirror
-  return v;
+// Lane `lane` (wave-uniform) of a double, into scalar registers.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return __longlong_as_double((long long)u64_of(__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), lane),
+                                                 __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane)));
 }

@@ -5,15 +5,16 @@
 //      trial x complex walker -> two real 16x16 blocks per block pair);
 //      16-row slabs of phi_w and Psi_T are staged in LDS with coalesced loads,
 //      prefetched two slabs ahead.  One workgroup per walker.
-//   2. invert_kernel: in-place Gauss-Jordan exchange with partial pivoting
-//      (largest |re|+|im| among the rows not yet used as pivots, compared to
-//      45 bits, lowest row on ties); one wave per 16-column panel with a row
-//      per lane, one barrier per elimination step.  Gives O^{-1}, log det O
-//      and the zero-pivot index.
+//   2. invert_kernel: exchange (Gauss-Jordan) elimination with partial
+//      pivoting, blocked by 16-column panels: each panel is swept inside one
+//      wave (no workgroup barrier per step), the other waves then apply the
+//      panel's rank-16 update to their columns.  Gives O^{-1} in pivot order
+//      with the pivot rows, log det O and the zero-pivot index.
 //   3. apply_kernel: theta = phi O^{-1} on MFMA with three real products per
 //      complex block (re = P1 - P2, im = P3 - P1 - P2 with P1 = a_re b_re,
 //      P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im)); one workgroup per
-//      walker with O^{-1} in LDS, one wave per 16-row block.  theta is written
+//      walker with O^{-1} in LDS (put back in natural order while it is staged),
+//      one wave per 16-row block.  theta is written
 //      walker-major [w][r][j] or, with the orbital-major flag, as [j][r][w];
 //      walkers 8g .. 8g+7 then run on the same XCD so that their interleaved
 //      16-byte stores meet in one L2.
@@ -136,51 +137,67 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, const double
 }
 
 // ---------------------------------------------------------------------------
-// 2. O_w -> O_w^{-1} in place (padded rows/columns zero), log det, info.
-//    Wave q owns the 16 columns 16q .. 16q+15 of every row; lane l holds rows
-//    l and l + 64.  Step k: the wave owning column k picks the pivot row (its
-//    column is already updated), publishes the column through LDS, and after
-//    one barrier every wave reads the multipliers of its rows and the pivot
-//    row of its own columns (written by its lane p) from LDS, and updates.
+// 2. O_w -> R_w, the exchange (Gauss-Jordan) inverse in pivot order:
+//    O_w^{-1}[k][p_m] = R_w[p_k][m], with the pivot rows p_k written to perm;
+//    log det O_w and the zero-pivot index.  Wave q owns the 16 columns
+//    16q .. 16q+15 of every row (lane l holds rows l and l + 64).
+//
+//    Blocked by panels of 16 columns.  Panel b (the columns of wave b) is
+//    swept by wave b alone: for each of its columns k, the pivot row p (the
+//    largest |re|+|im| among rows not yet used, compared to 45 bits, lowest
+//    row on ties), then A[i][j] -= m_i A[p][j] on the panel's columns with
+//    m_i = (A[i][k] + [i == p]) / A[p][k], and column k set to A[i][k] / A[p][k]
+//    (1 / A[p][k] on row p).  The sixteen sweeps act on any other column as
+//    one rank-16 update: with P the panel's pivot rows, Z = A[P, J] taken
+//    before the panel and F the swept panel columns,
+//        A[:, J] <- (rows not in P ? A[:, J] : 0) - F Z,
+//    which every other wave applies to its own columns after one barrier.
 // ---------------------------------------------------------------------------
 template <int NB>
-__global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restrict__ O,
+__global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restrict__ O, int* __restrict__ perm,
                                                           double2* __restrict__ logov, int* __restrict__ info) {
   constexpr int NP = 16 * NB;
   constexpr int RPL = (NP + 63) / 64;        // rows per lane
-  __shared__ double2 sCol[2][NP];
+  constexpr int FS = 17;                     // padded row stride of the panel copy (no bank conflicts)
+  __shared__ double2 sF[2][NP * FS];         // swept panel columns, by panel parity
+  __shared__ double2 sZ[NB][16][16];         // per wave: its columns of the panel's pivot rows
   __shared__ int sPiv[NP];
-  __shared__ int sPinv[NP];
   __shared__ double2 sPivV[NP];
-  __shared__ double2 sRowW[NB][16];
-  __shared__ int sZero;
+  __shared__ int sZero[2];
+  __shared__ int sInvW[NB];                  // per panel: inversions of the pivot order
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const size_t w = blockIdx.x;
   double2* Ow = O + w * (size_t)NP * NP;
 
+  // the padded block is block-diag(O, I): the padding steps pivot on their own
+  // diagonal and leave O's block alone, so every panel runs 16 full steps
   double2 e[RPL][16];
   bool used[RPL];
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
     const int row = lane + 64 * t;
-    used[t] = row >= n;   // padding rows are never pivots
+    used[t] = row >= NP;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) e[t][j] = row < NP ? Ow[(size_t)row * NP + 16 * wv + j] : make_double2(0.0, 0.0);
+    for (int j = 0; j < 16; ++j) {
+      const int col = 16 * wv + j;
+      e[t][j] = row < NP ? Ow[(size_t)row * NP + col] : make_double2(0.0, 0.0);
+      if (row >= n && row < NP && row == col) e[t][j] = make_double2(1.0, 0.0);
+    }
   }
-  if (tid == 0) sZero = 0;
-  __syncthreads();
 
   int zero = 0;
-  for (int kb = 0; kb < NB; ++kb) {
-    // fixed trip count (fully unrolled, so e[][c] stays in registers); the
-    // step conditions are uniform, so the barrier inside is reached by all
+  for (int b = 0; b < NB; ++b) {
+    const int buf = b & 1;
+    if (wv == b) {
+      // inversions of k -> p_k: the rows still unused at step k are the later
+      // pivots, so the step adds the number of unused rows below p_k
+      int inversions = 0;
+      // sweep the panel, wave-local and branch-free (no join points, so the
+      // rows are updated in place)
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int k = 16 * kb + c;
-      if (k >= n || zero) continue;
-      if (wv == kb) {
-        // pivot: largest |re|+|im| (45 leading bits) among unused rows, lowest row on ties
+      for (int c = 0; c < 16; ++c) {
+        const int k = 16 * b + c;
         unsigned long long key = 0ull;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
@@ -189,83 +206,137 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
           const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(v.x) + fabs(v.y));
           const unsigned long long kt = used[t] ? 0ull : ((mb & ~127ull) | (unsigned long long)(127 - row));
           key = kt > key ? kt : key;
-          if (row < NP) sCol[k & 1][row] = v;
         }
         key = wave_max_u64(key);
+        // no pivot left (singular): record the first such step; the sweeps go
+        // on with zero multipliers and the result is discarded
+        const bool ok = (key >> 7) != 0ull && zero == 0;
+        zero = (zero == 0 && !ok) ? k + 1 : zero;
+        const int p = 127 - (int)(key & 127ull);
+        const int pl = p & 63, pt = p >> 6;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) inversions += __popcll(__ballot(!used[t] && lane + 64 * t < p));
+        // pivot value and, inside the update, the pivot row (the panel's 16
+        // columns) from lane pl, read into scalar registers one entry at a time
+        const double2 piv = make_double2(readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][c].x : e[0][c].x, pl),
+                                         readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][c].y : e[0][c].y, pl));
+        const double rn = ok ? 1.0 / (piv.x * piv.x + piv.y * piv.y) : 0.0;
+        const double2 inv = make_double2(piv.x * rn, -piv.y * rn);
         if (lane == 0) {
-          if ((key >> 7) == 0ull) {
-            sZero = k + 1;
-          } else {
-            sPiv[k] = 127 - (int)(key & 127ull);
+          sPiv[k] = p;
+          sPivV[k] = piv;
+        }
+        double2 mi[RPL], cc[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int row = lane + 64 * t;
+          double2 ci = e[t][c];
+          cc[t] = row == p ? make_double2(1.0, 0.0) : ci;
+          ci.x += row == p ? 1.0 : 0.0;
+          mi[t] = ok ? cmul(ci, inv) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const double2 src = (RPL > 1 && pt == 1) ? e[RPL - 1][j] : e[0][j];
+          const double2 a = make_double2(readlane_f64(src.x, pl), readlane_f64(src.y, pl));
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            double2 v = e[t][j];
+            v.x = fma(-mi[t].x, a.x, fma(mi[t].y, a.y, v.x));
+            v.y = fma(-mi[t].x, a.y, fma(-mi[t].y, a.x, v.y));
+            e[t][j] = v;
           }
         }
-      }
-      __syncthreads();
-      zero = sZero;
-      if (zero) continue;
-      const int p = sPiv[k];
-      const double2 piv = sCol[k & 1][p];
-      const double rn = 1.0 / (piv.x * piv.x + piv.y * piv.y);
-      const double2 inv = make_double2(piv.x * rn, -piv.y * rn);
-      if (wv == 0 && lane == 0) sPivV[k] = piv;
-      // pivot row (own 16 columns): lane p % 64 writes it to this wave's LDS
-      // slot and every lane of the wave reads it back; a wavefront-scope
-      // release/acquire pair around a wave barrier orders the two (without
-      // it the compiler may let the other lanes read before the write)
-      const int pl = p & 63, pt = p >> 6;
-      if (lane == pl) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) sRowW[wv][j] = (RPL > 1 && pt == 1) ? e[RPL - 1][j] : e[0][j];
+        for (int t = 0; t < RPL; ++t) {
+          e[t][c] = ok ? cmul(cc[t], inv) : e[t][c];
+          if (lane + 64 * t == p) used[t] = true;
+        }
+      }
+      // publish the swept panel (every row) and the outcome
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = lane + 64 * t;
+        if (row < NP) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) sF[buf][row * FS + j] = e[t][j];
+        }
+      }
+      if (lane == 0) {
+        sZero[buf] = zero;
+        sInvW[b] = inversions;
+      }
+    }
+    __syncthreads();
+    zero = sZero[buf];
+    if (zero) break;
+    if (wv != b) {
+      const int k0 = 16 * b;
+      // position of each of this lane's rows among the panel's pivot rows
+      int pos[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) pos[t] = -1;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int pc = sPiv[k0 + c];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t)
+          if (lane + 64 * t == pc) pos[t] = c;
+      }
+      // Z = this wave's columns of the pivot rows, through wave-local LDS; a
+      // wavefront-scope release/acquire pair around a wave barrier orders the
+      // writes before the reads of the other lanes
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        if (pos[t] >= 0) {
+          used[t] = true;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) sZ[wv][pos[t]][j] = e[t][j];
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      double2 apj[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) apj[j] = sRowW[wv][j];
-      // uniform exchange update A[i][j] -= m_i A[p][j] with m_i = (A[i][k] + [i == p]) / pivot,
-      // which leaves -A[p][j] / pivot on the pivot row; the owner of column k then
-      // writes A[i][k] / pivot (1 / pivot on row p)
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int row = lane + 64 * t;
-        double2 ci = row < NP ? sCol[k & 1][row] : make_double2(0.0, 0.0);
-        const double2 cc = row == p ? make_double2(1.0, 0.0) : ci;
-        ci.x += row == p ? 1.0 : 0.0;
-        const double2 mi = cmul(ci, inv);
+        if (row < NP) {
+          if (pos[t] >= 0) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          double2 v = e[t][j];
-          v.x = fma(-mi.x, apj[j].x, fma(mi.y, apj[j].y, v.x));
-          v.y = fma(-mi.x, apj[j].y, fma(-mi.y, apj[j].x, v.y));
-          e[t][j] = v;
+            for (int j = 0; j < 16; ++j) e[t][j] = make_double2(0.0, 0.0);
+          }
+          // c is not unrolled: only the column index j must be static
+#pragma unroll 1
+          for (int c = 0; c < 16; ++c) {
+            const double2 f = sF[buf][row * FS + c];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+              const double2 z = sZ[wv][c][j];
+              e[t][j].x = fma(-f.x, z.x, fma(f.y, z.y, e[t][j].x));
+              e[t][j].y = fma(-f.x, z.y, fma(-f.y, z.x, e[t][j].y));
+            }
+          }
         }
-        if (wv == kb) e[t][c] = cmul(cc, inv);
-        if (row == p) used[t] = true;
       }
     }
   }
   __syncthreads();
 
-  // un-permute: O^{-1}[k][p_m] = R[p_k][m]; padded rows/columns stay zero
-  if (!zero && tid < n) sPinv[sPiv[tid]] = tid;
-  __syncthreads();
+  // R in pivot order, row-contiguous (identity on the padding)
   if (!zero) {
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
-      const int i = lane + 64 * t;
-      if (i < n) {
+      const int row = lane + 64 * t;
+      if (row < NP) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int m = 16 * wv + j;
-          if (m < n) Ow[(size_t)sPinv[i] * NP + sPiv[m]] = e[t][j];
-        }
+        for (int j = 0; j < 16; ++j) Ow[(size_t)row * NP + 16 * wv + j] = e[t][j];
       }
     }
   }
   if (wv == 0) {
-    // log det O = sum_k log(pivot_k) + i pi * parity of the permutation k -> p_k;
-    // the parity is that of its number of inversions, counted by all lanes
+    // pivot rows: a permutation of 0..NP-1, the identity on the padding
+    for (int i = lane; i < NP; i += 64) perm[w * NP + i] = zero ? i : sPiv[i];
+    // log det O = sum_k log(pivot_k) + i pi * parity of the permutation k -> p_k
     double la = 0.0, ar = 0.0;
     int inv_count = 0;
     if (!zero) {
@@ -273,14 +344,12 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
         const double2 pv = sPivV[k];
         la += log(hypot(pv.x, pv.y));
         ar += atan2(pv.y, pv.x);
-        const int pk = sPiv[k];
-        for (int j = k + 1; j < n; ++j) inv_count += sPiv[j] < pk ? 1 : 0;
       }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) inv_count += sInvW[b];
     }
     la = wave_sum_lane0(la);
     ar = wave_sum_lane0(ar);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) inv_count += __shfl_down(inv_count, off, 64);
     if (lane == 0) {
       info[w] = zero;
       if (logov) {
@@ -306,11 +375,13 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
 // ---------------------------------------------------------------------------
 template <int NB>
 __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, const double2* __restrict__ phi,
-                                                    const double2* __restrict__ Oinv, const int* __restrict__ info,
+                                                    const double2* __restrict__ Oinv, const int* __restrict__ perm,
+                                                    const int* __restrict__ info,
                                                     double2* __restrict__ theta, int orbital_major) {
   using C = GtCfg<NB>;
   constexpr int NP = C::NP;
   __shared__ double2 sB[NP * NP];
+  __shared__ int sP[NP], sPi[NP];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -323,12 +394,28 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, co
     w = 8 * (xcd + 8 * (slot >> 3)) + (slot & 7);
     if (w >= nw) return;
   }
+  // O_w^{-1} into LDS from R_w in pivot order: O^{-1}[pinv[i]][piv[m]] = R[i][m]
   const double2* Bw = Oinv + w * (size_t)NP * NP;
-  for (int e = tid; e < NP * NP; e += 512) sB[e] = Bw[e];
+  const bool bad = info[w] != 0;
+  if (!bad) {
+    for (int i = tid; i < NP; i += 512) {
+      const int p = perm[w * NP + i];
+      sP[i] = p;
+      if ((unsigned)p < (unsigned)NP) sPi[p] = i;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NP * NP; e += 512) {
+    if (bad) {
+      sB[e] = make_double2(0.0, 0.0);
+    } else {
+      const int i = e / NP, m = e % NP;
+      sB[sPi[i] * NP + sP[m]] = Bw[e];
+    }
+  }
   __syncthreads();
   const int ksteps = (n + 3) / 4;
   const double2* ph = phi + w * (size_t)M * n;
-  const bool bad = info[w] != 0;
   const double nan = __builtin_nan("");
   // wave (q, h): 16-row blocks q, q+4, ... against the column blocks of half
   // h (JH blocks each), which keeps the accumulators to 3 * JH 16x16 blocks
@@ -384,9 +471,16 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, co
   }
 }
 
+// workspace: the overlap matrices (then R), [nw][NP][NP] complex, followed at
+// a 256-byte boundary by the pivot rows [nw][NP] int32
+static size_t gt_perm_offset(int n, int64_t nw) {
+  const size_t NP = 16 * (size_t)((n + 15) / 16);
+  return (sizeof(double2) * NP * NP * (size_t)nw + 255) / 256 * 256;
+}
+
 size_t green_theta_workspace(int n, int64_t nw) {
   const size_t NP = 16 * (size_t)((n + 15) / 16);
-  return sizeof(double2) * NP * NP * (size_t)nw;
+  return gt_perm_offset(n, nw) + sizeof(int) * NP * (size_t)nw;
 }
 
 template <int NB>
@@ -394,18 +488,19 @@ static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, const doubl
                             double* theta, double* logov, int* info, int orbital_major, double* work,
                             const ProfHook* prof) {
   double2* O = reinterpret_cast<double2*>(work);
+  int* perm = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + gt_perm_offset(n, nw));
   prof_mark(prof, "overlap_kernel");
   hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nw), dim3(256), 0, s, M, n, trial, (const double2*)phi, O);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   prof_mark(prof, "invert_kernel");
-  hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nw), dim3(64 * NB), 0, s, n, O, (double2*)logov, info);
+  hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nw), dim3(64 * NB), 0, s, n, O, perm, (double2*)logov, info);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t grid = 64 * ((nw + 63) / 64);
   prof_mark(prof, "apply_kernel");
   hipLaunchKernelGGL(apply_kernel<NB>, dim3((unsigned)grid), dim3(512), 0, s, M, n, nw, (const double2*)phi,
-                     (const double2*)O, info, (double2*)theta, orbital_major);
+                     (const double2*)O, perm, info, (double2*)theta, orbital_major);
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@ inline void prof_mark(const ProfHook* h, const char* name) {
 }
 
 // ---- per-walker path
-// work: device workspace of green_theta_workspace(n, nw) bytes (the overlap matrices)
+// work: device workspace of green_theta_workspace(n, nw) bytes (the overlap
+// matrices and their inverses in pivot order, then the pivot rows)
 size_t green_theta_workspace(int n, int64_t nw);
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
                               double* theta, double* logov, int* info, int orbital_major, double* work,
