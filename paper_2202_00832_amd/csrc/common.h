@@ -42,33 +42,29 @@ __device__ __forceinline__ double wave_sum_lane0(double v) {
   return v;
 }
 
-// Wave64 maximum of a 64-bit unsigned key, returned as a wave-uniform
+// Wave64 maximum of a 32-bit unsigned key, returned as a wave-uniform
 // (scalar) value.  Inside each row of 16 lanes: DPP quad permutes and the two
 // row mirrors leave every lane with its row's maximum; across rows: the GFX9
 // row broadcasts (lane 15 of each row into the next row, then lane 31 into
 // rows 2 and 3) leave the maximum of all 64 lanes in lane 63, which is read
-// into scalar registers.  Max is exact and associative, so the result does
-// not depend on the order of the steps.
-__device__ __forceinline__ unsigned long long u64_of(int lo, int hi) {
-  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
-}
+// into a scalar register.  Lanes outside a step's row mask keep their value.
 template <int CTRL, int ROWS>
-__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v) {
-  const int lo = (int)(unsigned)(v & 0xffffffffull), hi = (int)(unsigned)(v >> 32);
-  // rows outside the row mask keep their own value (old operand)
-  const unsigned long long o = u64_of(__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false),
-                                      __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false));
+__device__ __forceinline__ unsigned dpp_max_u32(unsigned v) {
+  const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROWS, 0xF, false);
   return o > v ? o : v;
 }
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  v = dpp_max_u64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-  v = dpp_max_u64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-  v = dpp_max_u64<0x141, 0xF>(v);   // row_half_mirror
-  v = dpp_max_u64<0x140, 0xF>(v);   // row_mirror
-  v = dpp_max_u64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-  v = dpp_max_u64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-  return u64_of(__builtin_amdgcn_readlane((int)(unsigned)(v & 0xffffffffull), 63),
-                __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63));
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = dpp_max_u32<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_max_u32<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_max_u32<0x141, 0xF>(v);   // row_half_mirror
+  v = dpp_max_u32<0x140, 0xF>(v);   // row_mirror
+  v = dpp_max_u32<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_max_u32<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ unsigned long long u64_of(int lo, int hi) {
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
 // Lane `lane` (wave-uniform) of a double, into scalar registers.

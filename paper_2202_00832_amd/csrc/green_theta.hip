@@ -144,8 +144,8 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, const double
 //
 //    Blocked by panels of 16 columns.  Panel b (the columns of wave b) is
 //    swept by wave b alone: for each of its columns k, the pivot row p (the
-//    largest |re|+|im| among rows not yet used, compared to 45 bits, lowest
-//    row on ties), then A[i][j] -= m_i A[p][j] on the panel's columns with
+//    largest |re|+|im| among rows not yet used, compared on its exponent and
+//    leading 14 mantissa bits, lowest row on ties), then A[i][j] -= m_i A[p][j] on the panel's columns with
 //    m_i = (A[i][k] + [i == p]) / A[p][k], and column k set to A[i][k] / A[p][k]
 //    (1 / A[p][k] on row p).  The sixteen sweeps act on any other column as
 //    one rank-16 update: with P the panel's pivot rows, Z = A[P, J] taken
@@ -191,28 +191,34 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
     const int buf = b & 1;
     if (wv == b) {
       // inversions of k -> p_k: the rows still unused at step k are the later
-      // pivots, so the step adds the number of unused rows below p_k
+      // pivots, so the step adds the number of unused rows below p_k.  Lane c
+      // keeps the pivot row and value of step c (no branches inside the sweep,
+      // so its sixteen steps form one block the scheduler can overlap).
       int inversions = 0;
+      int myp = 0;
+      double mypr = 1.0, mypi = 0.0;
       // sweep the panel, wave-local and branch-free (no join points, so the
       // rows are updated in place)
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
         const int k = 16 * b + c;
-        unsigned long long key = 0ull;
+        // key: exponent and leading 14 mantissa bits of |re|+|im| above the
+        // complement of the row index (largest magnitude, lowest row on ties)
+        unsigned key = 0u;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
           const int row = lane + 64 * t;
           const double2 v = e[t][c];
-          const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(v.x) + fabs(v.y));
-          const unsigned long long kt = used[t] ? 0ull : ((mb & ~127ull) | (unsigned long long)(127 - row));
+          const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fabs(v.x) + fabs(v.y)) >> 32);
+          const unsigned kt = used[t] ? 0u : (((hi >> 6) << 7) | (unsigned)(127 - row));
           key = kt > key ? kt : key;
         }
-        key = wave_max_u64(key);
+        key = wave_max_u32(key);
         // no pivot left (singular): record the first such step; the sweeps go
         // on with zero multipliers and the result is discarded
-        const bool ok = (key >> 7) != 0ull && zero == 0;
+        const bool ok = (key >> 7) != 0u && zero == 0;
         zero = (zero == 0 && !ok) ? k + 1 : zero;
-        const int p = 127 - (int)(key & 127ull);
+        const int p = 127 - (int)(key & 127u);
         const int pl = p & 63, pt = p >> 6;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) inversions += __popcll(__ballot(!used[t] && lane + 64 * t < p));
@@ -220,20 +226,28 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
         // columns) from lane pl, read into scalar registers one entry at a time
         const double2 piv = make_double2(readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][c].x : e[0][c].x, pl),
                                          readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][c].y : e[0][c].y, pl));
-        const double rn = ok ? 1.0 / (piv.x * piv.x + piv.y * piv.y) : 0.0;
+        // 1 / |pivot|^2: hardware reciprocal refined by two Newton steps
+        const double d = fma(piv.x, piv.x, piv.y * piv.y);
+        double r = __builtin_amdgcn_rcp(d);
+        r = fma(r, fma(-d, r, 1.0), r);
+        r = fma(r, fma(-d, r, 1.0), r);
+        const double rn = ok ? r : 0.0;
         const double2 inv = make_double2(piv.x * rn, -piv.y * rn);
-        if (lane == 0) {
-          sPiv[k] = p;
-          sPivV[k] = piv;
-        }
+        // (selects on scalars: a select of two double2 values goes through scratch)
+        myp = lane == c ? p : myp;
+        mypr = lane == c ? piv.x : mypr;
+        mypi = lane == c ? piv.y : mypi;
         double2 mi[RPL], cc[RPL];
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
           const int row = lane + 64 * t;
           double2 ci = e[t][c];
-          cc[t] = row == p ? make_double2(1.0, 0.0) : ci;
+          cc[t].x = row == p ? 1.0 : ci.x;
+          cc[t].y = row == p ? 0.0 : ci.y;
           ci.x += row == p ? 1.0 : 0.0;
-          mi[t] = ok ? cmul(ci, inv) : make_double2(0.0, 0.0);
+          const double2 m = cmul(ci, inv);
+          mi[t].x = ok ? m.x : 0.0;
+          mi[t].y = ok ? m.y : 0.0;
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
@@ -249,7 +263,9 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
         }
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
-          e[t][c] = ok ? cmul(cc[t], inv) : e[t][c];
+          const double2 v = cmul(cc[t], inv);
+          e[t][c].x = ok ? v.x : e[t][c].x;
+          e[t][c].y = ok ? v.y : e[t][c].y;
           if (lane + 64 * t == p) used[t] = true;
         }
       }
@@ -261,6 +277,10 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
 #pragma unroll
           for (int j = 0; j < 16; ++j) sF[buf][row * FS + j] = e[t][j];
         }
+      }
+      if (lane < 16) {
+        sPiv[16 * b + lane] = myp;
+        sPivV[16 * b + lane] = make_double2(mypr, mypi);
       }
       if (lane == 0) {
         sZero[buf] = zero;
@@ -305,15 +325,20 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
 #pragma unroll
             for (int j = 0; j < 16; ++j) e[t][j] = make_double2(0.0, 0.0);
           }
-          // c is not unrolled: only the column index j must be static
+          // per panel column: the Z row's loads are all issued before the
+          // products (a scheduling barrier keeps them apart), so each product
+          // waits only for its own operand; c is not unrolled (only j must be static)
 #pragma unroll 1
           for (int c = 0; c < 16; ++c) {
+            double2 z[16];
             const double2 f = sF[buf][row * FS + c];
 #pragma unroll
+            for (int j = 0; j < 16; ++j) z[j] = sZ[wv][c][j];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
             for (int j = 0; j < 16; ++j) {
-              const double2 z = sZ[wv][c][j];
-              e[t][j].x = fma(-f.x, z.x, fma(f.y, z.y, e[t][j].x));
-              e[t][j].y = fma(-f.x, z.y, fma(-f.y, z.x, e[t][j].y));
+              e[t][j].x = fma(-f.x, z[j].x, fma(f.y, z[j].y, e[t][j].x));
+              e[t][j].y = fma(-f.x, z[j].y, fma(-f.y, z[j].x, e[t][j].y));
             }
           }
         }
