@@ -165,7 +165,8 @@ int lo_factors_export(const lo_factors* f, double* rows, int64_t* row_offset);
  *   info     : int32 [nw] (output): 0, or k > 0 if the k-th pivot (1-based)
  *              of O_w is exactly zero; theta_w is then undefined and the
  *              energy calls return NaN for that walker.
- * Always FP64.  Supports n_occ <= 96. */
+ * Always FP64.  Supports n_occ <= 96.
+ * "info" reports exact zeros only: a nearly singular O_w is not flagged. */
 int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double* trial,
                 const double* phi, double* theta, double* log_ovlp, int32_t* info, unsigned flags);
 

@@ -36,7 +36,7 @@ struct GtCfg {
 // 1. O_w = Psi_T^T phi_w, written as a padded NP x NP complex block per walker
 // ---------------------------------------------------------------------------
 template <int NB>
-__global__ __launch_bounds__(256) void overlap_kernel(int M, int n, const double* __restrict__ trial,
+__global__ __launch_bounds__(256) void overlap_kernel(int M, int n, int64_t w0, const double* __restrict__ trial,
                                                       const double2* __restrict__ phi,
                                                       double2* __restrict__ O) {
   using C = GtCfg<NB>;
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, const double
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const size_t w = blockIdx.x;
+  const size_t w = w0 + blockIdx.x;
   const double2* ph = phi + w * (size_t)M * n;
 
   constexpr int NPAIR = NB * NB;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, const double
 //    which every other wave applies to its own columns after one barrier.
 // ---------------------------------------------------------------------------
 template <int NB>
-__global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restrict__ O, int* __restrict__ perm,
+__global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, double2* __restrict__ O, int* __restrict__ perm,
                                                           double2* __restrict__ logov, int* __restrict__ info) {
   constexpr int NP = 16 * NB;
   constexpr int RPL = (NP + 63) / 64;        // rows per lane
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
   __shared__ int sInvW[NB];                  // per panel: inversions of the pivot order
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const size_t w = blockIdx.x;
+  const size_t w = w0 + blockIdx.x;
   double2* Ow = O + w * (size_t)NP * NP;
 
   // the padded block is block-diag(O, I): the padding steps pivot on their own
@@ -399,7 +399,8 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, double2* __restr
 //    against half h of the column blocks
 // ---------------------------------------------------------------------------
 template <int NB>
-__global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, const double2* __restrict__ phi,
+__global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, int64_t w0, int64_t nwc,
+                                                    const double2* __restrict__ phi,
                                                     const double2* __restrict__ Oinv, const int* __restrict__ perm,
                                                     const int* __restrict__ info,
                                                     double2* __restrict__ theta, int orbital_major) {
@@ -417,7 +418,8 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, co
     const int64_t b = blockIdx.x;
     const int64_t xcd = b & 7, slot = b >> 3;
     w = 8 * (xcd + 8 * (slot >> 3)) + (slot & 7);
-    if (w >= nw) return;
+    if (w >= nwc) return;
+    w += w0;
   }
   // O_w^{-1} into LDS from R_w in pivot order: O^{-1}[pinv[i]][piv[m]] = R[i][m]
   const double2* Bw = Oinv + w * (size_t)NP * NP;
@@ -509,36 +511,38 @@ size_t green_theta_workspace(int n, int64_t nw) {
 }
 
 template <int NB>
-static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                            double* theta, double* logov, int* info, int orbital_major, double* work,
-                            const ProfHook* prof) {
+static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
+                            const double* phi, double* theta, double* logov, int* info, int orbital_major,
+                            double* work, const ProfHook* prof) {
   double2* O = reinterpret_cast<double2*>(work);
   int* perm = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + gt_perm_offset(n, nw));
   prof_mark(prof, "overlap_kernel");
-  hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nw), dim3(256), 0, s, M, n, trial, (const double2*)phi, O);
+  hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nwc), dim3(256), 0, s, M, n, w0, trial, (const double2*)phi,
+                     O);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   prof_mark(prof, "invert_kernel");
-  hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nw), dim3(64 * NB), 0, s, n, O, perm, (double2*)logov, info);
+  hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nwc), dim3(64 * NB), 0, s, n, w0, O, perm, (double2*)logov,
+                     info);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t grid = 64 * ((nw + 63) / 64);
+  const int64_t grid = 64 * ((nwc + 63) / 64);
   prof_mark(prof, "apply_kernel");
-  hipLaunchKernelGGL(apply_kernel<NB>, dim3((unsigned)grid), dim3(512), 0, s, M, n, nw, (const double2*)phi,
-                     (const double2*)O, perm, info, (double2*)theta, orbital_major);
+  hipLaunchKernelGGL(apply_kernel<NB>, dim3((unsigned)grid), dim3(512), 0, s, M, n, nw, w0, nwc,
+                     (const double2*)phi, (const double2*)O, perm, info, (double2*)theta, orbital_major);
   return hipGetLastError();
 }
 
-hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                              double* theta, double* logov, int* info, int orbital_major, double* work,
-                              const ProfHook* prof) {
-  if (nw <= 0) return hipSuccess;
-  if (n <= 16) return launch_gt<1>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 32) return launch_gt<2>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 48) return launch_gt<3>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 64) return launch_gt<4>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 80) return launch_gt<5>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
-  return launch_gt<6>(s, M, n, nw, trial, phi, theta, logov, info, orbital_major, work, prof);
+hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
+                              const double* phi, double* theta, double* logov, int* info, int orbital_major,
+                              double* work, const ProfHook* prof) {
+  if (nwc <= 0) return hipSuccess;
+  if (n <= 16) return launch_gt<1>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 32) return launch_gt<2>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 48) return launch_gt<3>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 64) return launch_gt<4>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 80) return launch_gt<5>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
+  return launch_gt<6>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
 }
 
 }  // namespace lofqmc

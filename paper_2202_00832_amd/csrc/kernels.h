@@ -20,10 +20,13 @@ inline void prof_mark(const ProfHook* h, const char* name) {
 // ---- per-walker path
 // work: device workspace of green_theta_workspace(n, nw) bytes (the overlap
 // matrices and their inverses in pivot order, then the pivot rows)
+// The launch covers walkers w0 .. w0 + nwc - 1 of the nw addressed by the
+// arrays (and by the workspace), so disjoint walker ranges can run on
+// different streams.
 size_t green_theta_workspace(int n, int64_t nw);
-hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, const double* trial, const double* phi,
-                              double* theta, double* logov, int* info, int orbital_major, double* work,
-                              const ProfHook* prof);
+hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
+                              const double* phi, double* theta, double* logov, int* info, int orbital_major,
+                              double* work, const ProfHook* prof);
 
 int full_num_chunks(int64_t X, int64_t nw);
 hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* lbar,

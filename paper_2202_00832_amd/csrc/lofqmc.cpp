@@ -611,7 +611,7 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   int rc = ensure_ws(ctx, align256(lofqmc::green_theta_workspace((int)n_occ, nw)));
   if (rc) return rc;
   ProfScope prof(ctx);
-  HIP_OR_FAIL(ctx, lofqmc::launch_green_theta(ctx->stream, (int)M, (int)n_occ, nw, trial, phi, theta, log_ovlp,
+  HIP_OR_FAIL(ctx, lofqmc::launch_green_theta(ctx->stream, (int)M, (int)n_occ, nw, 0, nw, trial, phi, theta, log_ovlp,
                                               info, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0, (double*)ctx->ws,
                                               prof.get()));
   return LO_OK;

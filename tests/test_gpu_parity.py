@@ -108,6 +108,34 @@ def test_green_theta(ctx, M, n, nw):
     assert np.abs(dphi).max() <= 1e-11
 
 
+def test_green_theta_many_walkers_with_singular_ones(ctx):
+    """300 walkers (several XCD groups of the apply kernel and a ragged last
+    group): every walker, both layouts, and two singular walkers whose zero
+    pivots come at different steps."""
+    M, n, nw = 50, 17, 300
+    print("green_theta M=%d n=%d nw=%d with singular walkers" % (M, n, nw), flush=True)
+    _, trial, walkers = random_system(M, n, 1, nw, seed=11)
+    walkers[5, :, 3] = 0.0                     # zero columns: exactly zero overlap columns,
+    walkers[250, :, 16] = 0.0                  # which stay zero through the elimination
+    theta, logov, info = ctx.green_theta(dev(trial), dev(walkers))
+    theta_om, logov_om, info_om = ctx.green_theta(dev(trial), dev(walkers), orbital_major=True)
+    theta, logov, info, theta_om = host(theta), host(logov), host(info), host(theta_om)
+    assert np.array_equal(host(info_om), info)
+    assert (info[5], info[250]) == (4, 17)
+    assert (E.green_theta(trial, walkers[5])[2], E.green_theta(trial, walkers[250])[2]) == (4, 17)
+    ok = np.ones(nw, bool)
+    ok[[5, 250]] = False
+    assert (info[ok] == 0).all()
+    ref, ref_ld, ref_info = E.green_theta_batch(trial, walkers[ok])
+    assert (ref_info == 0).all()
+    scale = np.abs(ref).max()
+    assert np.abs(theta[ok] - ref).max() <= 1e-12 * scale
+    assert np.abs(theta_om.transpose(2, 1, 0)[ok] - ref).max() <= 1e-12 * scale
+    assert np.abs(logov[ok].real - ref_ld.real).max() <= 1e-11
+    assert np.abs(np.angle(np.exp(1j * (logov[ok].imag - ref_ld.imag)))).max() <= 1e-11
+    assert np.array_equal(host(logov_om)[ok], logov[ok])
+
+
 def test_green_theta_zero_pivot_and_nan_energy(ctx):
     M, n, X = 20, 3, 4
     rng = np.random.default_rng(3)
