@@ -16,14 +16,15 @@
 
 namespace lofqmc {
 
-// Pass 1: tile = up to LO_TILE_ROWS (64) output rows of one orbital o x 64
-// walkers, eight waves: wave (q, h) owns row block q (16 rows) against walker
-// half h (two 16-walker blocks, real and imaginary part), on the FP64 4x4x4
-// MFMA (four instructions per 16x16 block and K-step),
-// so a workgroup needs few registers and several fit on a compute unit (FP64
-// MFMA needs more than one wave per SIMD to stay busy).  Per 16-row slab of r
-// the factor rows (gathered through rowidx) and Q_o of the 64 walkers are
-// staged in LDS (double-buffered).
+// Pass 1: tile = up to LO_TILE_ROWS (192) output rows of one orbital o x 32
+// walkers.  The rows touching one orbital number about 2 x (sum of its pair
+// ranks), nearly the same for every orbital of a localized basis, so one tile
+// usually covers an orbital and each theta element is fetched once per
+// orbital.  Eight waves; wave v owns rows 24v .. 24v + 23 (six groups of 4)
+// against all 32 walkers (two 16-walker blocks, real and imaginary part) on
+// the FP64 4x4x4 MFMA: 24 accumulators, 24 MFMA per K-step from 6 + 2 LDS
+// reads.  Per 16-row slab of r the factor rows (gathered through rowidx) and
+// Q_o of the 32 walkers are staged in LDS (double-buffered).
 //
 // theta element (o, r, w) is read at theta[o * so + r * sr + w * sw], which
 // serves both layouts: walker-major [w][r][o] and orbital-major [o][r][w].
@@ -31,9 +32,11 @@ namespace lofqmc {
 // 8 XCDs (workgroups are dispatched round-robin over XCDs) and the tiles of
 // one unit run side by side on one XCD: with walker-major theta the orbitals
 // of a block share cache lines, which that XCD's L2 then fetches once.
-constexpr int LO_TILE_ROWS = 64;
-constexpr int LO_WT = 64;
+constexpr int LO_TILE_ROWS = 192;
+constexpr int LO_WT = 32;
 constexpr int LO_OBLK = 8;
+constexpr int LO_WROWS = LO_TILE_ROWS / 8;   // rows per wave (24)
+constexpr int LO_QG = LO_WROWS / 4;          // 4-row groups per wave (6)
 
 __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
                                                           const int* __restrict__ rowidx,
@@ -63,39 +66,39 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
   const int nrows = tile_nrows[t];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int qb = wv & 3, hw = wv >> 2;
   const int lr = lane & 15, lk = lane >> 4;
-  const bool active = 16 * qb < nrows;
+  const int rw = LO_WROWS * wv;                // first row of this wave
+  const bool active = rw < nrows;
   const double2* tho = theta + o * so;
 
-  // staging: A = nrows x 16 doubles (each row 128 contiguous bytes), B = 16 x 64 complex
-  constexpr int A_PER = LO_TILE_ROWS * 16 / 512;   // 2
-  constexpr int B_PER = 16 * LO_WT / 512;          // 2
+  // staging: A = nrows x 16 doubles (each row 128 contiguous bytes), B = 16 x 32 complex
+  constexpr int A_PER = LO_TILE_ROWS * 16 / 512;   // 6
   double pa[A_PER];
-  double2 pb[B_PER];
+  double2 pb;
   // the gathered factor rows of this thread, resolved once (a row index read
   // inside the slab loop would put a dependent global load on every slab)
-  const double* arow[A_PER];
+  int arow[A_PER];
 #pragma unroll
   for (int p = 0; p < A_PER; ++p) {
     const int row = (tid + 512 * p) >> 4;
-    arow[p] = row < nrows ? rows + (size_t)rowidx[row0 + row] * M : nullptr;
+    arow[p] = row < nrows ? rowidx[row0 + row] : -1;
   }
-  auto load = [&](int c) {
+  const int brr = tid / LO_WT, bww = tid % LO_WT;
+  const int64_t bw = w0 + bww;
+  // theta (HBM) is fetched one slab ahead, across the products; the factor
+  // rows (small, reused by every walker tile, so mostly cache hits) after them,
+  // which keeps two workgroups per CU
+  auto load_a = [&](int c) {
     const int rbase = 16 * c;
 #pragma unroll
     for (int p = 0; p < A_PER; ++p) {
       const int r = rbase + ((tid + 512 * p) & 15);
-      pa[p] = (arow[p] != nullptr && r < M) ? arow[p][r] : 0.0;
+      pa[p] = (arow[p] >= 0 && r < M) ? rows[(size_t)arow[p] * M + r] : 0.0;
     }
-#pragma unroll
-    for (int p = 0; p < B_PER; ++p) {
-      const int e = tid + 512 * p;
-      const int rr = e / LO_WT, ww = e % LO_WT;
-      const int r = rbase + rr;
-      const int64_t w = w0 + ww;
-      pb[p] = (r < M && w < nw) ? tho[r * sr + w * sw] : make_double2(0.0, 0.0);
-    }
+  };
+  auto load_b = [&](int c) {
+    const int r = 16 * c + brr;
+    pb = (r < M && bw < nw) ? tho[r * sr + bw * sw] : make_double2(0.0, 0.0);
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -103,36 +106,33 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
       const int e = tid + 512 * p;
       sA[buf][e >> 4][e & 15] = pa[p];
     }
-#pragma unroll
-    for (int p = 0; p < B_PER; ++p) {
-      const int e = tid + 512 * p;
-      sB[buf][e / LO_WT][e % LO_WT] = pb[p];
-    }
+    sB[buf][brr][bww] = pb;
   };
 
-  // acc[q][c]: rows 4q + lk of the block, walker column c (half h = c / 2,
-  // part = c % 2) -- one FP64 4x4x4 accumulator each (see mfma4)
-  double acc[4][4];
+  // acc[q][c]: rows rw + 4q + lk, walker column c (block h = c / 2, part = c % 2)
+  // -- one FP64 4x4x4 accumulator each (see mfma4)
+  double acc[LO_QG][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < LO_QG; ++q)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[q][c] = 0.0;
   const int nchunk = (M + 15) / 16;
-  load(0);
+  load_a(0);
+  load_b(0);
   store(0);
   __syncthreads();
   for (int c = 0; c < nchunk; ++c) {
     const int buf = c & 1;
-    if (c + 1 < nchunk) load(c + 1);
+    if (c + 1 < nchunk) load_b(c + 1);
     if (active) {
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const int rr = 4 * s4 + lk;
-        const double2 b0 = sB[buf][rr][32 * hw + lr];
-        const double2 b1 = sB[buf][rr][32 * hw + 16 + lr];
+        const double2 b0 = sB[buf][rr][lr];
+        const double2 b1 = sB[buf][rr][16 + lr];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double a = sA[buf][16 * qb + 4 * q + (lane & 3)][rr];
+        for (int q = 0; q < LO_QG; ++q) {
+          const double a = sA[buf][rw + 4 * q + (lane & 3)][rr];
           acc[q][0] = mfma4(a, b0.x, acc[q][0]);
           acc[q][1] = mfma4(a, b0.y, acc[q][1]);
           acc[q][2] = mfma4(a, b1.x, acc[q][2]);
@@ -140,18 +140,21 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
         }
       }
     }
-    if (c + 1 < nchunk) store(buf ^ 1);
+    if (c + 1 < nchunk) {
+      load_a(c + 1);
+      store(buf ^ 1);
+    }
     __syncthreads();
   }
-  // lane holds rows 4q + lk of the block, walker 16 * half + lr
+  // lane holds rows rw + 4q + lk, walker 16h + lr
   if (active) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int64_t w = w0 + 32 * hw + 16 * h + lr;
+      const int64_t w = w0 + 16 * h + lr;
       if (w < nw) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int lrow = 16 * qb + 4 * q + lk;
+        for (int q = 0; q < LO_QG; ++q) {
+          const int lrow = rw + 4 * q + lk;
           if (lrow < nrows)
             qbar[(size_t)(row0 + lrow) * nw + w] = make_double2(acc[q][2 * h], acc[q][2 * h + 1]);
         }

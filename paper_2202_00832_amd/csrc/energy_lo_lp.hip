@@ -227,6 +227,8 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_lp_kernel(int Mp, int NP, int
   }
 }
 
+int lo_lp_tile_rows() { return LP1_ROWS; }
+
 hipError_t launch_lo_pass1_lp(hipStream_t s, int precision, int M, int n, int64_t nw, int ntiles,
                               const void* rows_lp, const int* rowidx, const int* tiles, const int* blk, int nblk,
                               int tmax, const void* theta_lp, double* qbar) {

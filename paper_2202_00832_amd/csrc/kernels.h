@@ -48,6 +48,7 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
                            const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
                            const double* theta, int orbital_major, double* qbar);
 int lo_tile_rows();
+int lo_lp_tile_rows();
 int lo_orbital_block();
 int lo_pass2_chunks(int npairs);
 hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int npairs, int nchunk, const int* pK, const int64_t* offI,

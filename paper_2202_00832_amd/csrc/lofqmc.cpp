@@ -42,9 +42,11 @@ struct lo_factors {
   std::vector<double> discarded;       // [n][n], sum of the discarded singular values
   std::vector<int64_t> row_offset;     // [n][n], -1 for i > j
   int ntiles = 0, npairs = 0, nblk = 0, tmax = 0;
+  int ntiles_lp = 0, nblk_lp = 0, tmax_lp = 0;
   int* d_rowidx = nullptr;             // [n_out_rows]
   int* d_tiles = nullptr;              // [3][ntiles]: orbital, first output row, row count;
                                        // then [nblk + 1]: first tile of each orbital block
+  int* d_tiles_lp = nullptr;           // the same for the reduced-precision pass (smaller tiles)
   int* d_pK = nullptr;                 // [npairs]
   int64_t* d_off = nullptr;            // [2][npairs]: output rows of the pair for orbital i and j
   double* d_pw = nullptr;              // [npairs]
@@ -117,6 +119,7 @@ void free_factors(lo_factors* f) {
   (void)hipFree(f->rowsbf);
   (void)hipFree(f->d_rowidx);
   (void)hipFree(f->d_tiles);
+  (void)hipFree(f->d_tiles_lp);
   (void)hipFree(f->d_pK);
   (void)hipFree(f->d_off);
   (void)hipFree(f->d_pw);
@@ -488,7 +491,6 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
     return rc;
   }
   std::vector<int> rowidx(f->n_out_rows);
-  std::vector<int> t_orb, t_row0, t_nrows;
   for (int o = 0; o < n; ++o) {
     for (int k = 0; k < n; ++k) {
       const int i = std::min(o, k), j = std::max(o, k);
@@ -496,36 +498,42 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
       const int64_t cnt = 2 * (int64_t)f->ranks[o * n + k];
       for (int64_t q = 0; q < cnt; ++q) rowidx[obase[o] + loc[o * n + k] + q] = (int)(src + q);
     }
-    // split the orbital's rows into near-equal tiles of at most lo_tile_rows()
-    const int64_t R = obase[o + 1] - obase[o];
-    const int64_t cap = lofqmc::lo_tile_rows();
-    const int64_t ntile = (R + cap - 1) / cap;
-    for (int64_t q = 0; q < ntile; ++q) {
-      const int64_t a = obase[o] + R * q / ntile, b = obase[o] + R * (q + 1) / ntile;
-      t_orb.push_back(o);
-      t_row0.push_back((int)a);
-      t_nrows.push_back((int)(b - a));
-    }
   }
-  f->ntiles = (int)t_orb.size();
-  std::vector<int> tiles;
-  tiles.insert(tiles.end(), t_orb.begin(), t_orb.end());
-  tiles.insert(tiles.end(), t_row0.begin(), t_row0.end());
-  tiles.insert(tiles.end(), t_nrows.begin(), t_nrows.end());
-  // orbital blocks of pass 1: first tile of each block (tiles are sorted by orbital)
-  const int ob = lofqmc::lo_orbital_block();
-  f->nblk = (int)((n + ob - 1) / ob);
-  {
-    std::vector<int> blk(f->nblk + 1, f->ntiles);
+  // pass-1 tiles: each orbital's rows split into near-equal tiles of at most
+  // `cap` rows, listed by orbital as [orbital][first row][row count], then the
+  // first tile of each block of lo_orbital_block() orbitals
+  auto build_tiles = [&](int64_t cap, int* ntiles, int* nblk, int* tmax) {
+    std::vector<int> t_orb, t_row0, t_nrows;
+    for (int o = 0; o < n; ++o) {
+      const int64_t R = obase[o + 1] - obase[o];
+      const int64_t ntile = (R + cap - 1) / cap;
+      for (int64_t q = 0; q < ntile; ++q) {
+        const int64_t a = obase[o] + R * q / ntile, b = obase[o] + R * (q + 1) / ntile;
+        t_orb.push_back(o);
+        t_row0.push_back((int)a);
+        t_nrows.push_back((int)(b - a));
+      }
+    }
+    *ntiles = (int)t_orb.size();
+    std::vector<int> tiles;
+    tiles.insert(tiles.end(), t_orb.begin(), t_orb.end());
+    tiles.insert(tiles.end(), t_row0.begin(), t_row0.end());
+    tiles.insert(tiles.end(), t_nrows.begin(), t_nrows.end());
+    const int ob = lofqmc::lo_orbital_block();
+    *nblk = (int)((n + ob - 1) / ob);
+    std::vector<int> blk(*nblk + 1, *ntiles);
     int t = 0;
-    for (int b = 0; b < f->nblk; ++b) {
-      while (t < f->ntiles && t_orb[t] < b * ob) ++t;
+    for (int b = 0; b < *nblk; ++b) {
+      while (t < *ntiles && t_orb[t] < b * ob) ++t;
       blk[b] = t;
     }
-    f->tmax = 0;
-    for (int b = 0; b < f->nblk; ++b) f->tmax = std::max(f->tmax, blk[b + 1] - blk[b]);
+    *tmax = 0;
+    for (int b = 0; b < *nblk; ++b) *tmax = std::max(*tmax, blk[b + 1] - blk[b]);
     tiles.insert(tiles.end(), blk.begin(), blk.end());
-  }
+    return tiles;
+  };
+  const std::vector<int> tiles = build_tiles(lofqmc::lo_tile_rows(), &f->ntiles, &f->nblk, &f->tmax);
+  const std::vector<int> tiles_lp = build_tiles(lofqmc::lo_lp_tile_rows(), &f->ntiles_lp, &f->nblk_lp, &f->tmax_lp);
   std::vector<int> pK;
   std::vector<int64_t> off;
   std::vector<double> pw;
@@ -553,6 +561,7 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
     orbfeat[2 * i + 1] = (float)ms;
   }
   if ((rc = upload(ctx, &f->d_rowidx, rowidx)) || (rc = upload(ctx, &f->d_tiles, tiles)) ||
+      (rc = upload(ctx, &f->d_tiles_lp, tiles_lp)) ||
       (rc = upload(ctx, &f->d_pK, pK)) || (rc = upload(ctx, &f->d_off, off)) || (rc = upload(ctx, &f->d_pw, pw)) ||
       (rc = upload(ctx, &f->d_orbfeat, orbfeat))) {
     cleanup();
@@ -704,9 +713,9 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
     HIP_OR_FAIL(ctx, lofqmc::launch_lp_convert_theta(ctx->stream, precision, (int)M, (int)n, nw, theta, tlp));
     prof.mark("lo_pass1_lp_kernel");
     const void* rows_lp = precision == LO_FP32 ? (const void*)f->rows32 : (const void*)f->rowsbf;
-    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1_lp(ctx->stream, precision, (int)M, (int)n, nw, f->ntiles, rows_lp,
-                                                f->d_rowidx, f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk,
-                                                f->tmax, tlp, qbar));
+    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1_lp(ctx->stream, precision, (int)M, (int)n, nw, f->ntiles_lp, rows_lp,
+                                                f->d_rowidx, f->d_tiles_lp, f->d_tiles_lp + 3 * f->ntiles_lp,
+                                                f->nblk_lp, f->tmax_lp, tlp, qbar));
   }
   prof.mark("lo_pass2_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->npairs, nchunk, f->d_pK, f->d_off,
