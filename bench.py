@@ -12,6 +12,10 @@ total-energy error stays within 1 mHa of the full route: the walker-mean of
 Re(E_LO - E_full) plus twice its standard error must not exceed 1 mHa (the
 largest per-walker error is reported beside it).  Prints one
 JSON line (stdout); progress goes to stderr.
+
+The LO step takes about half a millisecond, so the default warm-up (400 steps,
+about 0.2 s of GPU work) is long enough for the GPU clocks to settle; with a
+few warm-up steps the timed region runs some 10 % slower.
 """
 from __future__ import annotations
 
@@ -61,6 +65,9 @@ def kernel_work(M, n, nw, X=0, n_out=0, total_rows=0, pair_rows=0):
         "energy_full_kernel": ("mfma", nw * X * (4.0 * n * n * M + 8.0 * n * n),
                                r8 * X * M * n + c16 * nw * M * n),
         "theta_transpose_kernel": ("hbm", 0.0, 2 * c16 * nw * M * n),
+        # Eq. 17: Y^[ij] theta_j and Y^[ij] theta_i per pair i < j, one product for i = j
+        "hr_energy_kernel": ("mfma", 4.0 * M * M * nw * (n * (n - 1) + n),
+                             r8 * M * M * n * (n + 1) / 2 + c16 * nw * M * n),
     }
 
 
@@ -131,6 +138,44 @@ def time_route(torch, ctx, step, steps, warmup, marks):
     for a, b in zip(marks[:-1], marks[1:]):
         split[a + "->" + b] = [e[a].elapsed_time(e[b]) for e in evs]
     return total, split, kernels
+
+
+def hr_study(torch, ctx, lbar, trial_d, phi_d, info, energy, e_full_h, work, M, n, nw, steps=10):
+    """The half-rotated ERI route (Eq. 17) on the same workload: pair-block
+    build, time per step (green_theta + local_energy_hr, with theta
+    orbital-major: the route reads theta columns of 32 walkers, contiguous in
+    that layout) and agreement with the full route."""
+    t = time.perf_counter()
+    hr = ctx.build_hr_eri(lbar)
+    build_s = time.perf_counter() - t
+    theta_om = torch.empty((n, M, nw), dtype=torch.complex128, device="cuda")
+    logov = torch.empty(nw, dtype=torch.complex128, device="cuda")
+    ctx.green_theta(trial_d, phi_d, theta_om, logov, info, orbital_major=True)
+    e_hr = ctx.local_energy_hr(hr, theta_om, info, orbital_major=True)
+    torch.cuda.synchronize()
+    diff = float(np.abs(e_hr.cpu().numpy() - e_full_h).max())
+
+    def step(ev):
+        if ev is not None:
+            ev["a"].record()
+        ctx.green_theta(trial_d, phi_d, theta_om, logov, info, orbital_major=True)
+        if ev is not None:
+            ev["b"].record()
+        ctx.local_energy_hr(hr, theta_om, info, energy, orbital_major=True)
+        if ev is not None:
+            ev["c"].record()
+
+    tot, split, kern = time_route(torch, ctx, step, steps, 2, ["a", "b", "c"])
+    ms = tot / steps
+    kernels = {k: roofline_of(k, work, t_ / c) for k, (c, t_) in kern.items() if k in work}
+    log("HR-ERI: %.3f ms/step (local_energy_hr %.3f), pair blocks %.2f GB built in %.2f s, max |E_hr - E_full| %.2e"
+        % (ms, float(np.mean(split["b->c"])), hr.bytes / 1e9, build_s, diff))
+    out = {"value": round(nw / (ms * 1e-3), 1), "unit": "walker-energies/s", "ms_per_step": round(ms, 4),
+           "local_energy_hr_ms": round(float(np.mean(split["b->c"])), 4), "steps": steps, "theta": "orbital-major",
+           "pair_block_bytes": hr.bytes, "build_s": round(build_s, 3), "max_abs_diff_vs_full_Ha": diff,
+           "roofline": kernels.get("hr_energy_kernel"), "kernels": kernels}
+    hr.close()
+    return out
 
 
 def precision_study(torch, lofqmc, synth, steps):
@@ -332,8 +377,8 @@ def cpu_baseline(cfg, system, eps, sample):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--cpu-sample", type=int, default=256,
                     help="walkers timed on the CPU reference (about 10 s of host work at the default)")
     ap.add_argument("--eps", type=str, default="",
@@ -344,6 +389,8 @@ def main():
                     help="skip the multi-system batching study (8 chain systems, captured graph)")
     ap.add_argument("--no-residual", action="store_true",
                     help="skip the learned-residual study")
+    ap.add_argument("--no-hr", action="store_true",
+                    help="skip the half-rotated ERI route (Eq. 17; its pair blocks take 2.3 GB)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -479,6 +526,10 @@ def main():
     full_kernels = {k: roofline_of(k, work, t / c) for k, (c, t) in kern_f.items() if k in work}
     full_roof = full_kernels["energy_full_kernel"]
 
+    hr_out = None
+    if not args.no_hr:
+        hr_out = hr_study(torch, ctx, lbar, trial_d, phi_d, info, energy, e_full_h, work, M, n, nw)
+
     prec = None
     if not args.no_precision:
         prec = precision_study(torch, lofqmc, synth, max(2, min(args.steps, 5)))
@@ -503,6 +554,7 @@ def main():
         "full": {"value": round(nw / (full_ms * 1e-3), 1), "unit": "walker-energies/s", "ms_per_step": round(full_ms, 4),
                  "steps": full_steps, "roofline": full_roof, "kernels": full_kernels},
         "lo_vs_full_speedup": round(full_ms / head["ms_per_step"], 2),
+        "hr_eri": hr_out,
         "eps_sweep": [{k: v for k, v in s.items() if not k.startswith("_")} for s in sweep],
         "roofline": roofline,
         "kernels": per_kernel,

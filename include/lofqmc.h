@@ -31,6 +31,7 @@ extern "C" {
 
 typedef struct lo_ctx lo_ctx;
 typedef struct lo_factors lo_factors;
+typedef struct lo_hr lo_hr;
 
 enum lo_status {
   LO_OK = 0,
@@ -203,6 +204,39 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
  * workspace first.  flags may hold LO_THETA_ORBITAL_MAJOR only. */
 int local_energy_lo(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const double* theta,
                     const int32_t* info, int precision, unsigned flags, double* energy);
+
+/* ------------------------------------------------ half-rotated ERI route
+ *
+ * The route the LO compression approximates (Sec. 2.2, Eq. 17): the pair
+ * blocks
+ *   Y^[ij]_{rs} = sum_g Lbar^g_{ri} Lbar^g_{sj}       (M x M, i <= j)
+ * are stored whole (n_occ (n_occ + 1) / 2 * M^2 doubles: 2.3 GB at M = 400,
+ * n_occ = 60), and per walker
+ *   E_J = 2 sum_ij Q_i^T Y^[ij] Q_j,   E_K = -sum_ij Q_j^T Y^[ij] Q_i
+ * (complex, bilinear); Y^[ji] = (Y^[ij])^T, so the pairs i < j count twice. */
+
+/* Builds the pair blocks on the device (library-owned handle, released by
+ * lo_hr_destroy; LO_ENOMEM when they do not fit).  lbar as for
+ * build_lo_factors.  Synchronous. */
+int build_hr_eri(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar, lo_hr** out);
+
+int lo_hr_destroy(lo_hr* h);
+
+/* Any output pointer may be NULL; bytes = device bytes of the pair blocks. */
+int lo_hr_info(const lo_hr* h, int64_t* M, int64_t* n_occ, int64_t* bytes);
+
+/* Energy by Eq. 17, FP64.
+ *   h      : handle from build_hr_eri (shapes M, n_occ taken from it)
+ *   theta  : complex [nw][M][n_occ], or [n_occ][M][nw] with flags
+ *            LO_THETA_ORBITAL_MAJOR
+ *   info   : int32 [nw] or NULL (walkers with info != 0 get NaN)
+ *   energy : complex [nw][2] (output) = (E_J, E_K)
+ * flags may hold LO_THETA_ORBITAL_MAJOR only.  The kernel reads theta columns
+ * of 32 walkers, contiguous in the orbital-major layout, which is about twice
+ * as fast here as walker-major.  Partial sums of npairs x nw x 32 bytes live in
+ * the context workspace. */
+int local_energy_hr(lo_ctx* ctx, const lo_hr* h, int64_t nw, const double* theta, const int32_t* info,
+                    unsigned flags, double* energy);
 
 /* --------------------------------------------------- several systems at once
  *

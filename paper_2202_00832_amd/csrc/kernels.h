@@ -104,6 +104,13 @@ hipError_t launch_residual_train_step(hipStream_t s, int64_t nw, int n, float* p
                                       int64_t step, float lr, const float* x, const double* target, void* work,
                                       float* grad_out, double* loss, double* pred);
 
+// ---- half-rotated ERI route
+// Y: device [npairs][M][M] (row-major pair blocks, i <= j); pairs: device int
+// [npairs][2]; partial: device [npairs][nw][4] doubles, reduced by
+// launch_reduce_partials with nchunk = npairs.
+hipError_t launch_hr_energy(hipStream_t s, int M, int n, int64_t nw, int npairs, const double* Y, const int* pairs,
+                            const double* theta, int orbital_major, double* partial);
+
 // ---- set-up
 // C_b(m, c) = sum_k A_b(m, k) B_b(k, c), element (m, k) of A at a_base[b] + m * a_m + k * a_k, etc.
 // bases: device int64 [batch][3] = (a_base, b_base, c_base).

@@ -53,6 +53,12 @@ struct lo_factors {
   float* d_orbfeat = nullptr;          // [n][2]: sum_j K_ij, sum_j discarded mass (residual features)
 };
 
+struct lo_hr {
+  int64_t M = 0, n = 0, npairs = 0;
+  double* Y = nullptr;     // device [npairs][M][M], row-major, pairs i <= j in row order
+  int* d_pairs = nullptr;  // device [npairs][2]
+};
+
 namespace {
 
 constexpr int kMaxOcc = 64;     // FP64 full route
@@ -600,6 +606,118 @@ int lo_factors_export(const lo_factors* f, double* rows, int64_t* row_offset) {
     if (hipMemcpy(rows, f->rows, sizeof(double) * (size_t)f->total_rows * f->M, hipMemcpyDeviceToHost) != hipSuccess)
       return LO_EHIP;
   }
+  return LO_OK;
+}
+
+int build_hr_eri(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar, lo_hr** out) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!out) return fail(ctx, LO_EINVAL, "null output handle");
+  *out = nullptr;
+  if (M <= 0 || n_occ <= 0 || n_chol < 0) return fail(ctx, LO_EINVAL, "sizes must be M > 0, n_occ > 0, n_chol >= 0");
+  if (n_occ > M) return fail(ctx, LO_EINVAL, "n_occ exceeds M");
+  if (M > 65535 || n_chol > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "M above 65535");
+  if (n_chol > 0 && !lbar) return fail(ctx, LO_EINVAL, "null lbar");
+  const int64_t npairs = n_occ * (n_occ + 1) / 2;
+  int64_t elems = 0, bytes = 0;
+  if (!mul_ok(npairs, M * M, &elems) || !mul_ok(elems, (int64_t)sizeof(double), &bytes))
+    return fail(ctx, LO_EUNSUPPORTED, "pair blocks too large");
+  lo_hr* h = new (std::nothrow) lo_hr();
+  if (!h) return fail(ctx, LO_ENOMEM, "host allocation failed");
+  h->M = M;
+  h->n = n_occ;
+  h->npairs = npairs;
+  double* lbarT = nullptr;
+  int64_t* d_bases = nullptr;
+  auto release = [&]() {
+    (void)hipFree(lbarT);
+    (void)hipFree(d_bases);
+  };
+  auto fail_all = [&](int code, const char* what) {
+    (void)hipStreamSynchronize(ctx->stream);
+    release();
+    lo_hr_destroy(h);
+    return fail(ctx, code, "%s", what);
+  };
+  if (hipMalloc(&h->Y, (size_t)bytes) != hipSuccess) {
+    h->Y = nullptr;
+    return fail_all(LO_ENOMEM, "device allocation of the pair blocks failed");
+  }
+  std::vector<int> pairs(2 * npairs);
+  std::vector<int64_t> bases(3 * npairs);
+  for (int64_t i = 0, p = 0; i < n_occ; ++i) {
+    for (int64_t j = i; j < n_occ; ++j, ++p) {
+      pairs[2 * p] = (int)i;
+      pairs[2 * p + 1] = (int)j;
+      bases[3 * p] = i * n_chol * M;
+      bases[3 * p + 1] = j * n_chol * M;
+      bases[3 * p + 2] = p * M * M;
+    }
+  }
+  int rc = upload(ctx, &h->d_pairs, pairs);
+  if (rc) return fail_all(rc, "device allocation failed");
+  rc = upload(ctx, &d_bases, bases);
+  if (rc) return fail_all(rc, "device allocation failed");
+  if (n_chol > 0) {
+    if (hipMalloc(&lbarT, sizeof(double) * (size_t)n_occ * n_chol * M) != hipSuccess) {
+      lbarT = nullptr;
+      return fail_all(LO_ENOMEM, "device allocation of the transposed Cholesky vectors failed");
+    }
+    if (lofqmc::launch_lbar_transpose(ctx->stream, (int)M, (int)n_occ, n_chol, lbar, lbarT) != hipSuccess)
+      return fail_all(LO_EHIP, "transpose launch failed");
+  }
+  // Y^[ij](r, s) = sum_g lbarT[i][g][r] lbarT[j][g][s], row-major; with no
+  // Cholesky vectors the K loop is empty and the blocks are written as zeros
+  for (int64_t p0 = 0; p0 < npairs; p0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, npairs - p0);
+    if (lofqmc::launch_gemm_setup(ctx->stream, (int)M, (int)M, (int)n_chol, lbarT, 1, M, lbarT, M, 1, h->Y, M, 1,
+                                  d_bases + 3 * p0, nb) != hipSuccess)
+      return fail_all(LO_EHIP, "pair-block launch failed");
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail_all(LO_EHIP, "pair-block build failed");
+  release();
+  *out = h;
+  return LO_OK;
+}
+
+int lo_hr_destroy(lo_hr* h) {
+  if (!h) return LO_OK;
+  (void)hipFree(h->Y);
+  (void)hipFree(h->d_pairs);
+  delete h;
+  return LO_OK;
+}
+
+int lo_hr_info(const lo_hr* h, int64_t* M, int64_t* n_occ, int64_t* bytes) {
+  if (!h) return LO_EINVAL;
+  if (M) *M = h->M;
+  if (n_occ) *n_occ = h->n;
+  if (bytes) *bytes = h->npairs * h->M * h->M * (int64_t)sizeof(double);
+  return LO_OK;
+}
+
+int local_energy_hr(lo_ctx* ctx, const lo_hr* h, int64_t nw, const double* theta, const int32_t* info,
+                    unsigned flags, double* energy) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!h) return fail(ctx, LO_EINVAL, "null pair blocks");
+  if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
+  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
+  if (nw == 0) return LO_OK;
+  if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
+  int64_t pbytes = 0;
+  if (!mul_ok(h->npairs * (int64_t)sizeof(double) * 4, nw, &pbytes))
+    return fail(ctx, LO_EUNSUPPORTED, "partial sums too large");
+  int rc = ensure_ws(ctx, align256((size_t)pbytes));
+  if (rc) return rc;
+  double* partial = (double*)ctx->ws;
+  ProfScope prof(ctx);
+  prof.mark("hr_energy_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_hr_energy(ctx->stream, (int)h->M, (int)h->n, nw, (int)h->npairs, h->Y, h->d_pairs,
+                                            theta, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0, partial));
+  prof.mark("reduce_partials_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, (int)h->npairs, partial, info, energy));
   return LO_OK;
 }
 

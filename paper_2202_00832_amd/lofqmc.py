@@ -41,6 +41,10 @@ _SIGS = {
     "local_energy_full": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _i64, _c_p, _c_p, _c_p, ctypes.c_int,
                                          ctypes.c_uint, _c_p]),
     "local_energy_lo": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p]),
+    "build_hr_eri": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, ctypes.POINTER(_c_p)]),
+    "lo_hr_destroy": (ctypes.c_int, [_c_p]),
+    "lo_hr_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p]),
+    "local_energy_hr": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_uint, _c_p]),
     "lo_batch_create": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int, _c_p, ctypes.POINTER(_c_p)]),
     "lo_batch_destroy": (ctypes.c_int, [_c_p]),
     "lo_batch_info": (ctypes.c_int, [_c_p, _c_p, _c_p]),
@@ -113,6 +117,33 @@ def _check_dev(name, t, dtype, shape):
         raise ValueError("%s must be contiguous" % name)
     if tuple(t.shape) != tuple(shape):
         raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+
+class HrEri:
+    """Owner of a lo_hr handle: the pair blocks Y^[ij] of the half-rotated ERI (device)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        M = ctypes.c_int64()
+        n = ctypes.c_int64()
+        b = ctypes.c_int64()
+        load().lo_hr_info(self._h, ctypes.byref(M), ctypes.byref(n), ctypes.byref(b))
+        self.M, self.n_occ, self.bytes = M.value, n.value, b.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load().lo_hr_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Factors:
@@ -323,6 +354,14 @@ class Context:
         self._check(self._lib.build_lo_factors(self._h, M, n, X, _ptr(lbar), float(epsilon), ctypes.byref(h)))
         return Factors(h.value)
 
+    def build_hr_eri(self, lbar) -> HrEri:
+        import torch
+        X, M, n = lbar.shape
+        _check_dev("lbar", lbar, torch.float64, (X, M, n))
+        h = ctypes.c_void_p()
+        self._check(self._lib.build_hr_eri(self._h, M, n, X, _ptr(lbar), ctypes.byref(h)))
+        return HrEri(h.value)
+
     # -- per walker ---------------------------------------------------------------
     def green_theta(self, trial, phi, theta=None, log_ovlp=None, info=None, orbital_major=False):
         """theta is [nw][M][n] (walker-major) or [n][M][nw] when orbital_major."""
@@ -379,6 +418,26 @@ class Context:
         _check_dev("energy", energy, torch.complex128, (nw, 2))
         self._check(self._lib.local_energy_lo(self._h, factors.handle, nw, _ptr(theta), _ptr(info), int(precision),
                                               int(flags), _ptr(energy)))
+        return energy
+
+    def local_energy_hr(self, hr: HrEri, theta, info=None, energy=None, orbital_major=False):
+        """Eq. 17 route; theta is [nw][M][n], or [n][M][nw] when orbital_major."""
+        import torch
+        flags = 0
+        if orbital_major:
+            nw = theta.shape[2]
+            _check_dev("theta", theta, torch.complex128, (hr.n_occ, hr.M, nw))
+            flags = LO_THETA_ORBITAL_MAJOR
+        else:
+            nw = theta.shape[0]
+            _check_dev("theta", theta, torch.complex128, (nw, hr.M, hr.n_occ))
+        if info is not None:
+            _check_dev("info", info, torch.int32, (nw,))
+        if energy is None:
+            energy = torch.empty((nw, 2), dtype=torch.complex128, device=theta.device)
+        _check_dev("energy", energy, torch.complex128, (nw, 2))
+        self._check(self._lib.local_energy_hr(self._h, hr.handle, nw, _ptr(theta), _ptr(info), flags,
+                                              _ptr(energy)))
         return energy
 
     # -- learned residual (extension) ---------------------------------------------

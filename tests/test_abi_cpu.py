@@ -20,7 +20,7 @@ def test_every_declared_symbol_is_exported(lib):
     names = L.declared_functions()
     assert len(names) >= 13
     for name in ["lo_create", "build_half_rotated_chol", "build_lo_factors", "green_theta",
-                 "local_energy_full", "local_energy_lo"]:
+                 "local_energy_full", "local_energy_lo", "build_hr_eri", "local_energy_hr"]:
         assert name in names
     for name in names:
         assert hasattr(lib, name), name
@@ -65,6 +65,19 @@ def test_validation_errors_need_no_device(lib):
         assert lib.build_half_rotated_chol(h, 8, 2, 0, None, None, None) == L.LO_OK  # nothing to do
         assert lib.lo_factors_info(None, None, None, None, None, None, None) == L.LO_EINVAL
         assert lib.lo_factors_destroy(None) == L.LO_OK
+        # half-rotated ERI route
+        assert lib.build_hr_eri(h, 8, 2, 3, fake, None) == L.LO_EINVAL
+        assert lib.build_hr_eri(h, 8, 9, 3, fake, ctypes.byref(out)) == L.LO_EINVAL      # n > M
+        assert lib.build_hr_eri(h, 0, 2, 3, fake, ctypes.byref(out)) == L.LO_EINVAL
+        assert lib.build_hr_eri(h, 8, 2, 3, None, ctypes.byref(out)) == L.LO_EINVAL      # null lbar
+        assert lib.build_hr_eri(h, 70000, 2, 3, fake, ctypes.byref(out)) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_hr(h, None, 4, fake, None, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_hr(h, fake, 4, fake, None, 2, fake) == L.LO_EINVAL        # unknown flag
+        assert lib.local_energy_hr(h, fake, -1, fake, None, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_hr(h, fake, 4, None, None, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_hr(h, fake, 0, None, None, 0, None) == L.LO_OK            # empty batch
+        assert lib.lo_hr_info(None, None, None, None) == L.LO_EINVAL
+        assert lib.lo_hr_destroy(None) == L.LO_OK
     finally:
         assert lib.lo_destroy(h) == L.LO_OK
     assert lib.lo_destroy(None) == L.LO_OK
