@@ -133,6 +133,28 @@ int build_half_rotated_chol(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_cho
 int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol,
                      const double* lbar, double epsilon, lo_factors** out);
 
+/* LO factors from a randomized SVD of every pair block (the approximate
+ * decomposition Sec. 2.3.1 mentions as a cheaper set-up): randomized subspace
+ * iteration (Halko, Martinsson and Tropp, SIAM Rev. 53 (2011), Alg. 4.4),
+ *   Z = Y Omega, then power_iters times Q = orth(Z), Q' = orth(Y^T Q),
+ *   Z = Y Q'; Q = orth(Z); B = Q^T Y = U_B Sigma V; U = Q U_B,
+ * with orth a twice-applied Gram-Schmidt.  Singular values of B with sigma >= epsilon are
+ * kept as in build_lo_factors; the set-up costs O(M^2 sketch) per pair
+ * instead of O(M^3).
+ *   sketch      : columns of the test matrix, 1 <= sketch <= min(M, 64); if every one of
+ *                 the sketch singular values of some pair reaches epsilon the
+ *                 call fails with LO_EUNSUPPORTED (a larger sketch is needed)
+ *   power_iters : 0..16
+ *   omega       : [M][sketch] double (device, row-major), the random test
+ *                 matrix (the caller draws it, e.g. standard normal)
+ *   epsilon     : > 0
+ * The discarded mass reported for a pair sums only the discarded singular
+ * values the sketch resolves.  Other arguments and the handle as for
+ * build_lo_factors. */
+int build_lo_factors_randomized(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar,
+                                double epsilon, int64_t sketch, int power_iters, const double* omega,
+                                lo_factors** out);
+
 int lo_factors_destroy(lo_factors* f);
 
 /* Host-side description of a handle.  Any output pointer may be NULL.
@@ -166,7 +188,7 @@ int lo_factors_export(const lo_factors* f, double* rows, int64_t* row_offset);
  *   info     : int32 [nw] (output): 0, or k > 0 if the k-th pivot (1-based)
  *              of O_w is exactly zero; theta_w is then undefined and the
  *              energy calls return NaN for that walker.
- * Always FP64.  Supports n_occ <= 96.
+ * Always FP64.  Supports n_occ <= 112.
  * "info" reports exact zeros only: a nearly singular O_w is not flagged. */
 int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double* trial,
                 const double* phi, double* theta, double* log_ovlp, int32_t* info, unsigned flags);

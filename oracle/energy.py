@@ -164,6 +164,32 @@ def lo_decompose(lbar: np.ndarray, pairs: str = "ordered"):
     return out
 
 
+def lo_decompose_randomized(lbar: np.ndarray, omega: np.ndarray, power_iters: int):
+    """Approximate SVD of every pair block i <= j by randomized subspace
+    iteration (Halko, Martinsson and Tropp, SIAM Rev. 53 (2011), Alg. 4.4),
+    the cheaper decomposition Sec. 2.3.1 mentions: with the test matrix omega
+    (M x l), Z = Y omega; power_iters times Q = orth(Z), Q' = orth(Y^T Q),
+    Z = Y Q'; then Q = orth(Z), B = Q^T Y = U_B Sigma V, U = Q U_B.  orth is a
+    QR factorisation.  Returns dict (i, j) -> (U [M x l], sigma [l], V [l x M]),
+    the input format of lo_truncate.
+    """
+    n = lbar.shape[1]
+    cols = [np.ascontiguousarray(lbar[:, i, :]) for i in range(n)]
+    orth = lambda A: np.linalg.qr(A)[0]  # noqa: E731
+    out = {}
+    for i in range(n):
+        for j in range(i, n):
+            Y = cols[i].T @ cols[j]
+            Z = Y @ omega
+            for _ in range(power_iters):
+                Q = orth(Z)
+                Z = Y @ orth(Y.T @ Q)
+            Q = orth(Z)
+            Ub, s, Vh = np.linalg.svd(Q.T @ Y, full_matrices=False)
+            out[(i, j)] = (Q @ Ub, s, Vh)
+    return out
+
+
 def lo_truncate(decomp: dict, eps: float):
     """Keeps the singular values sigma_K >= eps (all of them when eps == 0).
 

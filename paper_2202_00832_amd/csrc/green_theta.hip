@@ -28,7 +28,9 @@ struct GtCfg {
   static constexpr int NP = 16 * NB;
   static constexpr int KC = 16;                // rows of r per overlap slab
   static constexpr int SLOTS = KC * NP;        // complex slots of a phi slab
-  static constexpr int PER = (SLOTS + 255) / 256;
+  static constexpr int OW = NB <= 6 ? 4 : 8;    // waves of the overlap kernel
+  static constexpr int OT = 64 * OW;            // its threads
+  static constexpr int PER = (SLOTS + OT - 1) / OT;
   static constexpr int NKS = NP / 4;           // K-steps of theta = phi O^{-1}
 };
 
@@ -36,7 +38,7 @@ struct GtCfg {
 // 1. O_w = Psi_T^T phi_w, written as a padded NP x NP complex block per walker
 // ---------------------------------------------------------------------------
 template <int NB>
-__global__ __launch_bounds__(256) void overlap_kernel(int M, int n, int64_t w0, const double* __restrict__ trial,
+__global__ __launch_bounds__(GtCfg<NB>::OT) void overlap_kernel(int M, int n, int64_t w0, const double* __restrict__ trial,
                                                       const double2* __restrict__ phi,
                                                       double2* __restrict__ O) {
   using C = GtCfg<NB>;
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, int64_t w0, 
   const double2* ph = phi + w * (size_t)M * n;
 
   constexpr int NPAIR = NB * NB;
-  constexpr int PPW = (NPAIR + 3) / 4;
+  constexpr int PPW = (NPAIR + C::OW - 1) / C::OW;
   d4 accR[PPW], accI[PPW];
 #pragma unroll
   for (int p = 0; p < PPW; ++p) { accR[p] = d4zero(); accI[p] = d4zero(); }
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, int64_t w0, 
   auto load_slab = [&](int c, double2 (&dP)[C::PER], double (&dS)[C::PER]) {
 #pragma unroll
     for (int q = 0; q < C::PER; ++q) {
-      const int s = tid + 256 * q;
+      const int s = tid + C::OT * q;
       const int rr = s / NP, j = s % NP;
       const int r = C::KC * c + rr;
       const bool ok = s < C::SLOTS && r < M && j < n;
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, int64_t w0, 
   auto store_slab = [&](int buf, const double2 (&sP)[C::PER], const double (&sS)[C::PER]) {
 #pragma unroll
     for (int q = 0; q < C::PER; ++q) {
-      const int s = tid + 256 * q;
+      const int s = tid + C::OT * q;
       if (s < C::SLOTS) {
         sPh[buf][s] = sP[q];
         sPs[buf][s] = sS[q];
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, int64_t w0, 
       } else {
 #pragma unroll
         for (int p = 0; p < PPW; ++p) {
-          const int bp = wv + 4 * p;
+          const int bp = wv + C::OW * p;
           if (bp < NPAIR) {
             const int I = bp / NB, J = bp % NB;
             const double a = sPs[buf][row + 16 * I + lr];
@@ -104,6 +106,8 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, int64_t w0, 
           }
         }
       }
+      // beyond 96 orbitals: operands of one K-step at a time (register file)
+      if constexpr (NB > 6) __builtin_amdgcn_sched_barrier(0);
     }
   };
   const int nslab = (M + C::KC - 1) / C::KC;
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(256) void overlap_kernel(int M, int n, int64_t w0, 
   double2* Ow = O + w * (size_t)NP * NP;
 #pragma unroll
   for (int p = 0; p < PPW; ++p) {
-    const int bp = wv + 4 * p;
+    const int bp = wv + C::OW * p;
     if (bp < NPAIR) {
       const int I = bp / NB, J = bp % NB;
 #pragma unroll
@@ -394,11 +398,13 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
 }
 
 // ---------------------------------------------------------------------------
-// 3. theta_w = phi_w O_w^{-1}; one 512-thread workgroup per walker, O_w^{-1}
-//    staged once in LDS, wave (q, h) takes the 16-row blocks q, q+4, ...
-//    against half h of the column blocks
+// 3. theta_w = phi_w O_w^{-1}; one 512-thread workgroup per walker and part of
+//    CB column blocks (all NB of them up to 96 orbitals; beyond that the
+//    columns of O_w^{-1} no longer fit the LDS and blockIdx.y picks the part),
+//    the part of O_w^{-1} staged once in LDS, wave (q, h) takes the 16-row
+//    blocks q, q+4, ... against half h of the part's column blocks
 // ---------------------------------------------------------------------------
-template <int NB>
+template <int NB, int CB>
 __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, int64_t w0, int64_t nwc,
                                                     const double2* __restrict__ phi,
                                                     const double2* __restrict__ Oinv, const int* __restrict__ perm,
@@ -406,11 +412,14 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, in
                                                     double2* __restrict__ theta, int orbital_major) {
   using C = GtCfg<NB>;
   constexpr int NP = C::NP;
-  __shared__ double2 sB[NP * NP];
+  constexpr int CW = 16 * CB;                  // columns of one part
+  __shared__ double2 sB[NP * CW];
   __shared__ int sP[NP], sPi[NP];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
+  const int part = blockIdx.y;
+  const int c0 = CW * part;                    // first column of the part
   // workgroups go round-robin over the 8 XCDs; walkers 8g .. 8g+7 share an
   // XCD so that their interleaved orbital-major 16-byte stores meet in one L2
   int64_t w;
@@ -432,12 +441,25 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, in
     }
   }
   __syncthreads();
-  for (int e = tid; e < NP * NP; e += 512) {
-    if (bad) {
-      sB[e] = make_double2(0.0, 0.0);
-    } else {
+  if (CB == NB) {
+    for (int e = tid; e < NP * NP; e += 512) {
+      if (bad) {
+        sB[e] = make_double2(0.0, 0.0);
+      } else {
+        const int i = e / NP, m = e % NP;
+        sB[sPi[i] * NP + sP[m]] = Bw[e];
+      }
+    }
+  } else {
+    // the part's columns only: entries of R whose column lands in [c0, c0 + CW)
+    for (int e = tid; e < NP * NP; e += 512) {
       const int i = e / NP, m = e % NP;
-      sB[sPi[i] * NP + sP[m]] = Bw[e];
+      if (bad) {
+        if (m < CW) sB[i * CW + m] = make_double2(0.0, 0.0);
+      } else {
+        const int c = sP[m] - c0;
+        if (c >= 0 && c < CW) sB[sPi[i] * CW + c] = Bw[e];
+      }
     }
   }
   __syncthreads();
@@ -446,7 +468,7 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, in
   const double nan = __builtin_nan("");
   // wave (q, h): 16-row blocks q, q+4, ... against the column blocks of half
   // h (JH blocks each), which keeps the accumulators to 3 * JH 16x16 blocks
-  constexpr int JH = (NB + 1) / 2;
+  constexpr int JH = (CB + 1) / 2;
   const int q = wv >> 1, hf = wv & 1;
   const int nrb = (M + 15) / 16;
   for (int rb = q; rb < nrb; rb += 4) {
@@ -468,9 +490,9 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, in
         const double as = av[u].x + av[u].y;
 #pragma unroll
         for (int J = 0; J < JH; ++J) {
-          const int JJ = hf * JH + J;
-          if (JJ < NB) {
-            const double2 bv = kk < NP ? sB[kk * NP + 16 * JJ + lr] : make_double2(0.0, 0.0);
+          const int JJ = hf * JH + J;   // block within the part
+          if (JJ < CB && c0 + 16 * JJ < NP) {
+            const double2 bv = kk < NP ? sB[kk * CW + 16 * JJ + lr] : make_double2(0.0, 0.0);
             P1[J] = mfma16(av[u].x, bv.x, P1[J]);
             P2[J] = mfma16(av[u].y, bv.y, P2[J]);
             P3[J] = mfma16(as, bv.x + bv.y, P3[J]);
@@ -480,11 +502,11 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, in
     }
 #pragma unroll
     for (int J = 0; J < JH; ++J) {
-      const int j = 16 * (hf * JH + J) + lr;
+      const int j = c0 + 16 * (hf * JH + J) + lr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * rb + 4 * v + lk;
-        if (hf * JH + J < NB && row < M && j < n) {
+        if (hf * JH + J < CB && row < M && j < n) {
           const double re = P1[J][v] - P2[J][v];
           const double im = P3[J][v] - P1[J][v] - P2[J][v];
           const double2 val = bad ? make_double2(nan, nan) : make_double2(re, im);
@@ -517,8 +539,8 @@ static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0,
   double2* O = reinterpret_cast<double2*>(work);
   int* perm = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + gt_perm_offset(n, nw));
   prof_mark(prof, "overlap_kernel");
-  hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nwc), dim3(256), 0, s, M, n, w0, trial, (const double2*)phi,
-                     O);
+  hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nwc), dim3(GtCfg<NB>::OT), 0, s, M, n, w0, trial,
+                     (const double2*)phi, O);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   prof_mark(prof, "invert_kernel");
@@ -527,8 +549,11 @@ static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0,
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t grid = 64 * ((nwc + 63) / 64);
+  // up to 96 orbitals O^{-1} fits the LDS whole; beyond, two column parts
+  constexpr int CB = NB <= 6 ? NB : (NB + 1) / 2;
+  constexpr int parts = (NB + CB - 1) / CB;
   prof_mark(prof, "apply_kernel");
-  hipLaunchKernelGGL(apply_kernel<NB>, dim3((unsigned)grid), dim3(512), 0, s, M, n, nw, w0, nwc,
+  hipLaunchKernelGGL((apply_kernel<NB, CB>), dim3((unsigned)grid, parts), dim3(512), 0, s, M, n, nw, w0, nwc,
                      (const double2*)phi, (const double2*)O, perm, info, (double2*)theta, orbital_major);
   return hipGetLastError();
 }
@@ -542,7 +567,8 @@ hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, int64_t w
   if (n <= 48) return launch_gt<3>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
   if (n <= 64) return launch_gt<4>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
   if (n <= 80) return launch_gt<5>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
-  return launch_gt<6>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 96) return launch_gt<6>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
+  return launch_gt<7>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
 }
 
 }  // namespace lofqmc

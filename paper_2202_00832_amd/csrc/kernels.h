@@ -117,10 +117,14 @@ hipError_t launch_hr_energy(hipStream_t s, int M, int n, int64_t nw, int npairs,
 hipError_t launch_gemm_setup(hipStream_t s, int Mr, int Nc, int K, const double* A, int64_t a_m, int64_t a_k,
                              const double* B, int64_t b_k, int64_t b_n, double* C, int64_t c_m, int64_t c_n,
                              const int64_t* bases, int batch);
+// orthonormal basis of the columns of each M x L block (L <= 64), in place
+hipError_t launch_orth(hipStream_t s, int M, int L, int nb, double* A, int64_t stride);
 // lbar[g][r][i] -> lbarT[i][g][r]
 hipError_t launch_lbar_transpose(hipStream_t s, int M, int n, int64_t X, const double* lbar, double* lbarT);
-// pack truncated SVD factors of a batch of column-major M x M problems
-hipError_t launch_pack_factors(hipStream_t s, int M, int nb, const double* U, const double* VT, const double* S,
+// pack truncated SVD factors of a batch of problems (K[b] <= kmax): U column-major
+// M x kmax (ld M), VT kmax x M with leading dimension vt_ld, S per problem
+hipError_t launch_pack_factors(hipStream_t s, int M, int nb, int kmax, const double* U, int64_t u_stride,
+                               const double* VT, int vt_ld, int64_t vt_stride, const double* S, int64_t s_stride,
                                const int* K, const int64_t* row_off, double* rows);
 
 }  // namespace lofqmc

@@ -62,7 +62,8 @@ struct lo_hr {
 namespace {
 
 constexpr int kMaxOcc = 64;     // FP64 full route
-constexpr int kMaxOccWide = 96;  // green_theta and the reduced-precision energies
+constexpr int kMaxOccWide = 96;  // the reduced-precision energies
+constexpr int kMaxOccTheta = 112;  // green_theta
 
 int fail(lo_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -293,8 +294,17 @@ int build_half_rotated_chol(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_cho
   return LO_OK;
 }
 
-int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar, double epsilon,
-                     lo_factors** out) {
+}  // extern "C"
+
+namespace {
+
+// Shared by the exact and the randomized factorisation.  L = 0: full SVD of
+// every pair block.  L > 0: randomized subspace iteration (Halko, Martinsson
+// and Tropp 2011, Alg. 4.4) with the caller's test matrix omega [M][L] (row-
+// major, device) and `power_iters` power steps, then the SVD of the L x M
+// projection.
+int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar, double epsilon,
+                  int64_t L, int power_iters, const double* omega, lo_factors** out) {
   if (!ctx) return LO_EINVAL;
   ctx->err.clear();
   if (!out) return fail(ctx, LO_EINVAL, "null output handle");
@@ -324,6 +334,7 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
   batch = std::min<int64_t>({batch, npairs, 512});
 
   double *d_lbarT = nullptr, *d_Y = nullptr, *d_U = nullptr, *d_VT = nullptr, *d_S = nullptr, *d_E = nullptr;
+  double *d_Z = nullptr, *d_W = nullptr, *d_B = nullptr, *d_UB = nullptr;
   int *d_info = nullptr, *d_K = nullptr;
   int64_t *d_bases = nullptr, *d_roff = nullptr;
   std::vector<double*> chunks;       // packed rows per batch
@@ -343,6 +354,10 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
     (void)hipFree(d_K);
     (void)hipFree(d_bases);
     (void)hipFree(d_roff);
+    (void)hipFree(d_Z);
+    (void)hipFree(d_W);
+    (void)hipFree(d_B);
+    (void)hipFree(d_UB);
     for (double* p : chunks) (void)hipFree(p);
   };
 #define TRY_HIP(call)                                                                           \
@@ -377,6 +392,15 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
   TRY_ALLOC(d_K, sizeof(int) * batch);
   TRY_ALLOC(d_bases, sizeof(int64_t) * 3 * batch);
   TRY_ALLOC(d_roff, sizeof(int64_t) * batch);
+  // randomized path: Z, W (M x L), B (L x M) and U_B (L x L) per pair
+  const size_t ml = (size_t)M * L;
+  if (L > 0) {
+    TRY_ALLOC(d_Z, sizeof(double) * ml * batch);
+    TRY_ALLOC(d_W, sizeof(double) * ml * batch);
+    TRY_ALLOC(d_B, sizeof(double) * ml * batch);
+    TRY_ALLOC(d_UB, sizeof(double) * (size_t)L * L * batch);
+  }
+  const int64_t kmax = L > 0 ? L : M;   // singular values per pair
 
   f = new lo_factors();
   f->M = M;
@@ -391,7 +415,7 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
   for (int i = 0; i < n; ++i)
     for (int j = i; j < n; ++j) plist.emplace_back(i, j);
 
-  std::vector<double> S_host(M * batch);
+  std::vector<double> S_host(kmax * batch);
   std::vector<int> info_host(batch), K_host(batch);
   std::vector<int64_t> bases(3 * batch), roff_host(batch);
   int64_t total_rows = 0;
@@ -408,17 +432,53 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
     // Y^[ij](r, s) = sum_g lbarT[i][g][r] lbarT[j][g][s], stored column-major
     TRY_HIP(lofqmc::launch_gemm_setup(ctx->stream, (int)M, (int)M, (int)n_chol, d_lbarT, 1, M, d_lbarT, M, 1, d_Y, 1,
                                       M, d_bases, nb));
-    rocblas_status st = rocsolver_dgesvd_strided_batched(
-        ctx->blas, rocblas_svect_singular, rocblas_svect_singular, (rocblas_int)M, (rocblas_int)M, d_Y,
-        (rocblas_int)M, (rocblas_stride)mm, d_S, (rocblas_stride)M, d_U, (rocblas_int)M, (rocblas_stride)mm, d_VT,
-        (rocblas_int)M, (rocblas_stride)mm, d_E, (rocblas_stride)M, rocblas_outofplace, d_info, nb);
+    rocblas_status st = rocblas_status_success;
+    if (L == 0) {
+      st = rocsolver_dgesvd_strided_batched(
+          ctx->blas, rocblas_svect_singular, rocblas_svect_singular, (rocblas_int)M, (rocblas_int)M, d_Y,
+          (rocblas_int)M, (rocblas_stride)mm, d_S, (rocblas_stride)M, d_U, (rocblas_int)M, (rocblas_stride)mm, d_VT,
+          (rocblas_int)M, (rocblas_stride)mm, d_E, (rocblas_stride)M, rocblas_outofplace, d_info, nb);
+    } else {
+      const double one = 1.0, zero = 0.0;
+      const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
+      auto gemm = [&](rocblas_operation ta, rocblas_operation tb, int64_t m, int64_t nn, int64_t k, const double* A,
+                      int64_t lda, int64_t sa, const double* Bm, int64_t ldb, int64_t sb, double* C, int64_t ldc,
+                      int64_t sc) {
+        return rocblas_dgemm_strided_batched(ctx->blas, ta, tb, (rocblas_int)m, (rocblas_int)nn, (rocblas_int)k, &one,
+                                             A, (rocblas_int)lda, sa, Bm, (rocblas_int)ldb, sb, &zero, C,
+                                             (rocblas_int)ldc, sc, nb);
+      };
+      // columns of an M x L block replaced by an orthonormal basis of their span
+      auto orth = [&](double* A) {
+        return lofqmc::launch_orth(ctx->stream, (int)M, (int)L, nb, A, (int64_t)ml) == hipSuccess
+                   ? rocblas_status_success
+                   : rocblas_status_internal_error;
+      };
+      // Z = Y Omega (omega is row-major M x L, i.e. column-major L x M)
+      st = gemm(N_, T_, M, L, M, d_Y, M, mm, omega, L, 0, d_Z, M, ml);
+      for (int q = 0; q < power_iters && st == rocblas_status_success; ++q) {
+        st = orth(d_Z);
+        if (st == rocblas_status_success) st = gemm(T_, N_, M, L, M, d_Y, M, mm, d_Z, M, ml, d_W, M, ml);  // Y^T Q
+        if (st == rocblas_status_success) st = orth(d_W);
+        if (st == rocblas_status_success) st = gemm(N_, N_, M, L, M, d_Y, M, mm, d_W, M, ml, d_Z, M, ml);  // Y Q'
+      }
+      if (st == rocblas_status_success) st = orth(d_Z);                                           // Q
+      if (st == rocblas_status_success) st = gemm(T_, N_, L, M, M, d_Z, M, ml, d_Y, M, mm, d_B, L, ml);   // Q^T Y
+      if (st == rocblas_status_success)
+        st = rocsolver_dgesvd_strided_batched(
+            ctx->blas, rocblas_svect_singular, rocblas_svect_singular, (rocblas_int)L, (rocblas_int)M, d_B,
+            (rocblas_int)L, (rocblas_stride)ml, d_S, (rocblas_stride)L, d_UB, (rocblas_int)L,
+            (rocblas_stride)(L * L), d_VT, (rocblas_int)L, (rocblas_stride)ml, d_E, (rocblas_stride)L,
+            rocblas_outofplace, d_info, nb);
+      if (st == rocblas_status_success) st = gemm(N_, N_, M, L, L, d_Z, M, ml, d_UB, L, L * L, d_U, M, ml);  // Q U_B
+    }
     if (st != rocblas_status_success) {
-      rc = fail(ctx, LO_ESOLVER, "rocsolver_dgesvd_strided_batched returned %d", (int)st);
+      rc = fail(ctx, LO_ESOLVER, "rocBLAS/rocSOLVER call of the pair-block decomposition returned %d", (int)st);
       cleanup();
       free_factors(f);
       return rc;
     }
-    TRY_HIP(hipMemcpyAsync(S_host.data(), d_S, sizeof(double) * M * nb, hipMemcpyDeviceToHost, ctx->stream));
+    TRY_HIP(hipMemcpyAsync(S_host.data(), d_S, sizeof(double) * kmax * nb, hipMemcpyDeviceToHost, ctx->stream));
     TRY_HIP(hipMemcpyAsync(info_host.data(), d_info, sizeof(int) * nb, hipMemcpyDeviceToHost, ctx->stream));
     TRY_HIP(hipStreamSynchronize(ctx->stream));
     int64_t batch_rows = 0;
@@ -429,20 +489,28 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
         free_factors(f);
         return rc;
       }
-      const double* s = S_host.data() + (size_t)b * M;
+      const double* s = S_host.data() + (size_t)b * kmax;
       int K = 0;
       if (epsilon == 0.0) {
-        K = (int)M;
+        K = (int)kmax;
       } else {
-        while (K < M && s[K] >= epsilon) ++K;
+        while (K < kmax && s[K] >= epsilon) ++K;
       }
       const auto [i, j] = plist[p0 + b];
+      if (L > 0 && K == kmax && kmax < M) {
+        rc = fail(ctx, LO_EUNSUPPORTED,
+                  "pair (%d, %d): all %d sketched singular values reach epsilon; a larger sketch is needed", i, j,
+                  (int)kmax);
+        cleanup();
+        free_factors(f);
+        return rc;
+      }
       f->ranks[i * n + j] = f->ranks[j * n + i] = K;
-      const double fd = (K < M) ? s[K] : 0.0;
+      const double fd = (K < kmax) ? s[K] : 0.0;
       f->first_dropped[i * n + j] = f->first_dropped[j * n + i] = fd;
       {
         double mass = 0.0;
-        for (int64_t k = K; k < M; ++k) mass += s[k];
+        for (int64_t k = K; k < kmax; ++k) mass += s[k];
         f->discarded[i * n + j] = f->discarded[j * n + i] = mass;
       }
       f->row_offset[i * n + j] = total_rows + batch_rows;
@@ -457,7 +525,12 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
       chunk_rows.push_back(batch_rows);
       TRY_HIP(hipMemcpyAsync(d_K, K_host.data(), sizeof(int) * nb, hipMemcpyHostToDevice, ctx->stream));
       TRY_HIP(hipMemcpyAsync(d_roff, roff_host.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, ctx->stream));
-      TRY_HIP(lofqmc::launch_pack_factors(ctx->stream, (int)M, nb, d_U, d_VT, d_S, d_K, d_roff, dst));
+      if (L == 0)
+        TRY_HIP(lofqmc::launch_pack_factors(ctx->stream, (int)M, nb, (int)M, d_U, (int64_t)mm, d_VT, (int)M,
+                                            (int64_t)mm, d_S, M, d_K, d_roff, dst));
+      else
+        TRY_HIP(lofqmc::launch_pack_factors(ctx->stream, (int)M, nb, (int)L, d_U, (int64_t)ml, d_VT, (int)L,
+                                            (int64_t)ml, d_S, L, d_K, d_roff, dst));
       TRY_HIP(hipStreamSynchronize(ctx->stream));  // host vectors are reused by the next batch
     }
     total_rows += batch_rows;
@@ -580,6 +653,29 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, cons
   return LO_OK;
 #undef TRY_HIP
 #undef TRY_ALLOC
+}
+
+}  // namespace
+
+extern "C" {
+
+int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar, double epsilon,
+                     lo_factors** out) {
+  return build_factors(ctx, M, n_occ, n_chol, lbar, epsilon, 0, 0, nullptr, out);
+}
+
+int build_lo_factors_randomized(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar,
+                                double epsilon, int64_t sketch, int power_iters, const double* omega,
+                                lo_factors** out) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (out) *out = nullptr;
+  if (sketch <= 0 || sketch > M) return fail(ctx, LO_EINVAL, "sketch must be in 1..M");
+  if (sketch > 64) return fail(ctx, LO_EUNSUPPORTED, "sketch above 64");
+  if (power_iters < 0 || power_iters > 16) return fail(ctx, LO_EINVAL, "power_iters must be in 0..16");
+  if (!(epsilon > 0.0) || std::isinf(epsilon)) return fail(ctx, LO_EINVAL, "epsilon must be finite and > 0");
+  if (!omega) return fail(ctx, LO_EINVAL, "null omega");
+  return build_factors(ctx, M, n_occ, n_chol, lbar, epsilon, sketch, power_iters, omega, out);
 }
 
 int lo_factors_destroy(lo_factors* f) {
@@ -729,7 +825,7 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   ctx->err.clear();
   if (M <= 0 || n_occ <= 0 || nw < 0) return fail(ctx, LO_EINVAL, "sizes must be M > 0, n_occ > 0, nw >= 0");
   if (n_occ > M) return fail(ctx, LO_EINVAL, "n_occ exceeds M");
-  if (n_occ > kMaxOccWide) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d", kMaxOccWide);
+  if (n_occ > kMaxOccTheta) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d", kMaxOccTheta);
   if (M > (1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "M above 2^24");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
   if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);

@@ -106,30 +106,107 @@ hipError_t launch_lbar_transpose(hipStream_t s, int M, int n, int64_t X, const d
 // Factor rows of batch entry b (rank K, first row row_off): rows K of
 // Ubar^T = (U Sigma^(1/2))^T, then K rows of Vbar = Sigma^(1/2) V.
 // U and VT are column-major M x M (LAPACK convention of the SVD routine).
-__global__ __launch_bounds__(256) void pack_factors_kernel(int M, const double* __restrict__ U,
-                                                           const double* __restrict__ VT,
-                                                           const double* __restrict__ S, const int* __restrict__ Kb,
+// Row k of the packed block of problem b: k < K is column k of U scaled by
+// sqrt(S_k), K <= k < 2K is row k - K of VT scaled the same way.  U is
+// column-major with leading dimension M (problem stride u_stride), VT has
+// leading dimension vt_ld (problem stride vt_stride), S problem stride s_stride.
+__global__ __launch_bounds__(256) void pack_factors_kernel(int M, const double* __restrict__ U, int64_t u_stride,
+                                                           const double* __restrict__ VT, int vt_ld,
+                                                           int64_t vt_stride, const double* __restrict__ S,
+                                                           int64_t s_stride, const int* __restrict__ Kb,
                                                            const int64_t* __restrict__ row_off,
                                                            double* __restrict__ rows) {
   const int b = blockIdx.y;
   const int k = blockIdx.x;
   const int K = Kb[b];
   if (k >= 2 * K) return;
-  const size_t mm = (size_t)M * M;
   const int kk = (k < K) ? k : k - K;
-  const double sq = sqrt(S[(size_t)b * M + kk]);
+  const double sq = sqrt(S[(size_t)b * s_stride + kk]);
   double* dst = rows + (size_t)(row_off[b] + k) * M;
   for (int r = threadIdx.x; r < M; r += blockDim.x) {
-    const double v = (k < K) ? U[b * mm + (size_t)kk * M + r] : VT[b * mm + (size_t)r * M + kk];
+    const double v = (k < K) ? U[b * u_stride + (size_t)kk * M + r] : VT[b * vt_stride + (size_t)r * vt_ld + kk];
     dst[r] = v * sq;
   }
 }
 
-hipError_t launch_pack_factors(hipStream_t s, int M, int nb, const double* U, const double* VT, const double* S,
+hipError_t launch_pack_factors(hipStream_t s, int M, int nb, int kmax, const double* U, int64_t u_stride,
+                               const double* VT, int vt_ld, int64_t vt_stride, const double* S, int64_t s_stride,
                                const int* K, const int64_t* row_off, double* rows) {
-  if (nb <= 0) return hipSuccess;
-  dim3 grid(2 * M, nb);
-  hipLaunchKernelGGL(pack_factors_kernel, grid, dim3(256), 0, s, M, U, VT, S, K, row_off, rows);
+  if (nb <= 0 || kmax <= 0) return hipSuccess;
+  dim3 grid(2 * kmax, nb);
+  hipLaunchKernelGGL(pack_factors_kernel, grid, dim3(256), 0, s, M, U, u_stride, VT, vt_ld, vt_stride, S, s_stride,
+                     K, row_off, rows);
+  return hipGetLastError();
+}
+
+// Columns of each M x L block (column-major, ld M) replaced by an orthonormal
+// basis of their span, column by column: classical Gram-Schmidt passes, each
+// followed by a normalisation, repeated until a pass keeps at least half of
+// the norm (at least two passes; the usual reorthogonalisation test).  A
+// column that is lost in the span of the earlier ones (its projection falls
+// below 1e-12 of its norm, as happens where the sketch is wider than the
+// block's numerical rank) is replaced by a unit vector and orthogonalised in
+// turn, so Q stays orthonormal also for rank-deficient blocks.  One workgroup
+// per block; every projection coefficient and norm is a wave reduction in a
+// fixed order, so every decision is uniform over the workgroup.
+__global__ __launch_bounds__(256) void orth_kernel(int M, int L, double* __restrict__ A, int64_t stride) {
+  __shared__ double sDot[64];
+  __shared__ double sNorm;
+  double* Z = A + blockIdx.x * stride;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  auto norm2 = [&](const double* z) {
+    if (wv == 0) {
+      double d = 0.0;
+      for (int r = lane; r < M; r += 64) d += z[r] * z[r];
+      d = wave_sum_lane0(d);
+      if (lane == 0) sNorm = d;
+    }
+    __syncthreads();
+    const double v = sqrt(sNorm);
+    __syncthreads();
+    return v;
+  };
+  for (int k = 0; k < L; ++k) {
+    double* zk = Z + (size_t)k * M;
+    double before = norm2(zk);
+    int fresh = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+      // coefficients q_j . z_k, j < k: wave wv takes j = wv, wv + 4, ...
+      for (int j = wv; j < k; j += 4) {
+        const double* qj = Z + (size_t)j * M;
+        double d = 0.0;
+        for (int r = lane; r < M; r += 64) d += qj[r] * zk[r];
+        d = wave_sum_lane0(d);
+        if (lane == 0) sDot[j] = d;
+      }
+      __syncthreads();
+      for (int r = tid; r < M; r += 256) {
+        double v = zk[r];
+        for (int j = 0; j < k; ++j) v -= sDot[j] * Z[(size_t)j * M + r];
+        zk[r] = v;
+      }
+      __syncthreads();
+      const double after = norm2(zk);
+      if (!(after > 1e-12 * before)) {
+        // lost in the span: restart from unit vector e_m
+        const int m = (k + fresh++) % M;
+        for (int r = tid; r < M; r += 256) zk[r] = r == m ? 1.0 : 0.0;
+        __syncthreads();
+        before = 1.0;
+        continue;
+      }
+      const double inv = 1.0 / after;
+      for (int r = tid; r < M; r += 256) zk[r] *= inv;
+      __syncthreads();
+      if (pass > 0 && after >= 0.5 * before) break;
+      before = 1.0;
+    }
+  }
+}
+
+hipError_t launch_orth(hipStream_t s, int M, int L, int nb, double* A, int64_t stride) {
+  if (nb <= 0 || L <= 0) return hipSuccess;
+  hipLaunchKernelGGL(orth_kernel, dim3(nb), dim3(256), 0, s, M, L, A, stride);
   return hipGetLastError();
 }
 

@@ -34,6 +34,8 @@ _SIGS = {
     "lo_profile_summary": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, ctypes.POINTER(ctypes.c_int)]),
     "build_half_rotated_chol": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p]),
     "build_lo_factors": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, ctypes.c_double, ctypes.POINTER(_c_p)]),
+    "build_lo_factors_randomized": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, ctypes.c_double, _i64, ctypes.c_int,
+                                                    _c_p, ctypes.POINTER(_c_p)]),
     "lo_factors_destroy": (ctypes.c_int, [_c_p]),
     "lo_factors_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "lo_factors_export": (ctypes.c_int, [_c_p, _c_p, _c_p]),
@@ -352,6 +354,17 @@ class Context:
         _check_dev("lbar", lbar, torch.float64, (X, M, n))
         h = ctypes.c_void_p()
         self._check(self._lib.build_lo_factors(self._h, M, n, X, _ptr(lbar), float(epsilon), ctypes.byref(h)))
+        return Factors(h.value)
+
+    def build_lo_factors_randomized(self, lbar, epsilon: float, omega, power_iters: int = 2) -> Factors:
+        """LO factors from a randomized SVD with the test matrix omega [M][sketch] (float64, device)."""
+        import torch
+        X, M, n = lbar.shape
+        _check_dev("lbar", lbar, torch.float64, (X, M, n))
+        _check_dev("omega", omega, torch.float64, (M, omega.shape[1]))
+        h = ctypes.c_void_p()
+        self._check(self._lib.build_lo_factors_randomized(self._h, M, n, X, _ptr(lbar), float(epsilon), omega.shape[1],
+                                                          int(power_iters), _ptr(omega), ctypes.byref(h)))
         return Factors(h.value)
 
     def build_hr_eri(self, lbar) -> HrEri:

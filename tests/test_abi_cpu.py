@@ -40,7 +40,7 @@ def test_validation_errors_need_no_device(lib):
         assert lib.green_theta(None, 4, 2, 1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert lib.green_theta(h, 0, 2, 1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert lib.green_theta(h, 4, 5, 1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL   # n > M
-        assert lib.green_theta(h, 100, 97, 1, fake, fake, fake, None, fake, 0) == L.LO_EUNSUPPORTED
+        assert lib.green_theta(h, 200, 113, 1, fake, fake, fake, None, fake, 0) == L.LO_EUNSUPPORTED
         assert lib.local_energy_full(h, 100, 65, 3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EUNSUPPORTED
         assert lib.local_energy_full(h, 100, 97, 3, 4, fake, fake, None, L.LO_FP32, 0, fake) == L.LO_EUNSUPPORTED
         assert lib.green_theta(h, 8, 2, -1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL
@@ -65,6 +65,14 @@ def test_validation_errors_need_no_device(lib):
         assert lib.build_half_rotated_chol(h, 8, 2, 0, None, None, None) == L.LO_OK  # nothing to do
         assert lib.lo_factors_info(None, None, None, None, None, None, None) == L.LO_EINVAL
         assert lib.lo_factors_destroy(None) == L.LO_OK
+        # randomized LO set-up
+        R = lib.build_lo_factors_randomized
+        assert R(h, 8, 2, 3, fake, 1e-4, 0, 2, fake, ctypes.byref(out)) == L.LO_EINVAL        # sketch 0
+        assert R(h, 8, 2, 3, fake, 1e-4, 9, 2, fake, ctypes.byref(out)) == L.LO_EINVAL        # sketch > M
+        assert R(h, 100, 2, 3, fake, 1e-4, 65, 2, fake, ctypes.byref(out)) == L.LO_EUNSUPPORTED
+        assert R(h, 8, 2, 3, fake, 0.0, 4, 2, fake, ctypes.byref(out)) == L.LO_EINVAL         # eps must be > 0
+        assert R(h, 8, 2, 3, fake, 1e-4, 4, -1, fake, ctypes.byref(out)) == L.LO_EINVAL
+        assert R(h, 8, 2, 3, fake, 1e-4, 4, 2, None, ctypes.byref(out)) == L.LO_EINVAL        # null omega
         # half-rotated ERI route
         assert lib.build_hr_eri(h, 8, 2, 3, fake, None) == L.LO_EINVAL
         assert lib.build_hr_eri(h, 8, 9, 3, fake, ctypes.byref(out)) == L.LO_EINVAL      # n > M
