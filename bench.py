@@ -277,33 +277,52 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
     return out
 
 
-def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, steps=2000, step_sigma=0.005):
-    """Learned correction of the LO energy on the 400-site chain at eps: walker
-    pairs (E_full, E_LO) along 512 random walks from the trial, training on the
-    GPU, held-out error with and without the correction (the held-out pairs are
-    whole walks, so train and test come from the same distribution of walkers),
-    and the checked corrected-LO throughput."""
+def residual_study(torch, lofqmc, synth, n_train=20480, n_test=2048, steps=2000, step_sigma=0.005, sketch=24):
+    """Learned correction of the LO energy on the 800-site chain (100 orbitals
+    per spin, 2048 walkers, eps = 1e-3): LO factors from the randomized SVD,
+    exact energies from the half-rotated ERI route, walker pairs along random
+    walks from the trial, training on the GPU, held-out error with and without
+    the correction (the held-out pairs are whole walks), and the checked
+    corrected-LO throughput."""
     from paper_2202_00832_amd import residual as RES
-    cfg = synth.CHAIN_POLYACENE
+    cfg = synth.CHAIN_RESIDUAL
+    eps = cfg.epsilons[0]
+    log("residual study: generating %s" % cfg.name)
     base = synth.make_system(cfg, nw=1)
+    M, n, nb = cfg.M, cfg.n, cfg.nw
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     ctx = lofqmc.Context()
     trial_d = dev(base.trial)
-    lbar = ctx.build_half_rotated_chol(dev(base.chol), trial_d)
-    f = ctx.build_lo_factors(lbar, eps)
+    chol_d = dev(base.chol)
+    lbar = ctx.build_half_rotated_chol(chol_d, trial_d)
+    del chol_d
     rng = np.random.default_rng(2025)
+    t0 = time.perf_counter()
+    omega = dev(rng.standard_normal((M, sketch)))
+    f = ctx.build_lo_factors_randomized(lbar, eps, omega, power_iters=2)
+    torch.cuda.synchronize()
+    factor_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hr = ctx.build_hr_eri(lbar)
+    torch.cuda.synchronize()
+    hr_s = time.perf_counter() - t0
+    exact = lambda th, inf: ctx.local_energy_hr(hr, th, inf)  # noqa: E731
+    ranks = f.info()["ranks"]
+    log("residual study: randomized LO factors %.2f s (<K> = %.3f), pair blocks %.1f GB %.2f s"
+        % (factor_s, ranks.mean(), hr.bytes / 1e9, hr_s))
     # walker pairs along random walks phi <- QR(phi + s (Z1 + i Z2)) from the
     # trial (a stand-in for the propagation), one pair per walker and step
-    nb = 512
     nsteps = -(-(n_train + n_test) // nb)
-    phi = np.repeat(base.trial[None].astype(np.complex128), nb, axis=0)
+    gen = torch.Generator(device="cuda").manual_seed(2025)
+    phi = trial_d.to(torch.complex128).unsqueeze(0).repeat(nb, 1, 1)
     X, Y = [], []
     t0 = time.perf_counter()
     for _ in range(nsteps):
-        noise = step_sigma * (rng.standard_normal(phi.shape) + 1j * rng.standard_normal(phi.shape))
-        phi = np.stack([np.linalg.qr(p_ + z)[0] for p_, z in zip(phi, noise)])
-        theta, _, info = ctx.green_theta(trial_d, dev(phi))
-        ef = ctx.local_energy_full(lbar, theta, info).sum(dim=1)
+        z = torch.complex(torch.randn(phi.shape, dtype=torch.float64, device="cuda", generator=gen),
+                          torch.randn(phi.shape, dtype=torch.float64, device="cuda", generator=gen))
+        phi = torch.linalg.qr(phi + step_sigma * z)[0].contiguous()
+        theta, _, info = ctx.green_theta(trial_d, phi)
+        ef = exact(theta, info).sum(dim=1)
         el = ctx.local_energy_lo(f, theta, info).sum(dim=1)
         X.append(ctx.residual_features(f, theta))
         Y.append(((ef - el).real * RES.MHA).contiguous())
@@ -317,6 +336,7 @@ def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, s
     ytr = y[:, tr].reshape(-1).contiguous()
     xte = x[:, te].reshape(-1, *x.shape[2:]).contiguous()
     yte = y[:, te].reshape(-1).contiguous()
+    del X, x
     model = RES.ResidualModel(ctx, RES.init_params(xtr.cpu().numpy(), ctx.residual_nparam(), seed=0))
     t0 = time.perf_counter()
     losses = model.train(xtr, ytr, steps=steps, lr=1e-3, batch=1024)
@@ -324,7 +344,7 @@ def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, s
     train_s = time.perf_counter() - t0
     pred = model.predict_mha(xte, lofqmc.LO_BF16)
     yh, ph = yte.cpu().numpy(), pred.cpu().numpy()
-    est = RES.CorrectedLO(ctx, f, lbar, model, bound_mha=0.2, check_every=10, check_walkers=64)
+    est = RES.CorrectedLO(ctx, f, lbar, model, bound_mha=0.2, check_every=10, check_walkers=64, reference=exact)
     th = theta   # the last step of every walk
     est(th)   # first call checks
     e0 = torch.cuda.Event(enable_timing=True)
@@ -336,7 +356,10 @@ def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, s
     e1.record()
     torch.cuda.synchronize()
     corr_ms = e0.elapsed_time(e1) / reps
-    out = {"workload": cfg.name, "epsilon": eps, "walks": nb, "walk_steps": nsteps, "step_sigma": step_sigma,
+    out = {"workload": cfg.name, "M": M, "n_occ": n, "n_chol": base.n_chol, "epsilon": eps,
+           "factors": "randomized SVD, sketch %d, 2 power steps" % sketch, "factor_build_s": round(factor_s, 2),
+           "mean_rank": float(ranks.mean()), "exact_route": "half-rotated ERI (Eq. 17)",
+           "walks": nb, "walk_steps": nsteps, "step_sigma": step_sigma,
            "train_pairs": int(ytr.numel()), "test_pairs": int(yte.numel()), "test_walks": n_test_walks,
            "pair_generation_s": round(gen_s, 2), "train_steps": steps, "train_s": round(train_s, 2),
            "loss_first_last_standardised": [float(losses[0]), float(np.mean(losses[-50:]))],
@@ -344,9 +367,10 @@ def residual_study(torch, lofqmc, synth, eps=1e-3, n_train=20480, n_test=2048, s
                                "corrected": float(np.sqrt(np.mean((yh - ph) ** 2)))},
            "heldout_max_abs_mHa": {"plain_lo": float(np.abs(yh).max()), "corrected": float(np.abs(yh - ph).max())},
            "check": est.last_check,
-           "corrected_lo_ms_per_call_512_walkers": round(corr_ms, 3)}
+           "corrected_lo_ms_per_call": round(corr_ms, 3)}
     log("residual: held-out RMS %.3f -> %.3f mHa, mode %s" % (out["heldout_rms_mHa"]["plain_lo"],
                                                              out["heldout_rms_mHa"]["corrected"], est.mode))
+    hr.close()
     f.close()
     ctx.close()
     return out
@@ -388,7 +412,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the multi-system batching study (8 chain systems, captured graph)")
     ap.add_argument("--no-residual", action="store_true",
-                    help="skip the learned-residual study")
+                    help="skip the learned-residual study (800-site chain: about 30 GB of device memory)")
     ap.add_argument("--no-hr", action="store_true",
                     help="skip the half-rotated ERI route (Eq. 17; its pair blocks take 2.3 GB)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,

@@ -418,8 +418,9 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, in
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int part = blockIdx.y;
-  const int c0 = CW * part;                    // first column of the part
+  // first column of the part (a compile-time 0 with a single part, which
+  // keeps the indexing and the bounds below static)
+  const int c0 = CB == NB ? 0 : CW * (int)blockIdx.y;
   // workgroups go round-robin over the 8 XCDs; walkers 8g .. 8g+7 share an
   // XCD so that their interleaved orbital-major 16-byte stores meet in one L2
   int64_t w;

@@ -87,17 +87,22 @@ class ResidualModel:
 
 class CorrectedLO:
     """E = E_LO + sum_i f(x_i), checked every `check_every` evaluations against
-    the full route on `check_walkers` sampled walkers.
+    an exact route on `check_walkers` sampled walkers.
 
-    After a check, `mode` is "corrected" if the largest |Re(E_full - E)| of the
-    sample is at most `bound_mha`; otherwise "lo" if plain LO's largest error is
-    at most `lo_gate_mha`, else "full".  The returned energies follow the mode
-    (the full route is then evaluated for every walker).
+    The exact route is the Cholesky route with `lbar` (up to 64 orbitals), or
+    any callable `reference(theta, info) -> energies [nw][2]`, e.g. the
+    half-rotated ERI route.  After a check, `mode` is "corrected" if the
+    largest |Re(E_exact - E)| of the sample is at most `bound_mha`; otherwise
+    "lo" if plain LO's largest error is at most `lo_gate_mha`, else "full".
+    The returned energies follow the mode (the exact route is then evaluated
+    for every walker).
     """
 
     def __init__(self, ctx, factors, lbar, model: ResidualModel, bound_mha=0.2, lo_gate_mha=1.0, check_every=10,
-                 check_walkers=64, seed=0):
+                 check_walkers=64, seed=0, reference=None):
         self.ctx, self.factors, self.lbar, self.model = ctx, factors, lbar, model
+        self.reference = reference if reference is not None else \
+            (lambda theta, info: ctx.local_energy_full(lbar, theta, info))
         self.bound, self.lo_gate = bound_mha, lo_gate_mha
         self.check_every, self.check_walkers = check_every, check_walkers
         self.rng = np.random.default_rng(seed)
@@ -112,7 +117,7 @@ class CorrectedLO:
         idx = torch.from_numpy(np.sort(self.rng.choice(nw, k, replace=False))).to(theta.device)
         th = theta.index_select(0, idx).contiguous()
         inf = info.index_select(0, idx).contiguous() if info is not None else None
-        ef = self.ctx.local_energy_full(self.lbar, th, inf).sum(dim=1).real.cpu().numpy()
+        ef = self.reference(th, inf).sum(dim=1).real.cpu().numpy()
         el = e_lo.index_select(0, idx).sum(dim=1).real.cpu().numpy()
         pr = pred_mha.index_select(0, idx).cpu().numpy() / MHA
         err_c = float(np.max(np.abs(ef - (el + pr))) * MHA)
@@ -138,4 +143,4 @@ class CorrectedLO:
             return e_lo.sum(dim=1) + pred.to(e_lo.dtype) / MHA
         if self.mode == "lo":
             return e_lo.sum(dim=1)
-        return self.ctx.local_energy_full(self.lbar, theta, info).sum(dim=1)
+        return self.reference(theta, info).sum(dim=1)

@@ -196,7 +196,10 @@ CHAIN_POLYACENE = ChainConfig("chain-M400-n60-w512", 400, 60, 512, 1e-5, 0.2, 10
 CHAIN_PRECISION = ChainConfig("chain-M500-n48-w1024", 500, 48, 1024, 1e-5, 0.2, 1003,
                               epsilons=(1e-4,))
 
-CONFIGS = {c.name: c for c in (CHAIN_SMALL, CHAIN_POLYACENE, CHAIN_PRECISION)}
+# Learned-residual size: 800 sites, 100 orbitals per spin, 2048 walkers, LO at 1e-3.
+CHAIN_RESIDUAL = ChainConfig("chain-M800-n100-w2048", 800, 100, 2048, 1e-5, 0.2, 1005, epsilons=(1e-3,))
+
+CONFIGS = {c.name: c for c in (CHAIN_SMALL, CHAIN_POLYACENE, CHAIN_PRECISION, CHAIN_RESIDUAL)}
 
 
 def batch_configs(count: int = 8, seed: int = 4004, m_range=(100, 600), w_range=(64, 512)) -> list:
