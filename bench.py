@@ -553,6 +553,11 @@ def main():
     hr_out = None
     if not args.no_hr:
         hr_out = hr_study(torch, ctx, lbar, trial_d, phi_d, info, energy, e_full_h, work, M, n, nw)
+        # the paper's comparison (Sec. 3, dodecane): LO against the HR-ERI
+        # energy evaluation at each threshold, energy call alone and whole step
+        hr_out["lo_speedup"] = {
+            "%g" % s["epsilon"]: {"energy_only": round(hr_out["local_energy_hr_ms"] / s["local_energy_lo_ms"], 1),
+                                  "step": round(hr_out["ms_per_step"] / s["ms_per_step"], 1)} for s in sweep}
 
     prec = None
     if not args.no_precision:

@@ -138,9 +138,12 @@ int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol,
  * iteration (Halko, Martinsson and Tropp, SIAM Rev. 53 (2011), Alg. 4.4),
  *   Z = Y Omega, then power_iters times Q = orth(Z), Q' = orth(Y^T Q),
  *   Z = Y Q'; Q = orth(Z); B = Q^T Y = U_B Sigma V; U = Q U_B,
- * with orth a twice-applied Gram-Schmidt.  Singular values of B with sigma >= epsilon are
- * kept as in build_lo_factors; the set-up costs O(M^2 sketch) per pair
- * instead of O(M^3).
+ * with orth a classical Gram-Schmidt repeated on each column until a pass
+ * keeps at least half of its norm (two to eight passes); a column that falls
+ * to 1e-12 of its norm (a rank-deficient sketch) is replaced by a unit vector
+ * (e_k, then e_k+1, ... while they too fall in the span) and orthogonalised.
+ * Singular values of B with sigma >= epsilon are kept as in build_lo_factors;
+ * the set-up costs O(M^2 sketch) per pair instead of O(M^3).
  *   sketch      : columns of the test matrix, 1 <= sketch <= min(M, 64); if every one of
  *                 the sketch singular values of some pair reaches epsilon the
  *                 call fails with LO_EUNSUPPORTED (a larger sketch is needed)
