@@ -15,8 +15,11 @@ Auxiliary-Field Quantum Monte Carlo" (arXiv 2202.00832):
                 (Eq. 17), pair SVD compression (Sec. 2.3.1, Eq. 18) and the LO
                 energy (Sec. 2.3.2, Eq. 19 and Eq. 22), plus the a-priori error
                 bound of the truncation.
+* ``multidet`` - multi-determinant (CAS-type) trials: the weighted sum of
+                Eq. 12 by its definition, and the LO energy by the
+                Sherman-Morrison-Woodbury steps of Eq. 20-23.
 
 Every function is plain numpy in float64 / complex128, without blocking,
 fusion or reordering beyond what the equations state.
 """
-from . import energy, fock  # noqa: F401
+from . import energy, fock, multidet  # noqa: F401

@@ -77,12 +77,22 @@ def spin_orbital_matrix(phi_alpha: np.ndarray, phi_beta: np.ndarray) -> np.ndarr
 
 def mixed_energy(eri: np.ndarray, trial_alpha, trial_beta, phi_alpha, phi_beta):
     """Returns (E2, <Psi_T|phi>) from the Fock-space expansion."""
+    return mixed_energy_multi(eri, [(trial_alpha, trial_beta)], [1.0], phi_alpha, phi_beta)
+
+
+def mixed_energy_multi(eri: np.ndarray, trial_dets, coeffs, phi_alpha, phi_beta):
+    """(E2, <Psi_T|phi>) for the multi-determinant trial
+    Psi_T = sum_d c_d |D_d^alpha D_d^beta> (Sec. 2.1.1, Eq. 12), with
+    trial_dets a list of (D_alpha, D_beta) orbital matrices: the trial's
+    occupation-number amplitudes are the c_d-weighted sum of the determinants'."""
     M = eri.shape[0]
     n_so = 2 * M
-    n_el = trial_alpha.shape[1] + trial_beta.shape[1]
+    n_el = trial_dets[0][0].shape[1] + trial_dets[0][1].shape[1]
     strings, ann1 = _annihilators(n_so, n_el)
     _, ann2 = _annihilators(n_so, n_el - 1)
-    t = determinant_amplitudes(spin_orbital_matrix(trial_alpha, trial_beta), strings)
+    t = np.zeros(len(strings), dtype=np.complex128)
+    for (da, db), c in zip(trial_dets, coeffs):
+        t += c * determinant_amplitudes(spin_orbital_matrix(da, db), strings)
     f = determinant_amplitudes(spin_orbital_matrix(phi_alpha, phi_beta), strings)
     # u[P,Q] = c_Q c_P |Psi_T>, v[R,S] = c_S c_R |phi>  (vectors in the N-2 sector)
     u = np.empty((n_so, n_so, ann2[0].shape[0]), dtype=np.complex128)

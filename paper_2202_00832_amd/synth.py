@@ -202,6 +202,116 @@ CHAIN_RESIDUAL = ChainConfig("chain-M800-n100-w2048", 800, 100, 2048, 1e-5, 0.2,
 CONFIGS = {c.name: c for c in (CHAIN_SMALL, CHAIN_POLYACENE, CHAIN_PRECISION, CHAIN_RESIDUAL)}
 
 
+# ----------------------------------------------------------------------------
+# Multi-determinant (CAS-type) trials
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class CasConfig:
+    name: str
+    M: int            # basis functions
+    n: int            # occupied orbitals per spin in each determinant
+    n_act_occ: int    # active orbitals occupied in the reference determinant
+    n_act_virt: int   # active orbitals empty in the reference determinant
+    n_det: int        # determinants, the reference included
+    max_exc: int      # largest excitation level
+    nw: int           # walkers
+    chol_tol: float
+    sigma: float
+    seed: int
+    epsilon: float = 1e-5
+
+    @property
+    def n_cas(self) -> int:
+        return self.n + self.n_act_virt
+
+
+# Small CAS case: 48 sites, 8 occupied + 3 active virtual orbitals, 3 active
+# occupied, all 20 determinants up to triples, 16 walkers.
+CAS_SMALL = CasConfig("cas-M48-n8-a3x3-d20-w16", 48, 8, 3, 3, 20, 3, 16, 1e-6, 0.1, 2001)
+# Polyacene-scale CAS case: 400 sites, 60 occupied + 5 active virtual orbitals,
+# 5 active occupied, 200 determinants up to quadruples, 512 walkers.
+CAS_POLYACENE = CasConfig("cas-M400-n60-a5x5-d200-w512", 400, 60, 5, 5, 200, 4, 512, 1e-5, 0.2, 2002)
+
+
+def cas_orbitals(M: int, n: int, n_act_occ: int, n_act_virt: int) -> np.ndarray:
+    """M x (n + n_act_virt) orthonormal localized orbitals (Lowdin Gaussians).
+
+    Columns 0 .. n-1 are the reference determinant's orbitals, the last
+    n_act_occ of them active; columns n .. are the active virtual orbitals.
+    The active orbitals are spread along the chain (evenly spaced centres,
+    alternately occupied and virtual) rather than bunched at one end.
+    """
+    n_cas = n + n_act_virt
+    C = lowdin_gaussian_trial(M, n_cas)
+    n_act = n_act_occ + n_act_virt
+    act = [int(round(x)) for x in np.linspace(0, n_cas - 1, n_act)]
+    occ_act, virt_act = [], []
+    for k, c in enumerate(act):
+        if (k % 2 == 0 and len(occ_act) < n_act_occ) or len(virt_act) == n_act_virt:
+            occ_act.append(c)
+        else:
+            virt_act.append(c)
+    inactive = [c for c in range(n_cas) if c not in act]
+    order = inactive + occ_act + virt_act
+    return np.ascontiguousarray(C[:, order])
+
+
+def cas_expansion(n: int, n_act_occ: int, n_act_virt: int, n_det: int, max_exc: int,
+                  rng: np.random.Generator):
+    """Seeded synthetic CI expansion over the active space.
+
+    Determinant d replaces the reference columns holes[d] (among the last
+    n_act_occ of the n occupied ones) by the orbitals particles[d] (columns
+    n .. n + n_act_virt - 1), hole k by particle k.  The reference comes first,
+    then n_det - 1 excitations drawn without replacement from all of those up to
+    max_exc, listed by level; coefficients 1 for the reference and
+    0.25^level x N(0, 1) otherwise.  Returns (holes, particles, coeffs).
+    """
+    import itertools
+    hole_set = range(n - n_act_occ, n)
+    part_set = range(n, n + n_act_virt)
+    pool = []
+    for k in range(1, max_exc + 1):
+        for h in itertools.combinations(hole_set, k):
+            for p in itertools.combinations(part_set, k):
+                pool.append((h, p))
+    if n_det - 1 > len(pool):
+        raise ValueError("only %d excitations up to level %d" % (len(pool), max_exc))
+    pick = sorted(rng.choice(len(pool), size=n_det - 1, replace=False)) if n_det > 1 else []
+    holes, parts, coeffs = [()], [()], [1.0]
+    for q in pick:
+        h, p = pool[q]
+        holes.append(h)
+        parts.append(p)
+        coeffs.append(0.25 ** len(h) * float(rng.standard_normal()))
+    return holes, parts, np.array(coeffs)
+
+
+@dataclasses.dataclass
+class CasSystem:
+    config: CasConfig
+    chol: np.ndarray      # [X][M][M]
+    orbitals: np.ndarray  # [M][n_cas]
+    holes: list
+    particles: list
+    coeffs: np.ndarray    # [n_det]
+    walkers: np.ndarray   # [nw][M][n] complex128
+
+    @property
+    def reference(self) -> np.ndarray:
+        return np.ascontiguousarray(self.orbitals[:, :self.config.n])
+
+
+def make_cas_system(cfg: CasConfig, nw: int | None = None) -> CasSystem:
+    rng = np.random.default_rng(cfg.seed)
+    chol = chain_cholesky(cfg.M, cfg.chol_tol)
+    C = cas_orbitals(cfg.M, cfg.n, cfg.n_act_occ, cfg.n_act_virt)
+    holes, parts, coeffs = cas_expansion(cfg.n, cfg.n_act_occ, cfg.n_act_virt, cfg.n_det, cfg.max_exc, rng)
+    walkers = noisy_walkers(np.ascontiguousarray(C[:, :cfg.n]), cfg.nw if nw is None else nw, cfg.sigma, rng)
+    return CasSystem(cfg, chol, C, holes, parts, coeffs, walkers)
+
+
 def batch_configs(count: int = 8, seed: int = 4004, m_range=(100, 600), w_range=(64, 512)) -> list:
     """Ragged set of chain systems: M uniform in m_range, n = M // 7 orbitals
     per spin, Cholesky to 1e-5, walkers uniform in w_range, noise 0.2; one
