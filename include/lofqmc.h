@@ -263,6 +263,70 @@ int lo_hr_info(const lo_hr* h, int64_t* M, int64_t* n_occ, int64_t* bytes);
 int local_energy_hr(lo_ctx* ctx, const lo_hr* h, int64_t nw, const double* theta, const int32_t* info,
                     unsigned flags, double* energy);
 
+/* ---------------------------------------- multi-determinant (CAS) trials
+ *
+ * Trial psi_T = sum_d c_d |Phi_d> (Sec. 2.1.1, Eq. 12) over the orbitals
+ * C (M x n_cas) of an LO factor handle built from lbar of all n_cas orbitals:
+ * the reference determinant Phi_0 holds columns 0 .. n_occ-1, of which the
+ * last n_act_occ are active; columns n_occ .. n_cas-1 are the active virtual
+ * orbitals.  Determinant d replaces the reference columns holes[d][m] by the
+ * orbitals particles[d][m] (m < n_exc[d]), in place, hole m by particle m.
+ * Every determinant is doubly occupied with the same spatial orbitals for
+ * both spins (closed shell), so <Phi_d|phi> = det(Phi_d^T phi)^2.
+ *
+ * local_energy_md evaluates the LO energy of Eq. 19 with the weights of
+ * Eq. 12 by the Sherman-Morrison-Woodbury update of Eq. 20-21: from the
+ * reference theta = phi (Phi_0^T phi)^{-1} (green_theta with Phi_0) and
+ * T = C_av^T theta, determinant d has det(Phi_d^T phi) / det(Phi_0^T phi) =
+ * det R_d with R_d = T[particles, holes], and the per-determinant four
+ * vectors of Eq. 22-23 are combinations of the projections of theta's own
+ * and active columns.  The weighted sum over determinants is formed once per
+ * walker (two moments of the R_d^{-1}), so the per-pair cost does not grow
+ * with n_det.  A determinant whose R_d is exactly singular has weight zero.
+ *
+ * build_md_trial:
+ *   f          : LO factors of all n_cas orbitals (f->n_occ = n_cas); must
+ *                outlive the handle (its rows are read at every evaluation)
+ *   n_occ      : occupied orbitals per determinant, 1 <= n_occ <= min(n_cas, 112)
+ *   n_act_occ  : 1..min(6, n_occ); n_cas - n_occ <= 6; n_cas <= 128
+ *   orbitals   : [M][n_cas] double (device), the orbitals C; only the active
+ *                virtual columns are copied into the handle
+ *   n_det      : 1..2^20;  max_exc: 0..min(n_act_occ, n_cas - n_occ)
+ *   n_exc      : host int32 [n_det], 0..max_exc
+ *   holes      : host int32 [n_det][max_exc], reference columns in
+ *                [n_occ - n_act_occ, n_occ), distinct within a determinant
+ *   particles  : host int32 [n_det][max_exc], orbitals in [n_occ, n_cas), distinct
+ *   coeffs     : host double [n_det], the CI coefficients c_d (real)
+ *   out        : receives a library-owned handle, released by lo_md_destroy
+ * Synchronous.  LO_EINVAL for indices or sizes out of range. */
+typedef struct lo_md lo_md;
+int build_md_trial(lo_ctx* ctx, const lo_factors* f, int64_t n_occ, int64_t n_act_occ, const double* orbitals,
+                   int64_t n_det, int64_t max_exc, const int32_t* n_exc, const int32_t* holes,
+                   const int32_t* particles, const double* coeffs, lo_md** out);
+
+int lo_md_destroy(lo_md* md);
+
+/* Host-side description; any output may be NULL.  out_rows: pass-1 output
+ * rows per walker (the workspace of local_energy_md holds out_rows x nw
+ * complex values). */
+int lo_md_info(const lo_md* md, int64_t* n_occ, int64_t* n_cas, int64_t* n_det, int64_t* npairs,
+               int64_t* out_rows);
+
+/* Multi-determinant LO two-body energy per walker.
+ *   theta      : from green_theta with the reference determinant Phi_0
+ *                ([M][n_occ] columns 0 .. n_occ-1 of the orbitals), layout
+ *                as flags says
+ *   info       : from that green_theta call, or NULL; walkers with info != 0
+ *                get NaN energies
+ *   energy     : complex [nw][2], (E_J, E_K) of E2 = sum_d w_d E2^d,
+ *                w_d = c_d det(R_d)^2 / sum_d' c_d' det(R_d')^2
+ *   ovlp_ratio : complex [nw] or NULL: sum_d c_d det(R_d)^2, i.e.
+ *                <psi_T|phi> / det(Phi_0^T phi)^2 (zero gives NaN energies)
+ * LO_EUNSUPPORTED if out_rows x nw exceeds 2^31 - 1 (evaluate fewer walkers
+ * per call). */
+int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* theta, const int32_t* info,
+                    unsigned flags, double* energy, double* ovlp_ratio);
+
 /* --------------------------------------------------- several systems at once
  *
  * Full-route energies (Eq. 16) of several systems of different size in one

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblofqmc.so")
-SOURCES = ["lofqmc.cpp", "green_theta.hip", "energy_full.hip", "energy_full_lp.hip", "energy_lo.hip", "energy_lo_lp.hip", "energy_hr.hip", "residual.hip", "setup.hip"]
+SOURCES = ["lofqmc.cpp", "green_theta.hip", "energy_full.hip", "energy_full_lp.hip", "energy_lo.hip", "energy_lo_lp.hip", "energy_hr.hip", "energy_md.hip", "residual.hip", "setup.hip"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 FLAGS = [

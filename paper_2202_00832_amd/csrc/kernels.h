@@ -111,6 +111,41 @@ hipError_t launch_residual_train_step(hipStream_t s, int64_t nw, int n, float* p
 hipError_t launch_hr_energy(hipStream_t s, int M, int n, int64_t nw, int npairs, const double* Y, const int* pairs,
                             const double* theta, int orbital_major, double* partial);
 
+// ---- multi-determinant LO energy
+// Arguments of one evaluation: theta (reference determinant, strides so, sr,
+// sw), C_av [M][nav], determinant tables [ndet][hstride] (hstride >= NA =
+// max(nao, nav); hole and particle indices relative to the active sets), the
+// pair tables (own output rows of orbitals i, j or -1, first output row of the
+// pair's rows in the active-column region, act_stride rows per active column)
+// and the pass-1 output qbar.
+struct MdArgs {
+  int M, n, ncas, nao, nav, ndet, hstride, npairs;
+  int64_t nw, so, sr, sw, act_stride;
+  const double* cav;
+  const double* theta;
+  const int* exc;
+  const int* holes;
+  const int* parts;
+  const double* coef;
+  const int* pi;
+  const int* pj;
+  const int* pK;
+  const int64_t* offI;
+  const int64_t* offJ;
+  const int64_t* offA;
+  const double* qbar;
+};
+int md_max_orbitals();
+int md_max_active();
+// per-walker device bytes of the moments and T (work of launch_md_energy is nw times this)
+size_t md_walker_bytes(int na, int n);
+int md_pair_chunks(int npairs);
+// prep: T, the determinant moments (into work) and ovr, device complex [nw]
+// (sum_d c_d det(R_d)^2) or null; pairs: the weighted pair sums into partial
+// [nchunk][nw][4], reduced by launch_reduce_partials
+hipError_t launch_md_prep(hipStream_t s, const MdArgs& g, void* work, double* ovr);
+hipError_t launch_md_pairs(hipStream_t s, const MdArgs& g, void* work, int nchunk, double* partial);
+
 // ---- set-up
 // C_b(m, c) = sum_k A_b(m, k) B_b(k, c), element (m, k) of A at a_base[b] + m * a_m + k * a_k, etc.
 // bases: device int64 [batch][3] = (a_base, b_base, c_base).

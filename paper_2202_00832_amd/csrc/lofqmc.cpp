@@ -53,6 +53,23 @@ struct lo_factors {
   float* d_orbfeat = nullptr;          // [n][2]: sum_j K_ij, sum_j discarded mass (residual features)
 };
 
+struct lo_md {
+  int64_t M = 0, n = 0, ncas = 0, nao = 0, nav = 0, ndet = 0, maxe = 0;
+  int na = 0;
+  const lo_factors* f = nullptr;  // not owned: the factor rows are read at every evaluation
+  double* cav = nullptr;          // device [M][nav]: the active virtual orbitals
+  int* d_exc = nullptr;           // [ndet]
+  int* d_holes = nullptr;         // [ndet][na], relative to the first active occupied column
+  int* d_parts = nullptr;         // [ndet][na], relative to column n
+  double* d_coef = nullptr;       // [ndet]
+  int64_t n_out_rows = 0, act_base = 0, total_rows = 0;
+  int ntiles = 0, nblk = 0, tmax = 0, npairs = 0;
+  int* d_rowidx = nullptr;        // pass-1 gather table: own rows of orbitals < n, then na copies of all rows
+  int* d_tiles = nullptr;         // [3][ntiles] then [nblk + 1]
+  int* d_pair = nullptr;          // [3][npairs]: i, j, K
+  int64_t* d_off = nullptr;       // [3][npairs]: own rows of i and j (-1 if virtual), first active row
+};
+
 struct lo_hr {
   int64_t M = 0, n = 0, npairs = 0;
   double* Y = nullptr;     // device [npairs][M][M], row-major, pairs i <= j in row order
@@ -814,6 +831,269 @@ int local_energy_hr(lo_ctx* ctx, const lo_hr* h, int64_t nw, const double* theta
                                             theta, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0, partial));
   prof.mark("reduce_partials_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, (int)h->npairs, partial, info, energy));
+  return LO_OK;
+}
+
+// ------------------------------------------------- multi-determinant trials
+
+int lo_md_destroy(lo_md* md) {
+  if (!md) return LO_OK;
+  (void)hipFree(md->cav);
+  (void)hipFree(md->d_exc);
+  (void)hipFree(md->d_holes);
+  (void)hipFree(md->d_parts);
+  (void)hipFree(md->d_coef);
+  (void)hipFree(md->d_rowidx);
+  (void)hipFree(md->d_tiles);
+  (void)hipFree(md->d_pair);
+  (void)hipFree(md->d_off);
+  delete md;
+  return LO_OK;
+}
+
+int build_md_trial(lo_ctx* ctx, const lo_factors* f, int64_t n_occ, int64_t n_act_occ, const double* orbitals,
+                   int64_t n_det, int64_t max_exc, const int32_t* n_exc, const int32_t* holes,
+                   const int32_t* particles, const double* coeffs, lo_md** out) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!out) return fail(ctx, LO_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!f) return fail(ctx, LO_EINVAL, "null factors");
+  const int64_t M = f->M, ncas = f->n;
+  if (n_occ <= 0 || n_occ > ncas) return fail(ctx, LO_EINVAL, "n_occ must be in 1..n_cas (the factors' orbitals)");
+  const int64_t nav = ncas - n_occ;
+  const int amax = lofqmc::md_max_active();
+  if (n_act_occ <= 0 || n_act_occ > n_occ) return fail(ctx, LO_EINVAL, "n_act_occ must be in 1..n_occ");
+  if (n_act_occ > amax || nav > amax)
+    return fail(ctx, LO_EUNSUPPORTED, "more than %d active occupied or active virtual orbitals", amax);
+  if (n_occ > kMaxOccTheta || ncas > lofqmc::md_max_orbitals())
+    return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d or n_cas above %d", kMaxOccTheta, lofqmc::md_max_orbitals());
+  if (n_det <= 0 || n_det > (1 << 20)) return fail(ctx, LO_EINVAL, "n_det must be in 1..2^20");
+  if (max_exc < 0 || max_exc > std::min(n_act_occ, nav))
+    return fail(ctx, LO_EINVAL, "max_exc must be in 0..min(n_act_occ, n_cas - n_occ)");
+  if (!orbitals || !n_exc || !coeffs || (max_exc > 0 && (!holes || !particles)))
+    return fail(ctx, LO_EINVAL, "null array");
+  const int na = (int)std::max(n_act_occ, nav);
+  const int64_t act0 = n_occ - n_act_occ;
+  std::vector<int> exc(n_det), hrel((size_t)n_det * na, 0), prel((size_t)n_det * na, 0);
+  std::vector<double> coef(coeffs, coeffs + n_det);
+  for (int64_t d = 0; d < n_det; ++d) {
+    const int e = n_exc[d];
+    if (e < 0 || e > max_exc) return fail(ctx, LO_EINVAL, "determinant %lld: excitation level out of range", (long long)d);
+    exc[d] = e;
+    unsigned hm = 0, pm = 0;
+    for (int m = 0; m < e; ++m) {
+      const int h = holes[d * max_exc + m], p = particles[d * max_exc + m];
+      if (h < act0 || h >= n_occ || p < n_occ || p >= ncas)
+        return fail(ctx, LO_EINVAL, "determinant %lld: hole or particle outside the active space", (long long)d);
+      const unsigned hb = 1u << (h - act0), pb = 1u << (p - n_occ);
+      if ((hm & hb) || (pm & pb)) return fail(ctx, LO_EINVAL, "determinant %lld: repeated hole or particle", (long long)d);
+      hm |= hb;
+      pm |= pb;
+      hrel[d * na + m] = (int)(h - act0);
+      prel[d * na + m] = (int)(p - n_occ);
+    }
+    if (!std::isfinite(coef[d])) return fail(ctx, LO_EINVAL, "non-finite coefficient");
+  }
+  // output rows of pass 1: each orbital o < n_occ's own rows (as in the
+  // single-determinant tables, restricted to the reference's orbitals), then
+  // every factor row once per active occupied column
+  const int64_t total = f->total_rows;
+  std::vector<int64_t> obase(n_occ + 1, 0), loc(n_occ * ncas, 0);
+  for (int64_t o = 0; o < n_occ; ++o) {
+    int64_t R = 0;
+    for (int64_t k = 0; k < ncas; ++k) {
+      loc[o * ncas + k] = R;
+      R += 2 * (int64_t)f->ranks[o * ncas + k];
+    }
+    obase[o + 1] = obase[o] + R;
+  }
+  const int64_t act_base = obase[n_occ];
+  const int64_t n_out = act_base + n_act_occ * total;
+  if (n_out > std::numeric_limits<int>::max()) return fail(ctx, LO_EUNSUPPORTED, "too many factor rows");
+  std::vector<int> rowidx((size_t)n_out);
+  for (int64_t o = 0; o < n_occ; ++o)
+    for (int64_t k = 0; k < ncas; ++k) {
+      const int64_t i = std::min(o, k), j = std::max(o, k);
+      const int64_t src = f->row_offset[i * ncas + j];
+      const int64_t cnt = 2 * (int64_t)f->ranks[o * ncas + k];
+      for (int64_t q = 0; q < cnt; ++q) rowidx[obase[o] + loc[o * ncas + k] + q] = (int)(src + q);
+    }
+  for (int64_t a = 0; a < n_act_occ; ++a)
+    for (int64_t r = 0; r < total; ++r) rowidx[act_base + a * total + r] = (int)r;
+  // pass-1 tiles: own rows per orbital in blocks of lo_orbital_block()
+  // orbitals; the active-column rows in tiles of the same size, eight
+  // consecutive tiles (one active column) to a block
+  const int64_t cap = lofqmc::lo_tile_rows();
+  const int ob = lofqmc::lo_orbital_block();
+  std::vector<int> t_orb, t_row0, t_nrows, blk;
+  for (int64_t o = 0; o < n_occ; ++o) {
+    if (o % ob == 0) blk.push_back((int)t_orb.size());
+    const int64_t R = obase[o + 1] - obase[o];
+    const int64_t nt = (R + cap - 1) / cap;
+    for (int64_t q = 0; q < nt; ++q) {
+      t_orb.push_back((int)o);
+      t_row0.push_back((int)(obase[o] + R * q / nt));
+      t_nrows.push_back((int)(R * (q + 1) / nt - R * q / nt));
+    }
+  }
+  for (int64_t a = 0; a < n_act_occ; ++a) {
+    const int64_t nt = (total + cap - 1) / cap;
+    for (int64_t q = 0; q < nt; ++q) {
+      if (q % 8 == 0) blk.push_back((int)t_orb.size());
+      t_orb.push_back((int)(act0 + a));
+      t_row0.push_back((int)(act_base + a * total + total * q / nt));
+      t_nrows.push_back((int)(total * (q + 1) / nt - total * q / nt));
+    }
+  }
+  const int ntiles = (int)t_orb.size();
+  const int nblk = (int)blk.size();
+  blk.push_back(ntiles);
+  int tmax = 0;
+  for (int b = 0; b < nblk; ++b) tmax = std::max(tmax, blk[b + 1] - blk[b]);
+  std::vector<int> tiles;
+  tiles.insert(tiles.end(), t_orb.begin(), t_orb.end());
+  tiles.insert(tiles.end(), t_row0.begin(), t_row0.end());
+  tiles.insert(tiles.end(), t_nrows.begin(), t_nrows.end());
+  tiles.insert(tiles.end(), blk.begin(), blk.end());
+  // pairs i <= j of all n_cas orbitals with a stored block
+  std::vector<int> pi, pj, pK;
+  std::vector<int64_t> offI, offJ, offA;
+  for (int64_t i = 0; i < ncas; ++i)
+    for (int64_t j = i; j < ncas; ++j) {
+      const int K = f->ranks[i * ncas + j];
+      if (K == 0) continue;
+      pi.push_back((int)i);
+      pj.push_back((int)j);
+      pK.push_back(K);
+      offI.push_back(i < n_occ ? obase[i] + loc[i * ncas + j] : -1);
+      offJ.push_back(j < n_occ ? obase[j] + loc[j * ncas + i] : -1);
+      offA.push_back(act_base + f->row_offset[i * ncas + j]);
+    }
+  lo_md* md = new (std::nothrow) lo_md();
+  if (!md) return fail(ctx, LO_ENOMEM, "host allocation failed");
+  md->M = M;
+  md->n = n_occ;
+  md->ncas = ncas;
+  md->nao = n_act_occ;
+  md->nav = nav;
+  md->ndet = n_det;
+  md->maxe = max_exc;
+  md->na = na;
+  md->f = f;
+  md->n_out_rows = n_out;
+  md->act_base = act_base;
+  md->total_rows = total;
+  md->ntiles = ntiles;
+  md->nblk = nblk;
+  md->tmax = tmax;
+  md->npairs = (int)pi.size();
+  std::vector<int> pair(pi);
+  pair.insert(pair.end(), pj.begin(), pj.end());
+  pair.insert(pair.end(), pK.begin(), pK.end());
+  std::vector<int64_t> off(offI);
+  off.insert(off.end(), offJ.begin(), offJ.end());
+  off.insert(off.end(), offA.begin(), offA.end());
+  int rc = 0;
+  if ((rc = upload(ctx, &md->d_exc, exc)) || (rc = upload(ctx, &md->d_holes, hrel)) ||
+      (rc = upload(ctx, &md->d_parts, prel)) || (rc = upload(ctx, &md->d_coef, coef)) ||
+      (rc = upload(ctx, &md->d_rowidx, rowidx)) || (rc = upload(ctx, &md->d_tiles, tiles)) ||
+      (!pair.empty() && (rc = upload(ctx, &md->d_pair, pair))) || (!off.empty() && (rc = upload(ctx, &md->d_off, off)))) {
+    lo_md_destroy(md);
+    return rc;
+  }
+  if (nav > 0) {
+    if (hipMalloc(&md->cav, sizeof(double) * (size_t)M * nav) != hipSuccess) {
+      md->cav = nullptr;
+      lo_md_destroy(md);
+      return fail(ctx, LO_ENOMEM, "device allocation failed");
+    }
+    // C_av [M][nav] from the columns n_occ .. n_cas - 1 of the orbitals
+    if (hipMemcpy2DAsync(md->cav, sizeof(double) * nav, orbitals + n_occ, sizeof(double) * ncas,
+                         sizeof(double) * nav, M, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      lo_md_destroy(md);
+      return fail(ctx, LO_EHIP, "copy of the active virtual orbitals failed");
+    }
+  }
+  *out = md;
+  return LO_OK;
+}
+
+int lo_md_info(const lo_md* md, int64_t* n_occ, int64_t* n_cas, int64_t* n_det, int64_t* npairs,
+               int64_t* out_rows) {
+  if (!md) return LO_EINVAL;
+  if (n_occ) *n_occ = md->n;
+  if (n_cas) *n_cas = md->ncas;
+  if (n_det) *n_det = md->ndet;
+  if (npairs) *npairs = md->npairs;
+  if (out_rows) *out_rows = md->n_out_rows;
+  return LO_OK;
+}
+
+int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* theta, const int32_t* info,
+                    unsigned flags, double* energy, double* ovlp_ratio) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!md) return fail(ctx, LO_EINVAL, "null trial");
+  if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
+  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  // the pair kernel addresses qbar with 32-bit element offsets from a walker's base
+  if (nw > 0 && md->n_out_rows > (((int64_t)1 << 31) - 1) / nw)
+    return fail(ctx, LO_EUNSUPPORTED, "output rows x walkers above 2^31-1: evaluate fewer walkers per call");
+  if (nw == 0) return LO_OK;
+  if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
+  const lo_factors* f = md->f;
+  const bool om = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
+  const int nchunk = lofqmc::md_pair_chunks(md->npairs);
+  const size_t qbytes = align256(sizeof(double) * 2 * (size_t)md->n_out_rows * nw);
+  const size_t mbytes = align256(lofqmc::md_walker_bytes(md->na, (int)md->n) * (size_t)nw);
+  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
+  int rc = ensure_ws(ctx, qbytes + mbytes + pbytes);
+  if (rc) return rc;
+  char* base = (char*)ctx->ws;
+  double* qbar = (double*)base;
+  void* mwork = base + qbytes;
+  double* partial = (double*)(base + qbytes + mbytes);
+  lofqmc::MdArgs g{};
+  g.M = (int)md->M;
+  g.n = (int)md->n;
+  g.ncas = (int)md->ncas;
+  g.nao = (int)md->nao;
+  g.nav = (int)md->nav;
+  g.ndet = (int)md->ndet;
+  g.hstride = md->na;
+  g.npairs = md->npairs;
+  g.nw = nw;
+  g.so = om ? md->M * nw : 1;
+  g.sr = om ? nw : md->n;
+  g.sw = om ? 1 : md->M * md->n;
+  g.act_stride = md->total_rows;
+  g.cav = md->cav;
+  g.theta = theta;
+  g.exc = md->d_exc;
+  g.holes = md->d_holes;
+  g.parts = md->d_parts;
+  g.coef = md->d_coef;
+  g.pi = md->d_pair;
+  g.pj = md->d_pair + md->npairs;
+  g.pK = md->d_pair + 2 * md->npairs;
+  g.offI = md->d_off;
+  g.offJ = md->d_off + md->npairs;
+  g.offA = md->d_off + 2 * md->npairs;
+  g.qbar = qbar;
+  ProfScope prof(ctx);
+  prof.mark("lo_pass1_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)md->M, (int)md->n, nw, md->ntiles, f->rows,
+                                           md->d_rowidx, md->d_tiles, md->d_tiles + 3 * md->ntiles, md->nblk,
+                                           md->tmax, theta, om ? 1 : 0, qbar));
+  prof.mark("md_prep_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_md_prep(ctx->stream, g, mwork, ovlp_ratio));
+  prof.mark("md_energy_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_md_pairs(ctx->stream, g, mwork, nchunk, partial));
+  prof.mark("reduce_partials_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, md->npairs > 0 ? nchunk : 0, partial, info,
+                                                  energy));
   return LO_OK;
 }
 

@@ -47,6 +47,11 @@ _SIGS = {
     "lo_hr_destroy": (ctypes.c_int, [_c_p]),
     "lo_hr_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p]),
     "local_energy_hr": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_uint, _c_p]),
+    "build_md_trial": (ctypes.c_int, [_c_p, _c_p, _i64, _i64, _c_p, _i64, _i64, _c_p, _c_p, _c_p, _c_p,
+                                      ctypes.POINTER(_c_p)]),
+    "lo_md_destroy": (ctypes.c_int, [_c_p]),
+    "lo_md_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "local_energy_md": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_uint, _c_p, _c_p]),
     "lo_batch_create": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int, _c_p, ctypes.POINTER(_c_p)]),
     "lo_batch_destroy": (ctypes.c_int, [_c_p]),
     "lo_batch_info": (ctypes.c_int, [_c_p, _c_p, _c_p]),
@@ -139,6 +144,34 @@ class HrEri:
     def close(self):
         if self._h:
             load().lo_hr_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MdTrial:
+    """Owner of a lo_md handle: a multi-determinant trial over the orbitals of an
+    LO factor handle (which must stay open while this one is used)."""
+
+    def __init__(self, handle: int, factors):
+        self._h = ctypes.c_void_p(handle)
+        self._factors = factors
+        vals = [ctypes.c_int64() for _ in range(5)]
+        load().lo_md_info(self._h, *[ctypes.byref(v) for v in vals])
+        self.n_occ, self.n_cas, self.n_det, self.npairs, self.out_rows = [v.value for v in vals]
+        self.M = factors.M
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load().lo_md_destroy(self._h)
             self._h = ctypes.c_void_p(0)
 
     def __del__(self):
@@ -451,6 +484,60 @@ class Context:
         _check_dev("energy", energy, torch.complex128, (nw, 2))
         self._check(self._lib.local_energy_hr(self._h, hr.handle, nw, _ptr(theta), _ptr(info), flags,
                                               _ptr(energy)))
+        return energy
+
+    # -- multi-determinant trials ---------------------------------------------------
+    def build_md_trial(self, factors, n_occ, n_act_occ, orbitals, holes, particles, coeffs) -> MdTrial:
+        """holes / particles: one sequence of column indices per determinant (the
+        reference: empty); orbitals: device float64 [M][n_cas]."""
+        import numpy as np
+        import torch
+        _check_dev("orbitals", orbitals, torch.float64, (factors.M, factors.n_occ))
+        n_det = len(coeffs)
+        if len(holes) != n_det or len(particles) != n_det:
+            raise ValueError("holes, particles and coeffs differ in length")
+        max_exc = max([len(h) for h in holes] + [0])
+        exc = np.zeros(n_det, dtype=np.int32)
+        hh = np.zeros((n_det, max(max_exc, 1)), dtype=np.int32)
+        pp = np.zeros((n_det, max(max_exc, 1)), dtype=np.int32)
+        for d, (h, p) in enumerate(zip(holes, particles)):
+            if len(h) != len(p):
+                raise ValueError("determinant %d: %d holes, %d particles" % (d, len(h), len(p)))
+            exc[d] = len(h)
+            hh[d, :len(h)] = h
+            pp[d, :len(p)] = p
+        if max_exc == 0:
+            hh = hh[:, :0].copy()
+            pp = pp[:, :0].copy()
+        c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+        h = ctypes.c_void_p()
+        self._check(self._lib.build_md_trial(
+            self._h, factors.handle, n_occ, n_act_occ, _ptr(orbitals), n_det, max_exc,
+            exc.ctypes.data, hh.ctypes.data if hh.size else None, pp.ctypes.data if pp.size else None,
+            c.ctypes.data, ctypes.byref(h)))
+        return MdTrial(h.value, factors)
+
+    def local_energy_md(self, md: MdTrial, theta, info=None, energy=None, ovlp_ratio=None, orbital_major=False):
+        """Multi-determinant LO energy; theta from green_theta with the reference
+        determinant, [nw][M][n_occ] or [n_occ][M][nw] when orbital_major."""
+        import torch
+        flags = 0
+        if orbital_major:
+            nw = theta.shape[2]
+            _check_dev("theta", theta, torch.complex128, (md.n_occ, md.M, nw))
+            flags = LO_THETA_ORBITAL_MAJOR
+        else:
+            nw = theta.shape[0]
+            _check_dev("theta", theta, torch.complex128, (nw, md.M, md.n_occ))
+        if info is not None:
+            _check_dev("info", info, torch.int32, (nw,))
+        if energy is None:
+            energy = torch.empty((nw, 2), dtype=torch.complex128, device=theta.device)
+        _check_dev("energy", energy, torch.complex128, (nw, 2))
+        if ovlp_ratio is not None:
+            _check_dev("ovlp_ratio", ovlp_ratio, torch.complex128, (nw,))
+        self._check(self._lib.local_energy_md(self._h, md.handle, nw, _ptr(theta), _ptr(info), flags,
+                                              _ptr(energy), _ptr(ovlp_ratio)))
         return energy
 
     # -- learned residual (extension) ---------------------------------------------

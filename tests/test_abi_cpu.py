@@ -89,3 +89,22 @@ def test_validation_errors_need_no_device(lib):
     finally:
         assert lib.lo_destroy(h) == L.LO_OK
     assert lib.lo_destroy(None) == L.LO_OK
+
+
+def test_multideterminant_validation_needs_no_device(lib):
+    h = _ctx(lib)
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p()
+    one = (ctypes.c_int32 * 1)(0)
+    c = (ctypes.c_double * 1)(1.0)
+    try:
+        assert lib.build_md_trial(None, fake, 4, 1, fake, 1, 0, one, None, None, c, ctypes.byref(out)) == L.LO_EINVAL
+        assert lib.build_md_trial(h, None, 4, 1, fake, 1, 0, one, None, None, c, ctypes.byref(out)) == L.LO_EINVAL
+        assert b"null factors" in lib.lo_last_error(h)
+        assert lib.build_md_trial(h, fake, 4, 1, fake, 1, 0, one, None, None, c, None) == L.LO_EINVAL
+        assert lib.local_energy_md(h, None, 4, fake, None, 0, fake, None) == L.LO_EINVAL
+        assert lib.local_energy_md(None, fake, 4, fake, None, 0, fake, None) == L.LO_EINVAL
+        assert lib.lo_md_destroy(None) == L.LO_OK
+        assert lib.lo_md_info(None, None, None, None, None, None) == L.LO_EINVAL
+    finally:
+        lib.lo_destroy(h)
