@@ -376,6 +376,105 @@ def residual_study(torch, lofqmc, synth, n_train=20480, n_test=2048, steps=2000,
     return out
 
 
+def md_study(torch, lofqmc, synth, steps, warmup, baseline_steps=2):
+    """Multi-determinant trial on the 400-site CAS chain (60 occupied + 5 active
+    virtual orbitals, 5 active occupied, 200 determinants up to quadruples, 512
+    walkers, LO at 1e-5): reference green_theta + local_energy_md per step (the
+    SMW route of Eq. 20-23), against evaluating every determinant on its own
+    (green_theta with that determinant and the LO energy over the padded n_cas
+    orbitals, weighted by c_d det^2), which also cross-checks the energies."""
+    cfg = synth.CAS_POLYACENE
+    log("multi-determinant study: generating %s" % cfg.name)
+    s = synth.make_cas_system(cfg)
+    M, n, nw, ncas, ndet = cfg.M, cfg.n, cfg.nw, cfg.n_cas, cfg.n_det
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    ctx = lofqmc.Context()
+    C, ref, phi = dev(s.orbitals), dev(s.reference), dev(s.walkers)
+    lbar = ctx.build_half_rotated_chol(dev(s.chol), C)
+    t0 = time.perf_counter()
+    f = ctx.build_lo_factors(lbar, cfg.epsilon)
+    md = ctx.build_md_trial(f, n, cfg.n_act_occ, C, s.holes, s.particles, s.coeffs)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    theta = torch.empty((nw, M, n), dtype=torch.complex128, device="cuda")
+    logov = torch.empty(nw, dtype=torch.complex128, device="cuda")
+    info = torch.empty(nw, dtype=torch.int32, device="cuda")
+    energy = torch.empty((nw, 2), dtype=torch.complex128, device="cuda")
+    ovr = torch.empty(nw, dtype=torch.complex128, device="cuda")
+
+    def step(ev):
+        if ev is not None:
+            ev["a"].record()
+        ctx.green_theta(ref, phi, theta, logov, info)
+        if ev is not None:
+            ev["b"].record()
+        ctx.local_energy_md(md, theta, info, energy, ovr)
+        if ev is not None:
+            ev["c"].record()
+
+    tot, split, kern = time_route(torch, ctx, step, steps, warmup, ["a", "b", "c"])
+    ms = tot / steps
+    e_md = energy.cpu().numpy()
+    log("multi-determinant: %.3f ms/step (local_energy_md %.3f), %d determinants, %d pairs"
+        % (ms, float(np.mean(split["b->c"])), ndet, md.npairs))
+
+    # every determinant on its own
+    trials, occs = [], []
+    for h, p in zip(s.holes, s.particles):
+        occ = list(range(n))
+        for a, b in zip(h, p):
+            occ[a] = b
+        occs.append(torch.tensor(occ, dtype=torch.int64, device="cuda"))
+        trials.append(C[:, occs[-1]].contiguous())
+    coef = torch.tensor(s.coeffs, dtype=torch.complex128, device="cuda")
+    th_d = torch.empty((nw, M, n), dtype=torch.complex128, device="cuda")
+    lo_d = torch.empty(nw, dtype=torch.complex128, device="cuda")
+    inf_d = torch.empty(nw, dtype=torch.int32, device="cuda")
+    pad = torch.zeros((nw, M, ncas), dtype=torch.complex128, device="cuda")
+    e_d = torch.empty((nw, 2), dtype=torch.complex128, device="cuda")
+
+    def per_det():
+        num = torch.zeros((nw, 2), dtype=torch.complex128, device="cuda")
+        den = torch.zeros(nw, dtype=torch.complex128, device="cuda")
+        for d in range(ndet):
+            ctx.green_theta(trials[d], phi, th_d, lo_d, inf_d)
+            pad.zero_()
+            pad[:, :, occs[d]] = th_d
+            ctx.local_energy_lo(f, pad, inf_d, energy=e_d)
+            ov = coef[d] * torch.exp(2.0 * (lo_d - logov))
+            num += ov[:, None] * e_d
+            den += ov
+        return num / den[:, None]
+
+    e_pd = per_det()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(baseline_steps):
+        per_det()
+    t1.record()
+    torch.cuda.synchronize()
+    pd_ms = t0.elapsed_time(t1) / baseline_steps + float(np.mean(split["a->b"]))
+    diff = float(np.abs(e_md - e_pd.cpu().numpy()).max())
+    log("per-determinant evaluation: %.1f ms/step, max |E_md - E_per_det| %.2e Ha" % (pd_ms, diff))
+    own = [k for k in kern if k.startswith("md_") or k == "lo_pass1_kernel" or k == "reduce_partials_kernel"]
+    out = {"workload": cfg.name, "M": M, "n_occ": n, "n_cas": ncas, "n_act_occ": cfg.n_act_occ,
+           "n_act_virt": cfg.n_act_virt, "n_det": ndet, "max_exc": cfg.max_exc, "walkers": nw,
+           "epsilon": cfg.epsilon, "n_chol": s.chol.shape[0], "setup_s": round(setup_s, 2),
+           "value": round(nw / (ms * 1e-3), 1), "unit": "walker-energies/s", "ms_per_step": round(ms, 4),
+           "local_energy_md_ms": round(float(np.mean(split["b->c"])), 4),
+           "kernel_us": {k: round(kern[k][1] / kern[k][0] * 1e3, 2) for k in own},
+           "pass1_out_rows": md.out_rows, "pairs": md.npairs,
+           "per_determinant_ms_per_step": round(pd_ms, 2),
+           "smw_speedup_vs_per_determinant": round(pd_ms / ms, 1),
+           "max_abs_diff_vs_per_determinant_Ha": diff}
+    md.close()
+    f.close()
+    ctx.close()
+    return out
+
+
 def cpu_baseline(cfg, system, eps, sample):
     """The CPU reference (numpy FP64) on a fixed sample of walkers: LO route."""
     from oracle import energy as E
@@ -413,6 +512,7 @@ def main():
                     help="skip the multi-system batching study (8 chain systems, captured graph)")
     ap.add_argument("--no-residual", action="store_true",
                     help="skip the learned-residual study (800-site chain: about 30 GB of device memory)")
+    ap.add_argument("--no-md", action="store_true", help="skip the multi-determinant study")
     ap.add_argument("--no-hr", action="store_true",
                     help="skip the half-rotated ERI route (Eq. 17; its pair blocks take 2.3 GB)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -565,6 +665,9 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_study(torch, lofqmc, synth)
+    mdet = None
+    if not args.no_md:
+        mdet = md_study(torch, lofqmc, synth, max(5, min(args.steps, 50)), min(args.warmup, 20))
     resid = None
     if not args.no_residual:
         resid = residual_study(torch, lofqmc, synth)
@@ -589,6 +692,7 @@ def main():
         "kernels": per_kernel,
         "mixed_precision": prec,
         "batching": batch,
+        "multi_determinant": mdet,
         "learned_residual": resid,
         "cpu_baseline": cpu,
         "setup_s": {"half_rotation": round(t_half, 3)},
