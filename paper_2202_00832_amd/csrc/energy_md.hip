@@ -38,7 +38,6 @@
 namespace lofqmc {
 
 constexpr int MD_MAXN = 128;   // largest n_occ and n_cas (LDS tables)
-constexpr int MD_CH = 32;      // determinants per chunk of the moment sums
 
 __device__ __forceinline__ double2 csel(bool c, double2 a, double2 b) {
   return make_double2(c ? a.x : b.x, c ? a.y : b.y);
@@ -59,59 +58,73 @@ __global__ __launch_bounds__(256) void md_prep_kernel(int M, int n, int nao, int
                                                       double2* __restrict__ ovr) {
   constexpr int NA2 = NA * NA;
   constexpr int NA4 = NA2 * NA2;
-  constexpr int NV = (NA + 1) / 2;             // virtual orbitals per thread in the T product
   constexpr int NE = (NA4 + 255) / 256;        // Omega entries per thread
+  constexpr int CH = NA <= 5 ? 128 : 64;       // determinants per round (LDS: CH x NA^2 complex)
+  constexpr int RG = 4;                        // row groups of the T product
+  // one LDS buffer serves the row-group partial sums of T ([RG][NA][64])
+  // and then the inverses of a round of determinants ([CH][NA^2])
+  constexpr int NBUF = CH * NA2 > RG * NA * 64 ? CH * NA2 : RG * NA * 64;
   __shared__ double2 sT[NA][MD_MAXN];
-  __shared__ double2 sB[MD_CH][NA2];
-  __shared__ double2 sW[MD_CH];
+  __shared__ double2 sBuf[NBUF];
+  __shared__ double2 sW[CH];
   __shared__ double2 sS;
+  double2 (*sB)[NA2] = reinterpret_cast<double2 (*)[NA2]>(sBuf);
   const int64_t w = blockIdx.x;
   const int tid = threadIdx.x;
 
-  // T[v][c] = sum_r C_av[r][v] theta[r][c]: thread (g, c) takes column c and
-  // the virtual orbitals g, g + 2, ...
+  // T[v][c] = sum_r C_av[r][v] theta[r][c]: thread (rg, c) sums the rows
+  // r = rg, rg + RG, ... of column c for every v (four short dependency
+  // chains per column instead of one long one), then the row groups are added
+  // in a fixed order through LDS
   {
-    const int c = tid & 127, g = tid >> 7;
-    double2 acc[NV];
+    const int c = tid & 63, rg = tid >> 6;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int cc = c0 + c;
+      double2 acc[NA];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = make_double2(0.0, 0.0);
-    if (c < n) {
-      const double2* th = theta + c * so + w * sw;
-      int r = 0;
-      for (; r + 4 <= M; r += 4) {
-        double2 t[4];
+      for (int v = 0; v < NA; ++v) acc[v] = make_double2(0.0, 0.0);
+      if (cc < n) {
+        const double2* th = theta + cc * so + w * sw;
+        int r = rg;
+        for (; r + 3 * RG < M; r += 4 * RG) {
+          double2 t[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = th[(r + u) * sr];
+          for (int u = 0; u < 4; ++u) t[u] = th[(r + u * RG) * sr];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int q = 0; q < NV; ++q) {
-            const int v = g + 2 * q;
-            const double cv = v < nav ? cav[(size_t)(r + u) * nav + v] : 0.0;
-            acc[q].x += cv * t[u].x;
-            acc[q].y += cv * t[u].y;
+            for (int v = 0; v < NA; ++v) {
+              const double cv = v < nav ? cav[(size_t)(r + u * RG) * nav + v] : 0.0;
+              acc[v].x += cv * t[u].x;
+              acc[v].y += cv * t[u].y;
+            }
+        }
+        for (; r < M; r += RG) {
+          const double2 t = th[r * sr];
+#pragma unroll
+          for (int v = 0; v < NA; ++v) {
+            const double cv = v < nav ? cav[(size_t)r * nav + v] : 0.0;
+            acc[v].x += cv * t.x;
+            acc[v].y += cv * t.y;
           }
-      }
-      for (; r < M; ++r) {
-        const double2 t = th[r * sr];
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          const int v = g + 2 * q;
-          const double cv = v < nav ? cav[(size_t)r * nav + v] : 0.0;
-          acc[q].x += cv * t.x;
-          acc[q].y += cv * t.y;
         }
       }
-    }
-    if (c < n) {
+      double2* part = sBuf;                      // [RG][NA][64] partial sums
 #pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        const int v = g + 2 * q;
-        if (v < NA) sT[v][c] = acc[q];
+      for (int v = 0; v < NA; ++v) part[(rg * NA + v) * 64 + c] = acc[v];
+      __syncthreads();
+      if (rg == 0 && cc < n) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+          double2 t = part[v * 64 + c];
+#pragma unroll
+          for (int g = 1; g < RG; ++g) t = cadd(t, part[(g * NA + v) * 64 + c]);
+          sT[v][cc] = t;
+        }
       }
+      __syncthreads();
     }
   }
-  __syncthreads();
   for (int e = tid; e < NA * n; e += 256) tau[(w * NA + e / n) * n + e % n] = sT[e / n][e % n];
 
   double2 bacc = make_double2(0.0, 0.0);
@@ -121,8 +134,8 @@ __global__ __launch_bounds__(256) void md_prep_kernel(int M, int n, int nao, int
   double2 sacc = make_double2(0.0, 0.0);
   const int act0 = n - nao;
 
-  for (int d0 = 0; d0 < ndet; d0 += MD_CH) {
-    if (tid < MD_CH) {
+  for (int d0 = 0; d0 < ndet; d0 += CH) {
+    if (tid < CH) {
       const int d = d0 + tid;
 #pragma unroll
       for (int e = 0; e < NA2; ++e) sB[tid][e] = make_double2(0.0, 0.0);
@@ -216,7 +229,7 @@ __global__ __launch_bounds__(256) void md_prep_kernel(int M, int n, int nao, int
       sW[tid] = wgt;
     }
     __syncthreads();
-    const int nd = ndet - d0 < MD_CH ? ndet - d0 : MD_CH;
+    const int nd = ndet - d0 < CH ? ndet - d0 : CH;
     for (int dd = 0; dd < nd; ++dd) {
       const double2 wg = sW[dd];
       if (tid < NA2) bacc = cfma(wg, sB[dd][tid], bacc);
