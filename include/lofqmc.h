@@ -322,8 +322,9 @@ int lo_md_info(const lo_md* md, int64_t* n_occ, int64_t* n_cas, int64_t* n_det, 
  *                w_d = c_d det(R_d)^2 / sum_d' c_d' det(R_d')^2
  *   ovlp_ratio : complex [nw] or NULL: sum_d c_d det(R_d)^2, i.e.
  *                <psi_T|phi> / det(Phi_0^T phi)^2 (zero gives NaN energies)
- * LO_EUNSUPPORTED if out_rows x nw exceeds 2^31 - 1 (evaluate fewer walkers
- * per call). */
+ * The context workspace grows to out_rows x nw complex values plus
+ * nw x (NA n_occ + NA^2 + NA^4) complex values, NA = max(n_act_occ, n_cas - n_occ),
+ * plus the partial sums. */
 int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* theta, const int32_t* info,
                     unsigned flags, double* energy, double* ovlp_ratio);
 

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
                                                           const int* __restrict__ blk, int nblk, int tmax,
                                                           const double2* __restrict__ theta, int64_t so,
                                                           int64_t sr, int64_t sw, double2* __restrict__ qbar,
-                                                          int nwt) {
+                                                          int64_t orow, int64_t ow, int nwt) {
   __shared__ double sA[2][LO_TILE_ROWS][17];   // [row][r], padded against bank conflicts
   __shared__ double2 sB[2][16][LO_WT];         // [r][walker]
   int t;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
         for (int q = 0; q < LO_QG; ++q) {
           const int lrow = rw + 4 * q + lk;
           if (lrow < nrows)
-            qbar[(size_t)(row0 + lrow) * nw + w] = make_double2(acc[q][2 * h], acc[q][2 * h + 1]);
+            qbar[(size_t)(row0 + lrow) * orow + w * ow] = make_double2(acc[q][2 * h], acc[q][2 * h + 1]);
         }
       }
     }
@@ -168,7 +168,7 @@ int lo_orbital_block() { return LO_OBLK; }
 
 hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
                            const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
-                           const double* theta, int orbital_major, double* qbar) {
+                           const double* theta, int orbital_major, double* qbar, int64_t out_walker_stride) {
   if (nw <= 0 || ntiles <= 0) return hipSuccess;
   const int nwt = (int)((nw + LO_WT - 1) / LO_WT);
   const int64_t units = (int64_t)nblk * nwt;
@@ -178,7 +178,8 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
   const int64_t sw = orbital_major ? 1 : (int64_t)M * n;
   hipLaunchKernelGGL(lo_pass1_kernel, dim3((unsigned)grid), dim3(512), 0, s, M, nw, rows, rowidx, tiles,
                      tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax, (const double2*)theta, so, sr, sw,
-                     (double2*)qbar, nwt);
+                     (double2*)qbar, out_walker_stride ? (int64_t)1 : nw,
+                     out_walker_stride ? out_walker_stride : (int64_t)1, nwt);
   return hipGetLastError();
 }
 // Pass 2: one thread per walker, a contiguous chunk of pairs per grid row.

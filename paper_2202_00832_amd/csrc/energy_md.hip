@@ -263,6 +263,7 @@ __global__ __launch_bounds__(256) void md_energy_kernel(int n, int ncas, int nao
                                                         const int64_t* __restrict__ offI,
                                                         const int64_t* __restrict__ offJ,
                                                         const int64_t* __restrict__ offA, int64_t act_stride,
+                                                        int64_t n_out,
                                                         const double2* __restrict__ qbar,
                                                         const double2* __restrict__ tau,
                                                         const double2* __restrict__ bbar,
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(256) void md_energy_kernel(int n, int ncas, int nao
   }
   __syncthreads();
 
-  const double2* __restrict__ qw = qbar + w;
+  const double2* __restrict__ qw = qbar + w * n_out;
   const int as32 = (int)act_stride;
   const int p0 = chunk * per_chunk;
   const int p1 = p0 + per_chunk < npairs ? p0 + per_chunk : npairs;
@@ -316,13 +317,13 @@ __global__ __launch_bounds__(256) void md_energy_kernel(int n, int ncas, int nao
       mj[a] = sMu[j][a];
     }
     const bool own_i = i < n, own_j = j < n;
-    // element offsets from the walker's (uniform) base fit 32 bits (the host
-    // bounds rows x nw); an active virtual orbital has no own column: its loads
-    // read the pair's first active-column rows and are then replaced by zero
+    // the walker's projections are contiguous rows (qbar is [nw][n_out], so
+    // the 64 pairs of a wave read nearby rows); an active virtual orbital has
+    // no own column: its loads read the pair's first active-column rows and
+    // are then replaced by zero
     const int rA = (int)offA[p];
     const int rI = own_i ? (int)offI[p] : rA;
     const int rJ = own_j ? (int)offJ[p] : rA;
-    const int nw32 = (int)nw;
     double2 J = make_double2(0.0, 0.0), X = make_double2(0.0, 0.0);
     double2 G[NA][NA];
 #pragma unroll
@@ -332,17 +333,17 @@ __global__ __launch_bounds__(256) void md_energy_kernel(int n, int ncas, int nao
 #pragma unroll 1
     for (int k = 0; k < K; ++k) {
       const double2 z = make_double2(0.0, 0.0);
-      const double2 pli = csel(own_i, qw[(rI + k) * nw32], z);
-      const double2 pri = csel(own_i, qw[(rI + K + k) * nw32], z);
-      const double2 plj = csel(own_j, qw[(rJ + k) * nw32], z);
-      const double2 prj = csel(own_j, qw[(rJ + K + k) * nw32], z);
+      const double2 pli = csel(own_i, qw[rI + k], z);
+      const double2 pri = csel(own_i, qw[rI + K + k], z);
+      const double2 plj = csel(own_j, qw[rJ + k], z);
+      const double2 prj = csel(own_j, qw[rJ + K + k], z);
       double2 la[NA], ra[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
         // padded active columns (a >= nao) read column 0 and are zeroed
         const int ra0 = rA + (a < nao ? a : 0) * as32;
-        la[a] = csel(a < nao, qw[(ra0 + k) * nw32], z);
-        ra[a] = csel(a < nao, qw[(ra0 + K + k) * nw32], z);
+        la[a] = csel(a < nao, qw[ra0 + k], z);
+        ra[a] = csel(a < nao, qw[ra0 + K + k], z);
       }
       double2 sLi = z, sRi = z, sLj = z, sRj = z;
 #pragma unroll
@@ -447,7 +448,7 @@ static hipError_t launch_pairs_na(hipStream_t s, const MdArgs& g, const MdWork& 
   const int per = (g.npairs + nchunk - 1) / nchunk;
   const int64_t nw8 = (g.nw + 7) / 8;
   hipLaunchKernelGGL((md_energy_kernel<NA>), dim3((unsigned)(8 * nw8), nchunk), dim3(256), 0, s, g.n, g.ncas, g.nao,
-                     g.nw, g.npairs, per, g.pi, g.pj, g.pK, g.offI, g.offJ, g.offA, g.act_stride,
+                     g.nw, g.npairs, per, g.pi, g.pj, g.pK, g.offI, g.offJ, g.offA, g.act_stride, g.n_out,
                      (const double2*)g.qbar, m.tau, m.bbar, m.omega, partial);
   return hipGetLastError();
 }

@@ -44,9 +44,11 @@ hipError_t launch_reduce_partials(hipStream_t s, int64_t nw, int nchunk, const d
 // tiles: device int [3][ntiles] (orbital, first output row, row count), tiles
 // sorted by orbital; blk: device int [nblk + 1], first tile of each block of
 // lo_orbital_block() orbitals; tmax: most tiles in one block.
+// qbar: output row r of walker w at r * nw + w (walkers fastest), or, with a
+// nonzero out_walker_stride, at w * out_walker_stride + r (rows fastest)
 hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
                            const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
-                           const double* theta, int orbital_major, double* qbar);
+                           const double* theta, int orbital_major, double* qbar, int64_t out_walker_stride);
 int lo_tile_rows();
 int lo_lp_tile_rows();
 int lo_orbital_block();
@@ -117,10 +119,10 @@ hipError_t launch_hr_energy(hipStream_t s, int M, int n, int64_t nw, int npairs,
 // max(nao, nav); hole and particle indices relative to the active sets), the
 // pair tables (own output rows of orbitals i, j or -1, first output row of the
 // pair's rows in the active-column region, act_stride rows per active column)
-// and the pass-1 output qbar.
+// and the pass-1 output qbar, rows fastest ([nw][n_out]).
 struct MdArgs {
   int M, n, ncas, nao, nav, ndet, hstride, npairs;
-  int64_t nw, so, sr, sw, act_stride;
+  int64_t nw, so, sr, sw, act_stride, n_out;
   const double* cav;
   const double* theta;
   const int* exc;

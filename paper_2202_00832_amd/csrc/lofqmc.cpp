@@ -1038,9 +1038,6 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   if (!md) return fail(ctx, LO_EINVAL, "null trial");
   if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
   if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
-  // the pair kernel addresses qbar with 32-bit element offsets from a walker's base
-  if (nw > 0 && md->n_out_rows > (((int64_t)1 << 31) - 1) / nw)
-    return fail(ctx, LO_EUNSUPPORTED, "output rows x walkers above 2^31-1: evaluate fewer walkers per call");
   if (nw == 0) return LO_OK;
   if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
   const lo_factors* f = md->f;
@@ -1069,6 +1066,7 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   g.sr = om ? nw : md->n;
   g.sw = om ? 1 : md->M * md->n;
   g.act_stride = md->total_rows;
+  g.n_out = md->n_out_rows;
   g.cav = md->cav;
   g.theta = theta;
   g.exc = md->d_exc;
@@ -1086,7 +1084,7 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   prof.mark("lo_pass1_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)md->M, (int)md->n, nw, md->ntiles, f->rows,
                                            md->d_rowidx, md->d_tiles, md->d_tiles + 3 * md->ntiles, md->nblk,
-                                           md->tmax, theta, om ? 1 : 0, qbar));
+                                           md->tmax, theta, om ? 1 : 0, qbar, md->n_out_rows));
   prof.mark("md_prep_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_md_prep(ctx->stream, g, mwork, ovlp_ratio));
   prof.mark("md_energy_kernel");
@@ -1200,7 +1198,7 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
     prof.mark("lo_pass1_kernel");
     HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
                                              f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
-                                             orbital_major ? 1 : 0, qbar));
+                                             orbital_major ? 1 : 0, qbar, 0));
   } else if (f->ntiles > 0) {
     void* tlp = base + qbytes + pbytes;
     prof.mark("lp_convert_kernel");
