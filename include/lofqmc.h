@@ -38,7 +38,7 @@ enum lo_status {
   LO_EINVAL = -1,        /* bad argument (NULL, negative or inconsistent size, eps < 0 or NaN) */
   LO_ENOMEM = -2,        /* device or host allocation failed */
   LO_EHIP = -3,          /* a HIP runtime call failed */
-  LO_EUNSUPPORTED = -4,  /* valid request outside what this build implements */
+  LO_EUNSUPPORTED = -4,  /* valid request outside what this library implements */
   LO_ESOLVER = -5        /* the dense SVD used while building LO factors failed */
 };
 
