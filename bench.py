@@ -459,12 +459,34 @@ def md_study(torch, lofqmc, synth, steps, warmup, baseline_steps=2):
     diff = float(np.abs(e_md - e_pd.cpu().numpy()).max())
     log("per-determinant evaluation: %.1f ms/step, max |E_md - E_per_det| %.2e Ha" % (pd_ms, diff))
     own = [k for k in kern if k.startswith("md_") or k == "lo_pass1_kernel" or k == "reduce_partials_kernel"]
+    # algorithmic work per launch (unpadded sizes): pass 1 as in the single-
+    # determinant route; md_prep: T = C_av^T theta, a Gauss-Jordan inverse of
+    # every eps_d x eps_d R_d and its eps_d^4 moment products; md_energy: per
+    # pair and rank row the own products, the four mean projections and the
+    # outer product G, then the NA^4 contraction with Omega and two NA^2 forms
+    nao, nav = cfg.n_act_occ, cfg.n_act_virt
+    finfo = f.info()
+    ranks = finfo["ranks"]
+    iu = np.triu_indices(ncas)
+    Ks = ranks[iu][ranks[iu] > 0].astype(np.float64)
+    eps_d = np.array([len(h) for h in s.holes], dtype=np.float64)
+    mdwork = {
+        "lo_pass1_kernel": ("mfma", 4.0 * M * md.out_rows * nw,
+                            8.0 * M * finfo["total_rows"] + 16.0 * nw * (M * n + md.out_rows)),
+        "md_prep_kernel": ("alu", nw * (4.0 * M * nav * n + np.sum(8.0 * eps_d ** 3 + 16.0 * eps_d ** 4)),
+                           16.0 * nw * (M * n + nao * nav * (1 + nao * nav))),
+        "md_energy_kernel": ("alu", nw * 8.0 * float(np.sum(Ks * (2 + 4 * nao + nao * nao)
+                                                           + (nao * nav) ** 2 + 2 * nav * nav)),
+                             16.0 * nw * md.out_rows),
+    }
+    md_roof = {k: roofline_of(k, mdwork, kern[k][1] / kern[k][0]) for k in mdwork if k in kern}
     out = {"workload": cfg.name, "M": M, "n_occ": n, "n_cas": ncas, "n_act_occ": cfg.n_act_occ,
            "n_act_virt": cfg.n_act_virt, "n_det": ndet, "max_exc": cfg.max_exc, "walkers": nw,
            "epsilon": cfg.epsilon, "n_chol": s.chol.shape[0], "setup_s": round(setup_s, 2),
            "value": round(nw / (ms * 1e-3), 1), "unit": "walker-energies/s", "ms_per_step": round(ms, 4),
            "local_energy_md_ms": round(float(np.mean(split["b->c"])), 4),
            "kernel_us": {k: round(kern[k][1] / kern[k][0] * 1e3, 2) for k in own},
+           "kernels": md_roof,
            "pass1_out_rows": md.out_rows, "pairs": md.npairs,
            "per_determinant_ms_per_step": round(pd_ms, 2),
            "smw_speedup_vs_per_determinant": round(pd_ms / ms, 1),

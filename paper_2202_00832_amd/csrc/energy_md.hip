@@ -25,7 +25,9 @@
 // (QL(v) = sum_a v_a QL_a).  The sum over determinants is done once per
 // walker; the per-pair work does not grow with the number of determinants.
 //
-// md_prep_kernel: one workgroup per walker: T, the pivoted Gauss-Jordan
+// Pass 1 forms T next to every orbital's own projections (the active virtual
+// orbitals are extra rows of its tile).
+// md_prep_kernel: one workgroup per walker: the pivoted Gauss-Jordan
 // inverse and determinant of every padded R_d (eps <= 6, identity-padded to
 // NA x NA, so every determinant runs the same branch-free code), the
 // unnormalised moments summed over determinants in a fixed order, then scaled
@@ -48,10 +50,10 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
 }
 
 template <int NA>
-__global__ __launch_bounds__(256) void md_prep_kernel(int M, int n, int nao, int nav, int ndet, int hstride,
-                                                      const double* __restrict__ cav,
-                                                      const double2* __restrict__ theta, int64_t so, int64_t sr,
-                                                      int64_t sw, const int* __restrict__ exc,
+__global__ __launch_bounds__(256) void md_prep_kernel(int n, int nao, int nav, int ndet, int hstride,
+                                                      const int* __restrict__ tpos,
+                                                      const double2* __restrict__ qbar, int64_t n_out,
+                                                      const int* __restrict__ exc,
                                                       const int* __restrict__ holes, const int* __restrict__ parts,
                                                       const double* __restrict__ coef, double2* __restrict__ tau,
                                                       double2* __restrict__ bbar, double2* __restrict__ omega,
@@ -60,72 +62,22 @@ __global__ __launch_bounds__(256) void md_prep_kernel(int M, int n, int nao, int
   constexpr int NA4 = NA2 * NA2;
   constexpr int NE = (NA4 + 255) / 256;        // Omega entries per thread
   constexpr int CH = NA <= 5 ? 128 : 64;       // determinants per round (LDS: CH x NA^2 complex)
-  constexpr int RG = 4;                        // row groups of the T product
-  // one LDS buffer serves the row-group partial sums of T ([RG][NA][64])
-  // and then the inverses of a round of determinants ([CH][NA^2])
-  constexpr int NBUF = CH * NA2 > RG * NA * 64 ? CH * NA2 : RG * NA * 64;
   __shared__ double2 sT[NA][MD_MAXN];
-  __shared__ double2 sBuf[NBUF];
+  __shared__ double2 sB[CH][NA2];
   __shared__ double2 sW[CH];
   __shared__ double2 sS;
-  double2 (*sB)[NA2] = reinterpret_cast<double2 (*)[NA2]>(sBuf);
   const int64_t w = blockIdx.x;
   const int tid = threadIdx.x;
 
-  // T[v][c] = sum_r C_av[r][v] theta[r][c]: thread (rg, c) sums the rows
-  // r = rg, rg + RG, ... of column c for every v (four short dependency
-  // chains per column instead of one long one), then the row groups are added
-  // in a fixed order through LDS
-  {
-    const int c = tid & 63, rg = tid >> 6;
-    for (int c0 = 0; c0 < n; c0 += 64) {
-      const int cc = c0 + c;
-      double2 acc[NA];
-#pragma unroll
-      for (int v = 0; v < NA; ++v) acc[v] = make_double2(0.0, 0.0);
-      if (cc < n) {
-        const double2* th = theta + cc * so + w * sw;
-        int r = rg;
-        for (; r + 3 * RG < M; r += 4 * RG) {
-          double2 t[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) t[u] = th[(r + u * RG) * sr];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < NA; ++v) {
-              const double cv = v < nav ? cav[(size_t)(r + u * RG) * nav + v] : 0.0;
-              acc[v].x += cv * t[u].x;
-              acc[v].y += cv * t[u].y;
-            }
-        }
-        for (; r < M; r += RG) {
-          const double2 t = th[r * sr];
-#pragma unroll
-          for (int v = 0; v < NA; ++v) {
-            const double cv = v < nav ? cav[(size_t)r * nav + v] : 0.0;
-            acc[v].x += cv * t.x;
-            acc[v].y += cv * t.y;
-          }
-        }
-      }
-      double2* part = sBuf;                      // [RG][NA][64] partial sums
-#pragma unroll
-      for (int v = 0; v < NA; ++v) part[(rg * NA + v) * 64 + c] = acc[v];
-      __syncthreads();
-      if (rg == 0 && cc < n) {
-#pragma unroll
-        for (int v = 0; v < NA; ++v) {
-          double2 t = part[v * 64 + c];
-#pragma unroll
-          for (int g = 1; g < RG; ++g) t = cadd(t, part[(g * NA + v) * 64 + c]);
-          sT[v][cc] = t;
-        }
-      }
-      __syncthreads();
-    }
+  // T[v][c] = C_av[:, v] . theta_c, formed by pass 1 next to orbital c's own rows
+  const double2* qw = qbar + w * n_out;
+  for (int e = tid; e < NA * n; e += 256) {
+    const int v = e / n, c = e % n;
+    const double2 t = v < nav ? qw[tpos[c] + v] : make_double2(0.0, 0.0);
+    sT[v][c] = t;
+    tau[(w * NA + v) * n + c] = t;
   }
-  for (int e = tid; e < NA * n; e += 256) tau[(w * NA + e / n) * n + e % n] = sT[e / n][e % n];
+  __syncthreads();
 
   double2 bacc = make_double2(0.0, 0.0);
   double2 oacc[NE];
@@ -437,9 +389,9 @@ static MdWork md_work(const MdArgs& g, void* work) {
 
 template <int NA>
 static hipError_t launch_prep_na(hipStream_t s, const MdArgs& g, const MdWork& m, double2* ovr) {
-  hipLaunchKernelGGL((md_prep_kernel<NA>), dim3((unsigned)g.nw), dim3(256), 0, s, g.M, g.n, g.nao, g.nav, g.ndet,
-                     g.hstride, g.cav, (const double2*)g.theta, g.so, g.sr, g.sw, g.exc, g.holes, g.parts, g.coef,
-                     m.tau, m.bbar, m.omega, ovr);
+  hipLaunchKernelGGL((md_prep_kernel<NA>), dim3((unsigned)g.nw), dim3(256), 0, s, g.n, g.nao, g.nav, g.ndet,
+                     g.hstride, g.tpos, (const double2*)g.qbar, g.n_out, g.exc, g.holes, g.parts, g.coef, m.tau,
+                     m.bbar, m.omega, ovr);
   return hipGetLastError();
 }
 

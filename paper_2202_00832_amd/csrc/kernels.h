@@ -114,17 +114,16 @@ hipError_t launch_hr_energy(hipStream_t s, int M, int n, int64_t nw, int npairs,
                             const double* theta, int orbital_major, double* partial);
 
 // ---- multi-determinant LO energy
-// Arguments of one evaluation: theta (reference determinant, strides so, sr,
-// sw), C_av [M][nav], determinant tables [ndet][hstride] (hstride >= NA =
-// max(nao, nav); hole and particle indices relative to the active sets), the
-// pair tables (own output rows of orbitals i, j or -1, first output row of the
-// pair's rows in the active-column region, act_stride rows per active column)
-// and the pass-1 output qbar, rows fastest ([nw][n_out]).
+// Arguments of one evaluation: the pass-1 output qbar, rows fastest
+// ([nw][n_out]), with T[v][o] = C_av[:, v] . theta_o at row tpos[o] + v; the
+// determinant tables [ndet][hstride] (hstride >= NA = max(nao, nav); hole and
+// particle indices relative to the active sets); the pair tables (own output
+// rows of orbitals i, j or -1, first output row of the pair's rows in the
+// active-column region, act_stride rows per active column).
 struct MdArgs {
   int M, n, ncas, nao, nav, ndet, hstride, npairs;
-  int64_t nw, so, sr, sw, act_stride, n_out;
-  const double* cav;
-  const double* theta;
+  int64_t nw, act_stride, n_out;
+  const int* tpos;
   const int* exc;
   const int* holes;
   const int* parts;

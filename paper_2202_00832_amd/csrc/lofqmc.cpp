@@ -56,15 +56,17 @@ struct lo_factors {
 struct lo_md {
   int64_t M = 0, n = 0, ncas = 0, nao = 0, nav = 0, ndet = 0, maxe = 0;
   int na = 0;
-  const lo_factors* f = nullptr;  // not owned: the factor rows are read at every evaluation
-  double* cav = nullptr;          // device [M][nav]: the active virtual orbitals
+  const lo_factors* f = nullptr;  // not owned
+  double* rows = nullptr;         // device [total_rows + nav][M]: the factor rows, then C_av^T
   int* d_exc = nullptr;           // [ndet]
   int* d_holes = nullptr;         // [ndet][na], relative to the first active occupied column
   int* d_parts = nullptr;         // [ndet][na], relative to column n
   double* d_coef = nullptr;       // [ndet]
   int64_t n_out_rows = 0, act_base = 0, total_rows = 0;
   int ntiles = 0, nblk = 0, tmax = 0, npairs = 0;
-  int* d_rowidx = nullptr;        // pass-1 gather table: own rows of orbitals < n, then na copies of all rows
+  int* d_rowidx = nullptr;        // pass-1 gather table: per orbital < n its own rows then the nav C_av^T
+                                  // rows (T = C_av^T theta), then every factor row once per active column
+  int* d_tpos = nullptr;          // [n]: output row of T[0][o]
   int* d_tiles = nullptr;         // [3][ntiles] then [nblk + 1]
   int* d_pair = nullptr;          // [3][npairs]: i, j, K
   int64_t* d_off = nullptr;       // [3][npairs]: own rows of i and j (-1 if virtual), first active row
@@ -838,7 +840,8 @@ int local_energy_hr(lo_ctx* ctx, const lo_hr* h, int64_t nw, const double* theta
 
 int lo_md_destroy(lo_md* md) {
   if (!md) return LO_OK;
-  (void)hipFree(md->cav);
+  (void)hipFree(md->rows);
+  (void)hipFree(md->d_tpos);
   (void)hipFree(md->d_exc);
   (void)hipFree(md->d_holes);
   (void)hipFree(md->d_parts);
@@ -896,29 +899,34 @@ int build_md_trial(lo_ctx* ctx, const lo_factors* f, int64_t n_occ, int64_t n_ac
     if (!std::isfinite(coef[d])) return fail(ctx, LO_EINVAL, "non-finite coefficient");
   }
   // output rows of pass 1: each orbital o < n_occ's own rows (as in the
-  // single-determinant tables, restricted to the reference's orbitals), then
-  // every factor row once per active occupied column
+  // single-determinant tables, restricted to the reference's orbitals)
+  // followed by the nav rows of C_av^T, whose products with theta_o are
+  // T[v][o]; then every factor row once per active occupied column
   const int64_t total = f->total_rows;
   std::vector<int64_t> obase(n_occ + 1, 0), loc(n_occ * ncas, 0);
+  std::vector<int> tpos(n_occ);
   for (int64_t o = 0; o < n_occ; ++o) {
     int64_t R = 0;
     for (int64_t k = 0; k < ncas; ++k) {
       loc[o * ncas + k] = R;
       R += 2 * (int64_t)f->ranks[o * ncas + k];
     }
-    obase[o + 1] = obase[o] + R;
+    tpos[o] = (int)(obase[o] + R);
+    obase[o + 1] = obase[o] + R + nav;
   }
   const int64_t act_base = obase[n_occ];
   const int64_t n_out = act_base + n_act_occ * total;
   if (n_out > std::numeric_limits<int>::max()) return fail(ctx, LO_EUNSUPPORTED, "too many factor rows");
   std::vector<int> rowidx((size_t)n_out);
-  for (int64_t o = 0; o < n_occ; ++o)
+  for (int64_t o = 0; o < n_occ; ++o) {
     for (int64_t k = 0; k < ncas; ++k) {
       const int64_t i = std::min(o, k), j = std::max(o, k);
       const int64_t src = f->row_offset[i * ncas + j];
       const int64_t cnt = 2 * (int64_t)f->ranks[o * ncas + k];
       for (int64_t q = 0; q < cnt; ++q) rowidx[obase[o] + loc[o * ncas + k] + q] = (int)(src + q);
     }
+    for (int64_t v = 0; v < nav; ++v) rowidx[tpos[o] + v] = (int)(total + v);
+  }
   for (int64_t a = 0; a < n_act_occ; ++a)
     for (int64_t r = 0; r < total; ++r) rowidx[act_base + a * total + r] = (int)r;
   // pass-1 tiles: own rows per orbital in blocks of lo_orbital_block()
@@ -998,22 +1006,35 @@ int build_md_trial(lo_ctx* ctx, const lo_factors* f, int64_t n_occ, int64_t n_ac
   if ((rc = upload(ctx, &md->d_exc, exc)) || (rc = upload(ctx, &md->d_holes, hrel)) ||
       (rc = upload(ctx, &md->d_parts, prel)) || (rc = upload(ctx, &md->d_coef, coef)) ||
       (rc = upload(ctx, &md->d_rowidx, rowidx)) || (rc = upload(ctx, &md->d_tiles, tiles)) ||
+      (rc = upload(ctx, &md->d_tpos, tpos)) ||
       (!pair.empty() && (rc = upload(ctx, &md->d_pair, pair))) || (!off.empty() && (rc = upload(ctx, &md->d_off, off)))) {
     lo_md_destroy(md);
     return rc;
   }
+  // the pass-1 rows: the factor rows, then C_av^T (row v = orbital n_occ + v)
+  std::vector<double> cav((size_t)nav * M);
   if (nav > 0) {
-    if (hipMalloc(&md->cav, sizeof(double) * (size_t)M * nav) != hipSuccess) {
-      md->cav = nullptr;
+    std::vector<double> C((size_t)M * ncas);
+    if (hipMemcpy(C.data(), orbitals, sizeof(double) * C.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+      lo_md_destroy(md);
+      return fail(ctx, LO_EHIP, "copy of the orbitals failed");
+    }
+    for (int64_t v = 0; v < nav; ++v)
+      for (int64_t r = 0; r < M; ++r) cav[v * M + r] = C[r * ncas + n_occ + v];
+  }
+  if (total + nav > 0) {
+    if (hipMalloc(&md->rows, sizeof(double) * (size_t)(total + nav) * M) != hipSuccess) {
+      md->rows = nullptr;
       lo_md_destroy(md);
       return fail(ctx, LO_ENOMEM, "device allocation failed");
     }
-    // C_av [M][nav] from the columns n_occ .. n_cas - 1 of the orbitals
-    if (hipMemcpy2DAsync(md->cav, sizeof(double) * nav, orbitals + n_occ, sizeof(double) * ncas,
-                         sizeof(double) * nav, M, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+    if ((total > 0 && hipMemcpyAsync(md->rows, f->rows, sizeof(double) * (size_t)total * M, hipMemcpyDeviceToDevice,
+                                     ctx->stream) != hipSuccess) ||
+        (nav > 0 && hipMemcpyAsync(md->rows + (size_t)total * M, cav.data(), sizeof(double) * cav.size(),
+                                   hipMemcpyHostToDevice, ctx->stream) != hipSuccess) ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
       lo_md_destroy(md);
-      return fail(ctx, LO_EHIP, "copy of the active virtual orbitals failed");
+      return fail(ctx, LO_EHIP, "copy of the factor rows failed");
     }
   }
   *out = md;
@@ -1040,7 +1061,6 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   if (nw == 0) return LO_OK;
   if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
-  const lo_factors* f = md->f;
   const bool om = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
   const int nchunk = lofqmc::md_pair_chunks(md->npairs);
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)md->n_out_rows * nw);
@@ -1062,13 +1082,9 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   g.hstride = md->na;
   g.npairs = md->npairs;
   g.nw = nw;
-  g.so = om ? md->M * nw : 1;
-  g.sr = om ? nw : md->n;
-  g.sw = om ? 1 : md->M * md->n;
   g.act_stride = md->total_rows;
   g.n_out = md->n_out_rows;
-  g.cav = md->cav;
-  g.theta = theta;
+  g.tpos = md->d_tpos;
   g.exc = md->d_exc;
   g.holes = md->d_holes;
   g.parts = md->d_parts;
@@ -1082,7 +1098,7 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   g.qbar = qbar;
   ProfScope prof(ctx);
   prof.mark("lo_pass1_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)md->M, (int)md->n, nw, md->ntiles, f->rows,
+  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)md->M, (int)md->n, nw, md->ntiles, md->rows,
                                            md->d_rowidx, md->d_tiles, md->d_tiles + 3 * md->ntiles, md->nblk,
                                            md->tmax, theta, om ? 1 : 0, qbar, md->n_out_rows));
   prof.mark("md_prep_kernel");
