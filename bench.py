@@ -178,6 +178,41 @@ def hr_study(torch, ctx, lbar, trial_d, phi_d, info, energy, e_full_h, work, M, 
     return out
 
 
+def event_ms(torch, fn, reps=50, warm=5):
+    """Mean ms per call of fn() over reps calls between two events, after warm calls."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def few_walker_study(torch, ctx, lbar, trial_d, phi_d, factors, nw=16):
+    """The paper's timing shape (Sec. 3, dodecane: the energy evaluation of 16
+    walkers, LO at each threshold against the HR-ERI code): energy calls only,
+    on the first 16 walkers of the workload."""
+    phi = phi_d[:nw].contiguous()
+    th, _, inf = ctx.green_theta(trial_d, phi)
+    th_om, _, inf_om = ctx.green_theta(trial_d, phi, orbital_major=True)
+    hr = ctx.build_hr_eri(lbar)
+    hr_ms = event_ms(torch, lambda: ctx.local_energy_hr(hr, th_om, inf_om, orbital_major=True))
+    out = {"walkers": nw, "local_energy_hr_ms": round(hr_ms, 4), "lo": {}}
+    for eps, f in factors.items():
+        lo_ms = event_ms(torch, lambda f=f: ctx.local_energy_lo(f, th, inf))
+        out["lo"]["%g" % eps] = {"local_energy_lo_ms": round(lo_ms, 4), "speedup_vs_hr": round(hr_ms / lo_ms, 1)}
+    hr.close()
+    log("16 walkers: HR-ERI %.3f ms, LO %s" % (hr_ms, ", ".join("%s %.3f ms (%.0fx)" % (k, v["local_energy_lo_ms"],
+                                                                                          v["speedup_vs_hr"])
+                                                               for k, v in out["lo"].items())))
+    return out
+
+
 def precision_study(torch, lofqmc, synth, steps):
     """Full route with the exchange contraction in FP64, FP32 and split BF16 on
     the 500-site chain (48 orbitals, 1024 walkers): time per step and error of
@@ -491,6 +526,18 @@ def md_study(torch, lofqmc, synth, steps, warmup, baseline_steps=2):
            "per_determinant_ms_per_step": round(pd_ms, 2),
            "smw_speedup_vs_per_determinant": round(pd_ms / ms, 1),
            "max_abs_diff_vs_per_determinant_Ha": diff}
+    # cost against the number of determinants (same walkers and factors; every
+    # excitation up to quadruples: 250 besides the reference)
+    scaling = []
+    for k in (1, 20, 100, 251):
+        h, p_, c = synth.cas_expansion(n, cfg.n_act_occ, cfg.n_act_virt, k, cfg.max_exc, np.random.default_rng(k))
+        mk = ctx.build_md_trial(f, n, cfg.n_act_occ, C, h, p_, c)
+        ms_k = event_ms(torch, lambda mk=mk: ctx.local_energy_md(mk, theta, info, energy))
+        scaling.append({"n_det": k, "local_energy_md_ms": round(ms_k, 4)})
+        mk.close()
+    out["n_det_scaling"] = scaling
+    log("local_energy_md vs determinants: %s" % ", ".join("%d: %.3f ms" % (x["n_det"], x["local_energy_md_ms"])
+                                                         for x in scaling))
     md.close()
     f.close()
     ctx.close()
@@ -677,6 +724,7 @@ def main():
         hr_out = hr_study(torch, ctx, lbar, trial_d, phi_d, info, energy, e_full_h, work, M, n, nw)
         # the paper's comparison (Sec. 3, dodecane): LO against the HR-ERI
         # energy evaluation at each threshold, energy call alone and whole step
+        hr_out["walkers16"] = few_walker_study(torch, ctx, lbar, trial_d, phi_d, factors)
         hr_out["lo_speedup"] = {
             "%g" % s["epsilon"]: {"energy_only": round(hr_out["local_energy_hr_ms"] / s["local_energy_lo_ms"], 1),
                                   "step": round(hr_out["ms_per_step"] / s["ms_per_step"], 1)} for s in sweep}
