@@ -24,7 +24,11 @@ namespace lofqmc {
 // against all 32 walkers (two 16-walker blocks, real and imaginary part) on
 // the FP64 4x4x4 MFMA: 24 accumulators, 24 MFMA per K-step from 6 + 2 LDS
 // reads.  Per 16-row slab of r the factor rows (gathered through rowidx) and
-// Q_o of the 32 walkers are staged in LDS (double-buffered).
+// Q_o of the 32 walkers are staged in LDS (double-buffered): lo_pass1_kernel
+// loads both straight into LDS one slab ahead (M a multiple of 16);
+// lo_pass1_reg_kernel, for any M, stages them through registers (theta one
+// slab ahead, the factor rows after the products, to stay at two workgroups
+// per CU) and zero-fills a partial last slab.
 //
 // theta element (o, r, w) is read at theta[o * so + r * sr + w * sw], which
 // serves both layouts: walker-major [w][r][o] and orbital-major [o][r][w].
@@ -38,7 +42,7 @@ constexpr int LO_OBLK = 8;
 constexpr int LO_WROWS = LO_TILE_ROWS / 8;   // rows per wave (24)
 constexpr int LO_QG = LO_WROWS / 4;          // 4-row groups per wave (6)
 
-__global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
+__global__ __launch_bounds__(512, 2) void lo_pass1_reg_kernel(int M, int64_t nw, const double* __restrict__ rows,
                                                           const int* __restrict__ rowidx,
                                                           const int* __restrict__ tile_orb,
                                                           const int* __restrict__ tile_row0,
@@ -163,6 +167,139 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
   }
 }
 
+// The same product with both operand tiles loaded straight into LDS
+// (global_load_lds_dwordx4: lane L of a wave writes 16 bytes at the wave's
+// LDS base + 16 L), one slab ahead, so their latency overlaps the products of
+// the current slab without holding them in registers.  Used when M is a
+// multiple of 16 (every slab full: a lane cannot zero-fill what it loads).
+// The A tile is stored unpadded with the column pairs of row r XOR-swizzled
+// by 2 (r & 3): the 4 rows x 2 column pairs of one MFMA operand read fall in 8
+// distinct 16-byte bank groups.  Rows past the tile and walkers past nw load
+// a valid address and their outputs are discarded.
+__global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
+                                                             const int* __restrict__ rowidx,
+                                                             const int* __restrict__ tile_orb,
+                                                             const int* __restrict__ tile_row0,
+                                                             const int* __restrict__ tile_nrows,
+                                                             const int* __restrict__ blk, int nblk, int tmax,
+                                                             const double2* __restrict__ theta, int64_t so,
+                                                             int64_t sr, int64_t sw, double2* __restrict__ qbar,
+                                                             int64_t orow, int64_t ow, int nwt) {
+  // two buffers as distinct objects (and the slab loop unrolled by two), so
+  // the compiler sees that the reads of one buffer and the loads in flight
+  // into the other cannot alias and does not wait for the loads before reading
+  __shared__ __attribute__((aligned(16))) double sA0[LO_TILE_ROWS * 16];   // swizzled [row][r]
+  __shared__ __attribute__((aligned(16))) double sA1[LO_TILE_ROWS * 16];
+  __shared__ __attribute__((aligned(16))) double2 sB0[16 * LO_WT];         // [r][walker]
+  __shared__ __attribute__((aligned(16))) double2 sB1[16 * LO_WT];
+  int t;
+  int64_t w0;
+  {
+    const int xcd = blockIdx.x & 7;
+    const int slot = blockIdx.x >> 3;
+    const int64_t u = 8 * (int64_t)(slot / tmax) + xcd;
+    if (u >= (int64_t)nblk * nwt) return;
+    const int b = (int)(u / nwt);
+    t = blk[b] + slot % tmax;
+    if (t >= blk[b + 1]) return;
+    w0 = (u % nwt) * LO_WT;
+  }
+  const int o = tile_orb[t];
+  const int row0 = tile_row0[t];
+  const int nrows = tile_nrows[t];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rw = LO_WROWS * wv;                // first row of this wave
+  const bool active = rw < nrows;
+  const double2* tho = theta + o * so;
+
+  // A: 192 rows x 8 column pairs = 1536 16-byte slots, three per thread: slot
+  // S = 512 k + tid holds row S / 8, column pair (S % 8) ^ (2 (row & 3))
+  constexpr int A_LD = LO_TILE_ROWS * 8 / 512;   // 3
+  const double* asrc[A_LD];
+#pragma unroll
+  for (int k = 0; k < A_LD; ++k) {
+    const int S = 512 * k + tid;
+    const int row = S >> 3;
+    const int cp = (S & 7) ^ (2 * (row & 3));
+    const int ar = rowidx[row0 + (row < nrows ? row : 0)];
+    asrc[k] = rows + (size_t)ar * M + 2 * cp;
+  }
+  // B: slot tid holds r = tid / 32, walker tid % 32 (clamped to a valid walker)
+  const int64_t bw = w0 + (tid % LO_WT) < nw ? w0 + (tid % LO_WT) : nw - 1;
+  const double2* bsrc = tho + (tid / LO_WT) * sr + bw * sw;
+  auto issue = [&](int c, double* sa, double2* sb) {
+#pragma unroll
+    for (int k = 0; k < A_LD; ++k)
+      __builtin_amdgcn_global_load_lds((const void*)(asrc[k] + 16 * c),
+                                       (__attribute__((address_space(3))) void*)(sa + (512 * k + 64 * wv) * 2), 16, 0,
+                                       0);
+    __builtin_amdgcn_global_load_lds((const void*)(bsrc + 16 * c * sr),
+                                     (__attribute__((address_space(3))) void*)(sb + 64 * wv), 16, 0, 0);
+  };
+
+  // acc[q][c]: rows rw + 4q + lk, walker column c (block h = c / 2, part = c % 2)
+  double acc[LO_QG][4];
+#pragma unroll
+  for (int q = 0; q < LO_QG; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[q][c] = 0.0;
+  // A operand of this lane: row rw + 4q + (lane & 3) (so row & 3 = lane & 3),
+  // column 4 s4 + lk, i.e. column pair 2 s4 + (lk >> 1), element lk & 1
+  const int e2 = 2 * (lane & 3);
+  const int abase = (rw + (lane & 3)) * 16 + (lk & 1);
+  const int nchunk = M / 16;
+  auto compute = [&](const double* sa, const double2* sb) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int rr = 4 * s4 + lk;
+      const double2 b0 = sb[rr * LO_WT + lr];
+      const double2 b1 = sb[rr * LO_WT + 16 + lr];
+      const int aoff = abase + 2 * (((2 * s4) ^ e2) | (lk >> 1));
+#pragma unroll
+      for (int q = 0; q < LO_QG; ++q) {
+        const double a = sa[aoff + 64 * q];
+        acc[q][0] = mfma4(a, b0.x, acc[q][0]);
+        acc[q][1] = mfma4(a, b0.y, acc[q][1]);
+        acc[q][2] = mfma4(a, b1.x, acc[q][2]);
+        acc[q][3] = mfma4(a, b1.y, acc[q][3]);
+      }
+    }
+  };
+  issue(0, sA0, sB0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int c = 0; c < nchunk; c += 2) {
+    if (c + 1 < nchunk) issue(c + 1, sA1, sB1);
+    if (active) compute(sA0, sB0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (c + 1 < nchunk) {
+      if (c + 2 < nchunk) issue(c + 2, sA0, sB0);
+      if (active) compute(sA1, sB1);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+  }
+  // lane holds rows rw + 4q + lk, walker 16h + lr
+  if (active) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t w = w0 + 16 * h + lr;
+      if (w < nw) {
+#pragma unroll
+        for (int q = 0; q < LO_QG; ++q) {
+          const int lrow = rw + 4 * q + lk;
+          if (lrow < nrows)
+            qbar[(size_t)(row0 + lrow) * orow + w * ow] = make_double2(acc[q][2 * h], acc[q][2 * h + 1]);
+        }
+      }
+    }
+  }
+}
+
+const char* lo_pass1_name(int M) { return M % 16 == 0 ? "lo_pass1_kernel" : "lo_pass1_reg_kernel"; }
 int lo_tile_rows() { return LO_TILE_ROWS; }
 int lo_orbital_block() { return LO_OBLK; }
 
@@ -176,7 +313,8 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
   const int64_t so = orbital_major ? (int64_t)M * nw : 1;
   const int64_t sr = orbital_major ? nw : n;
   const int64_t sw = orbital_major ? 1 : (int64_t)M * n;
-  hipLaunchKernelGGL(lo_pass1_kernel, dim3((unsigned)grid), dim3(512), 0, s, M, nw, rows, rowidx, tiles,
+  hipLaunchKernelGGL(M % 16 == 0 ? lo_pass1_kernel : lo_pass1_reg_kernel, dim3((unsigned)grid), dim3(512), 0, s, M,
+                     nw, rows, rowidx, tiles,
                      tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax, (const double2*)theta, so, sr, sw,
                      (double2*)qbar, out_walker_stride ? (int64_t)1 : nw,
                      out_walker_stride ? out_walker_stride : (int64_t)1, nwt);

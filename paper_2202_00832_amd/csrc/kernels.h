@@ -49,6 +49,9 @@ hipError_t launch_reduce_partials(hipStream_t s, int64_t nw, int nchunk, const d
 hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
                            const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
                            const double* theta, int orbital_major, double* qbar, int64_t out_walker_stride);
+// name of the pass-1 kernel launch_lo_pass1 runs for this M (direct-to-LDS
+// staging when M is a multiple of 16, register staging otherwise)
+const char* lo_pass1_name(int M);
 int lo_tile_rows();
 int lo_lp_tile_rows();
 int lo_orbital_block();

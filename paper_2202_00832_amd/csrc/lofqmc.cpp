@@ -1097,7 +1097,7 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   g.offA = md->d_off + 2 * md->npairs;
   g.qbar = qbar;
   ProfScope prof(ctx);
-  prof.mark("lo_pass1_kernel");
+  prof.mark(lofqmc::lo_pass1_name((int)md->M));
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)md->M, (int)md->n, nw, md->ntiles, md->rows,
                                            md->d_rowidx, md->d_tiles, md->d_tiles + 3 * md->ntiles, md->nblk,
                                            md->tmax, theta, om ? 1 : 0, qbar, md->n_out_rows));
@@ -1211,7 +1211,7 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
   double* partial = (double*)(base + qbytes);
   ProfScope prof(ctx);
   if (precision == LO_FP64) {
-    prof.mark("lo_pass1_kernel");
+    prof.mark(lofqmc::lo_pass1_name((int)M));
     HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
                                              f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
                                              orbital_major ? 1 : 0, qbar, 0));
