@@ -226,8 +226,13 @@ def test_lo_energy_chain_small(ctx, eps):
         assert_energy_close(got, full)
 
 
+# M a multiple of 16 runs pass 1 with direct-to-LDS staging (one slab, two
+# slabs, an even slab count with a ragged third walker tile, several tiles per
+# orbital), any other M the register-staged form
 @pytest.mark.parametrize("M,n,X,nw,eps", [(37, 5, 11, 3, 1e-3), (50, 17, 23, 70, 1e-2), (70, 33, 30, 5, 1e-4),
-                                          (29, 1, 6, 2, 0.0), (70, 64, 12, 3, 1e-3)])
+                                          (29, 1, 6, 2, 0.0), (70, 64, 12, 3, 1e-3),
+                                          (16, 3, 5, 40, 0.0), (32, 9, 8, 33, 1e-4), (96, 20, 15, 65, 1e-3),
+                                          (112, 70, 10, 5, 1e-4)])
 def test_lo_energy_ragged(ctx, M, n, X, nw, eps):
     print("lo M=%d n=%d X=%d nw=%d eps=%g" % (M, n, X, nw, eps), flush=True)
     chol, trial, walkers = random_system(M, n, X, nw, seed=3 * M + n)
