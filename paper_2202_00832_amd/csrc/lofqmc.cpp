@@ -1037,6 +1037,11 @@ int build_md_trial(lo_ctx* ctx, const lo_factors* f, int64_t n_occ, int64_t n_ac
       return fail(ctx, LO_EHIP, "copy of the factor rows failed");
     }
   }
+  // the uploads read host vectors that end with this call
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    lo_md_destroy(md);
+    return fail(ctx, LO_EHIP, "upload of the determinant tables failed");
+  }
   *out = md;
   return LO_OK;
 }
