@@ -28,7 +28,7 @@ struct GtCfg {
   static constexpr int NP = 16 * NB;
   static constexpr int KC = 16;                // rows of r per overlap slab
   static constexpr int SLOTS = KC * NP;        // complex slots of a phi slab
-  static constexpr int OW = NB <= 6 ? 4 : 8;    // waves of the overlap kernel
+  static constexpr int OW = NB <= 3 ? 4 : 8;    // waves of the overlap kernel
   static constexpr int OT = 64 * OW;            // its threads
   static constexpr int PER = (SLOTS + OT - 1) / OT;
   static constexpr int NKS = NP / 4;           // K-steps of theta = phi O^{-1}
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(GtCfg<NB>::OT) void overlap_kernel(int M, int n, in
 #pragma unroll
     for (int s4 = 0; s4 < C::KC / 4; ++s4) {
       const int row = (4 * s4 + lk) * NP;
-      if constexpr (NB == 4) {
+      if constexpr (NB == 4 && C::OW == 4) {
         // wave q owns the pairs (I, q): one B fragment per K-step
         const double2 b = sPh[buf][row + 16 * wv + lr];
 #pragma unroll
