@@ -10,7 +10,7 @@
 // products of Eq. 22 per pair and walker,
 //   J_ij = QL_i . QR_j,   X_ij = QL_j . QR_i   (complex, bilinear),
 // with weight 1 for i = j and 2 for i < j (Y^[ji] = (Y^[ij])^T), and sums
-// E_J = 2 sum J, E_K = -sum X in a fixed order per pair chunk.
+// E_J = 2 sum J, E_K = -sum X in a fixed order per chunk of rank rows.
 #include "common.h"
 #include "kernels.h"
 
@@ -320,39 +320,38 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
                      out_walker_stride ? out_walker_stride : (int64_t)1, nwt);
   return hipGetLastError();
 }
-// Pass 2: one thread per walker, a contiguous chunk of pairs per grid row.
-__global__ __launch_bounds__(64) void lo_pass2_kernel(int64_t nw, int npairs, int per_chunk,
-                                                      const int* __restrict__ pK, const int64_t* __restrict__ offI,
-                                                      const int64_t* __restrict__ offJ,
-                                                      const double* __restrict__ pw,
+// Pass 2: one thread per walker, a chunk of LO_P2_CHUNK entries per grid row.
+// An entry is one rank row K of a stored pair with the output rows of QL_i,
+// QR_j, QL_j, QR_i and the pair weight, so every chunk has the same fixed
+// trip count and a wave issues the loads of all its entries at once (a loop
+// over pairs of varying rank put one memory round trip per pair on the path).
+// The entry tables are read at wave-uniform indices (scalar loads).
+constexpr int LO_P2_CHUNK = 8;
+
+__global__ __launch_bounds__(64) void lo_pass2_kernel(int64_t nw, const int* __restrict__ ent, int64_t nent,
+                                                      const double* __restrict__ entw,
                                                       const double2* __restrict__ qbar,
                                                       double* __restrict__ partial) {
   const int64_t w = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int chunk = blockIdx.y;
   if (w >= nw) return;
-  const int p0 = chunk * per_chunk;
-  const int p1 = (p0 + per_chunk < npairs) ? p0 + per_chunk : npairs;
+  const int64_t e0 = (int64_t)chunk * LO_P2_CHUNK;
+  double2 ql_i[LO_P2_CHUNK], qr_j[LO_P2_CHUNK], ql_j[LO_P2_CHUNK], qr_i[LO_P2_CHUNK];
+#pragma unroll
+  for (int e = 0; e < LO_P2_CHUNK; ++e) {
+    ql_i[e] = qbar[(size_t)ent[e0 + e] * nw + w];
+    qr_j[e] = qbar[(size_t)ent[nent + e0 + e] * nw + w];
+    ql_j[e] = qbar[(size_t)ent[2 * nent + e0 + e] * nw + w];
+    qr_i[e] = qbar[(size_t)ent[3 * nent + e0 + e] * nw + w];
+  }
   double jr = 0.0, ji = 0.0, xr = 0.0, xi = 0.0;
-  for (int p = p0; p < p1; ++p) {
-    const int K = pK[p];
-    const double wt = pw[p];
-    const double2* gi = qbar + (size_t)offI[p] * nw + w;   // [QL_i ; QR_i]
-    const double2* gj = qbar + (size_t)offJ[p] * nw + w;   // [QL_j ; QR_j]
-    double sjr = 0.0, sji = 0.0, sxr = 0.0, sxi = 0.0;
-    for (int k = 0; k < K; ++k) {
-      const double2 qli = gi[(size_t)k * nw];
-      const double2 qri = gi[(size_t)(K + k) * nw];
-      const double2 qlj = gj[(size_t)k * nw];
-      const double2 qrj = gj[(size_t)(K + k) * nw];
-      sjr += qli.x * qrj.x - qli.y * qrj.y;
-      sji += qli.x * qrj.y + qli.y * qrj.x;
-      sxr += qlj.x * qri.x - qlj.y * qri.y;
-      sxi += qlj.x * qri.y + qlj.y * qri.x;
-    }
-    jr += wt * sjr;
-    ji += wt * sji;
-    xr += wt * sxr;
-    xi += wt * sxi;
+#pragma unroll
+  for (int e = 0; e < LO_P2_CHUNK; ++e) {
+    const double wt = entw[e0 + e];
+    jr += wt * (ql_i[e].x * qr_j[e].x - ql_i[e].y * qr_j[e].y);
+    ji += wt * (ql_i[e].x * qr_j[e].y + ql_i[e].y * qr_j[e].x);
+    xr += wt * (ql_j[e].x * qr_i[e].x - ql_j[e].y * qr_i[e].y);
+    xi += wt * (ql_j[e].x * qr_i[e].y + ql_j[e].y * qr_i[e].x);
   }
   double* out = partial + ((size_t)chunk * nw + w) * 4;
   out[0] = 2.0 * jr;
@@ -361,20 +360,13 @@ __global__ __launch_bounds__(64) void lo_pass2_kernel(int64_t nw, int npairs, in
   out[3] = -xi;
 }
 
-int lo_pass2_chunks(int npairs) {
-  int c = (npairs + 3) / 4;
-  if (c > 512) c = 512;
-  if (c < 1) c = 1;
-  return c;
-}
+int lo_pass2_chunk() { return LO_P2_CHUNK; }
 
-hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int npairs, int nchunk, const int* pK, const int64_t* offI,
-                           const int64_t* offJ, const double* pw, const double* qbar, double* partial) {
-  if (nw <= 0) return hipSuccess;
-  const int per = (npairs + nchunk - 1) / nchunk;
-  dim3 grid((unsigned)((nw + 63) / 64), nchunk);
-  hipLaunchKernelGGL(lo_pass2_kernel, grid, dim3(64), 0, s, nw, npairs, per > 0 ? per : 1, pK, offI, offJ, pw,
-                     (const double2*)qbar, partial);
+hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int64_t nent, const int* ent, const double* entw,
+                           const double* qbar, double* partial) {
+  if (nw <= 0 || nent <= 0) return hipSuccess;
+  dim3 grid((unsigned)((nw + 63) / 64), (unsigned)(nent / LO_P2_CHUNK));
+  hipLaunchKernelGGL(lo_pass2_kernel, grid, dim3(64), 0, s, nw, ent, nent, entw, (const double2*)qbar, partial);
   return hipGetLastError();
 }
 

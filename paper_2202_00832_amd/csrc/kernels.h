@@ -55,9 +55,12 @@ const char* lo_pass1_name(int M);
 int lo_tile_rows();
 int lo_lp_tile_rows();
 int lo_orbital_block();
-int lo_pass2_chunks(int npairs);
-hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int npairs, int nchunk, const int* pK, const int64_t* offI,
-                           const int64_t* offJ, const double* pw, const double* qbar, double* partial);
+// pass 2 over entries (one per rank row of a stored pair): ent [4][nent]
+// output rows of QL_i, QR_j, QL_j, QR_i, entw [nent] the pair weights; nent a
+// multiple of lo_pass2_chunk(), partial [nent / lo_pass2_chunk()][nw][4]
+int lo_pass2_chunk();
+hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int64_t nent, const int* ent, const double* entw,
+                           const double* qbar, double* partial);
 
 // ---- reduced precision helpers (M padded to a multiple of 32, n to 16 NB)
 int lp_padded_m(int M);

@@ -47,9 +47,9 @@ struct lo_factors {
   int* d_tiles = nullptr;              // [3][ntiles]: orbital, first output row, row count;
                                        // then [nblk + 1]: first tile of each orbital block
   int* d_tiles_lp = nullptr;           // the same for the reduced-precision pass (smaller tiles)
-  int* d_pK = nullptr;                 // [npairs]
-  int64_t* d_off = nullptr;            // [2][npairs]: output rows of the pair for orbital i and j
-  double* d_pw = nullptr;              // [npairs]
+  int64_t n_ent = 0;                   // pass-2 entries, a multiple of lo_pass2_chunk()
+  int* d_ent = nullptr;                // [4][n_ent]: output rows of QL_i, QR_j, QL_j, QR_i of one rank row
+  double* d_entw = nullptr;            // [n_ent]: pair weight (1 for i = j, 2 for i < j; 0 for padding)
   float* d_orbfeat = nullptr;          // [n][2]: sum_j K_ij, sum_j discarded mass (residual features)
 };
 
@@ -146,9 +146,8 @@ void free_factors(lo_factors* f) {
   (void)hipFree(f->d_rowidx);
   (void)hipFree(f->d_tiles);
   (void)hipFree(f->d_tiles_lp);
-  (void)hipFree(f->d_pK);
-  (void)hipFree(f->d_off);
-  (void)hipFree(f->d_pw);
+  (void)hipFree(f->d_ent);
+  (void)hipFree(f->d_entw);
   (void)hipFree(f->d_orbfeat);
   delete f;
 }
@@ -632,22 +631,41 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
   };
   const std::vector<int> tiles = build_tiles(lofqmc::lo_tile_rows(), &f->ntiles, &f->nblk, &f->tmax);
   const std::vector<int> tiles_lp = build_tiles(lofqmc::lo_lp_tile_rows(), &f->ntiles_lp, &f->nblk_lp, &f->tmax_lp);
-  std::vector<int> pK;
-  std::vector<int64_t> off;
-  std::vector<double> pw;
-  std::vector<int64_t> offJ;
+  // pass-2 entries: one per rank row K of every stored pair i <= j, the
+  // output rows of QL_i, QR_j (Coulomb) and QL_j, QR_i (exchange), padded
+  // with weight-0 entries to whole chunks
+  std::vector<int> e_li, e_rj, e_lj, e_ri;
+  std::vector<double> e_w;
+  int nstored = 0;
   for (int i = 0; i < n; ++i) {
     for (int j = i; j < n; ++j) {
       const int K = f->ranks[i * n + j];
       if (K == 0) continue;
-      pK.push_back(K);
-      off.push_back(obase[i] + loc[i * n + j]);
-      offJ.push_back(obase[j] + loc[j * n + i]);
-      pw.push_back(i == j ? 1.0 : 2.0);
+      ++nstored;
+      const int64_t oi = obase[i] + loc[i * n + j], oj = obase[j] + loc[j * n + i];
+      for (int k = 0; k < K; ++k) {
+        e_li.push_back((int)(oi + k));
+        e_rj.push_back((int)(oj + K + k));
+        e_lj.push_back((int)(oj + k));
+        e_ri.push_back((int)(oi + K + k));
+        e_w.push_back(i == j ? 1.0 : 2.0);
+      }
     }
   }
-  f->npairs = (int)pK.size();
-  off.insert(off.end(), offJ.begin(), offJ.end());
+  f->npairs = nstored;
+  const int ech = lofqmc::lo_pass2_chunk();
+  while (e_w.size() % ech) {
+    e_li.push_back(0);
+    e_rj.push_back(0);
+    e_lj.push_back(0);
+    e_ri.push_back(0);
+    e_w.push_back(0.0);
+  }
+  f->n_ent = (int64_t)e_w.size();
+  std::vector<int> ent(e_li);
+  ent.insert(ent.end(), e_rj.begin(), e_rj.end());
+  ent.insert(ent.end(), e_lj.begin(), e_lj.end());
+  ent.insert(ent.end(), e_ri.begin(), e_ri.end());
   std::vector<float> orbfeat(2 * n, 0.0f);
   for (int i = 0; i < n; ++i) {
     double ks = 0.0, ms = 0.0;
@@ -660,7 +678,7 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
   }
   if ((rc = upload(ctx, &f->d_rowidx, rowidx)) || (rc = upload(ctx, &f->d_tiles, tiles)) ||
       (rc = upload(ctx, &f->d_tiles_lp, tiles_lp)) ||
-      (rc = upload(ctx, &f->d_pK, pK)) || (rc = upload(ctx, &f->d_off, off)) || (rc = upload(ctx, &f->d_pw, pw)) ||
+      (rc = upload(ctx, &f->d_ent, ent)) || (rc = upload(ctx, &f->d_entw, e_w)) ||
       (rc = upload(ctx, &f->d_orbfeat, orbfeat))) {
     cleanup();
     free_factors(f);
@@ -1205,7 +1223,7 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
   if (nw == 0) return LO_OK;
   if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
   const int64_t M = f->M, n = f->n;
-  const int nchunk = lofqmc::lo_pass2_chunks(f->npairs);
+  const int nchunk = (int)(f->n_ent / lofqmc::lo_pass2_chunk());
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
   const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
   const size_t tbytes = precision == LO_FP64 ? 0 : align256(lofqmc::lp_theta_bytes(precision, (int)M, (int)n, nw));
@@ -1231,8 +1249,7 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
                                                 f->nblk_lp, f->tmax_lp, tlp, qbar));
   }
   prof.mark("lo_pass2_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->npairs, nchunk, f->d_pK, f->d_off,
-                                           f->d_off + f->npairs, f->d_pw, qbar, partial));
+  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->n_ent, f->d_ent, f->d_entw, qbar, partial));
   prof.mark("reduce_partials_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nchunk, partial, info, energy));
   return LO_OK;
