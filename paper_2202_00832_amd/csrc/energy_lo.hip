@@ -320,29 +320,34 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
                      out_walker_stride ? out_walker_stride : (int64_t)1, nwt);
   return hipGetLastError();
 }
-// Pass 2: one thread per walker, a chunk of LO_P2_CHUNK entries per grid row.
-// An entry is one rank row K of a stored pair with the output rows of QL_i,
-// QR_j, QL_j, QR_i and the pair weight, so every chunk has the same fixed
-// trip count and a wave issues the loads of all its entries at once (a loop
-// over pairs of varying rank put one memory round trip per pair on the path).
-// The entry tables are read at wave-uniform indices (scalar loads).
+// Pass 2: one thread per walker; the four waves of a workgroup take four
+// consecutive chunks of LO_P2_CHUNK entries for the same 64 walkers and their
+// sums are added in LDS in wave order, so each grid row writes one partial
+// slot per walker for 4 LO_P2_CHUNK entries.  An entry is one rank row K of a
+// stored pair with the output rows of QL_i, QR_j, QL_j, QR_i and the pair
+// weight, so every chunk has the same fixed trip count and a wave issues the
+// loads of all its entries at once (a loop over pairs of varying rank put one
+// memory round trip per pair on the path).  The entry tables are read at
+// wave-uniform indices (scalar loads).
 constexpr int LO_P2_CHUNK = 8;
+constexpr int LO_P2_WAVES = 4;
 
-__global__ __launch_bounds__(64) void lo_pass2_kernel(int64_t nw, const int* __restrict__ ent, int64_t nent,
-                                                      const double* __restrict__ entw,
-                                                      const double2* __restrict__ qbar,
-                                                      double* __restrict__ partial) {
-  const int64_t w = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const int chunk = blockIdx.y;
-  if (w >= nw) return;
-  const int64_t e0 = (int64_t)chunk * LO_P2_CHUNK;
+__global__ __launch_bounds__(256) void lo_pass2_kernel(int64_t nw, const int* __restrict__ ent, int64_t nent,
+                                                       const double* __restrict__ entw,
+                                                       const double2* __restrict__ qbar,
+                                                       double* __restrict__ partial) {
+  __shared__ double4 sRed[LO_P2_WAVES][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t w = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t wl = w < nw ? w : nw - 1;     // every wave reaches the barrier
+  const int64_t e0 = ((int64_t)blockIdx.y * LO_P2_WAVES + q) * LO_P2_CHUNK;
   double2 ql_i[LO_P2_CHUNK], qr_j[LO_P2_CHUNK], ql_j[LO_P2_CHUNK], qr_i[LO_P2_CHUNK];
 #pragma unroll
   for (int e = 0; e < LO_P2_CHUNK; ++e) {
-    ql_i[e] = qbar[(size_t)ent[e0 + e] * nw + w];
-    qr_j[e] = qbar[(size_t)ent[nent + e0 + e] * nw + w];
-    ql_j[e] = qbar[(size_t)ent[2 * nent + e0 + e] * nw + w];
-    qr_i[e] = qbar[(size_t)ent[3 * nent + e0 + e] * nw + w];
+    ql_i[e] = qbar[(size_t)ent[e0 + e] * nw + wl];
+    qr_j[e] = qbar[(size_t)ent[nent + e0 + e] * nw + wl];
+    ql_j[e] = qbar[(size_t)ent[2 * nent + e0 + e] * nw + wl];
+    qr_i[e] = qbar[(size_t)ent[3 * nent + e0 + e] * nw + wl];
   }
   double jr = 0.0, ji = 0.0, xr = 0.0, xi = 0.0;
 #pragma unroll
@@ -353,20 +358,30 @@ __global__ __launch_bounds__(64) void lo_pass2_kernel(int64_t nw, const int* __r
     xr += wt * (ql_j[e].x * qr_i[e].x - ql_j[e].y * qr_i[e].y);
     xi += wt * (ql_j[e].x * qr_i[e].y + ql_j[e].y * qr_i[e].x);
   }
-  double* out = partial + ((size_t)chunk * nw + w) * 4;
-  out[0] = 2.0 * jr;
-  out[1] = 2.0 * ji;
-  out[2] = -xr;
-  out[3] = -xi;
+  sRed[q][lane] = make_double4(2.0 * jr, 2.0 * ji, -xr, -xi);
+  __syncthreads();
+  if (q == 0 && w < nw) {
+    double4 t = sRed[0][lane];
+#pragma unroll
+    for (int k = 1; k < LO_P2_WAVES; ++k) {
+      const double4 u = sRed[k][lane];
+      t.x += u.x;
+      t.y += u.y;
+      t.z += u.z;
+      t.w += u.w;
+    }
+    reinterpret_cast<double4*>(partial)[(size_t)blockIdx.y * nw + w] = t;
+  }
 }
 
-int lo_pass2_chunk() { return LO_P2_CHUNK; }
+int lo_pass2_chunk() { return LO_P2_CHUNK * LO_P2_WAVES; }
 
 hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int64_t nent, const int* ent, const double* entw,
                            const double* qbar, double* partial) {
   if (nw <= 0 || nent <= 0) return hipSuccess;
-  dim3 grid((unsigned)((nw + 63) / 64), (unsigned)(nent / LO_P2_CHUNK));
-  hipLaunchKernelGGL(lo_pass2_kernel, grid, dim3(64), 0, s, nw, ent, nent, entw, (const double2*)qbar, partial);
+  dim3 grid((unsigned)((nw + 63) / 64), (unsigned)(nent / (LO_P2_CHUNK * LO_P2_WAVES)));
+  hipLaunchKernelGGL(lo_pass2_kernel, grid, dim3(64 * LO_P2_WAVES), 0, s, nw, ent, nent, entw,
+                     (const double2*)qbar, partial);
   return hipGetLastError();
 }
 

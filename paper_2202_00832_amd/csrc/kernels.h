@@ -57,7 +57,8 @@ int lo_lp_tile_rows();
 int lo_orbital_block();
 // pass 2 over entries (one per rank row of a stored pair): ent [4][nent]
 // output rows of QL_i, QR_j, QL_j, QR_i, entw [nent] the pair weights; nent a
-// multiple of lo_pass2_chunk(), partial [nent / lo_pass2_chunk()][nw][4]
+// multiple of lo_pass2_chunk() (entries per partial slot),
+// partial [nent / lo_pass2_chunk()][nw][4]
 int lo_pass2_chunk();
 hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int64_t nent, const int* ent, const double* entw,
                            const double* qbar, double* partial);
