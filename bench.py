@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walker local energies/sec, LO vs full FP64 on 1 MI355X at <=1 mHa error"
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix (no sparsity)
 PEAK_HBM_GBS = 8000.0
 GATE_HA = 1e-3
 
@@ -245,6 +247,25 @@ def precision_study(torch, lofqmc, synth, steps):
              "p99_abs_dE_Ha": float(np.percentile(d, 99)), "max_rel_dE": float(rel.max()),
              "max_abs_dEK_Ha": float(dk.max()),
              "kernel_us": {k: round(t / c * 1e3, 1) for k, (c, t) in kern.items()}}
+        # rooflines of the contraction kernels against the peak of the dtype
+        # they run in (algorithmic flops on unpadded sizes): the exchange
+        # contraction T = Lbar^T theta (real x complex, 4 M n^2 per walker and
+        # vector; split BF16 runs it as three BF16 products) and the FP64
+        # Coulomb traces (4 M n per walker and vector)
+        contraction = 4.0 * M * n * n * X * nw
+        spec = {"energy_full_kernel": (contraction + 8.0 * n * n * X * nw, PEAK_FP64_TFLOPS, "fp64"),
+                "exchange_lp_kernel": ((3.0 if p == lofqmc.LO_BF16X3 else 1.0) * contraction,
+                                       PEAK_BF16_TFLOPS if p == lofqmc.LO_BF16X3 else PEAK_FP32_TFLOPS,
+                                       "bf16" if p == lofqmc.LO_BF16X3 else "fp32"),
+                "coulomb_trace_kernel": (4.0 * M * n * X * nw, PEAK_FP64_TFLOPS, "fp64")}
+        r["kernels"] = {}
+        for k, (flops, peak, dt) in spec.items():
+            if k in kern:
+                ach = flops / (kern[k][1] / kern[k][0] * 1e-3) / 1e12
+                r["kernels"][k] = {"bound": "mfma", "dtype": dt, "achieved": round(ach, 3), "peak": peak,
+                                   "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                                   "us_per_launch": round(kern[k][1] / kern[k][0] * 1e3, 2),
+                                   "algorithmic_flops_per_launch": flops}
         out["runs"][names[p]] = r
         log("precision %s: %.3f ms/call, max |dE| %.2e Ha" % (names[p], r["ms_per_call"], r["max_abs_dE_Ha"]))
     ctx.close()
@@ -296,6 +317,11 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
     torch.cuda.synchronize()
     seq_ms = e0.elapsed_time(e1) / evaluations
     maxdiff = max(float((a - o).abs().max()) for a, o in zip(b.energies, outs))
+    # FP32 exchange contraction of all systems per evaluation (4 M n^2 per
+    # walker and Cholesky vector), over the whole evaluation's time (which also
+    # holds the FP64 Coulomb sums and reductions)
+    xflops = sum(4.0 * sd["lbar"].shape[1] * sd["lbar"].shape[2] ** 2 * sd["lbar"].shape[0] * sd["theta"].shape[0]
+                 for sd in systems)
     info = b.info()
     b.close()
     ctx.close()
@@ -306,7 +332,12 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
            "graph_ms_per_evaluation": round(graph_ms, 3),
            "walker_energies_per_s": round(total_w / (graph_ms * 1e-3), 1),
            "separate_calls_ms_per_evaluation": round(seq_ms, 3),
-           "max_abs_diff_vs_separate_calls_Ha": maxdiff}
+           "max_abs_diff_vs_separate_calls_Ha": maxdiff,
+           "roofline_whole_evaluation": {"bound": "mfma", "dtype": "fp32",
+                                         "achieved": round(xflops / (graph_ms * 1e-3) / 1e12, 3),
+                                         "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": round(xflops / (graph_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+                                         "algorithmic_flops_per_evaluation": xflops}}
     log("batching: graph %.3f ms/eval (%.0f walker-energies/s), separate calls %.3f ms/eval"
         % (graph_ms, out["walker_energies_per_s"], seq_ms))
     return out
