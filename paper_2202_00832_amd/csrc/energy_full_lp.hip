@@ -297,35 +297,16 @@ __device__ __forceinline__ void exchange_item(int Mp, int64_t X, int64_t nw, int
   };
 
   float2 tfa[NB], tfb[NB];
+  // split BF16: theta of the next tile's slab, loaded once the products of the
+  // current tile are issued (a second register set two slabs ahead was slower)
   bf8 tba[NB][4];
   if (ntiles > 0) {
     if constexpr (MODE == LO_FP32) load_theta32(lk, tfa);
     else load_thetabf(0, tba);
   }
 
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const int buf = (int)(t & 1);
-    if (t + 1 < ntiles) load_tile(t + 1);
-    const int kt = (int)(t % nslab);
-    const int ktn = (kt + 1 == nslab) ? 0 : kt + 1;   // next tile's slab (same or next g)
-    if constexpr (MODE == LO_FP32) {
-      const float* Lt = (const float*)(sTileBase + buf * TILE_BYTES);
-      const int rb = LP_SLAB * kt + lk;
-#pragma unroll
-      for (int s = 0; s < LP_SLAB / 4; s += 2) {
-        load_theta32(rb + 4 * (s + 1), tfb);
-        mma32(Lt, s, tfa);
-        const int rn = (s + 2 < LP_SLAB / 4) ? rb + 4 * (s + 2) : LP_SLAB * ktn + lk;
-        load_theta32(rn, tfa);
-        mma32(Lt, s + 1, tfb);
-      }
-    } else {
-      const bf8* Lt = (const bf8*)(sTileBase + buf * TILE_BYTES);
-      mmabf(Lt, tba);
-      load_thetabf(ktn, tba);
-    }
-    if (t + 1 < ntiles) store_tile(buf ^ 1);
-
+  // the end of tile t: the exchange sum of a finished g, then the barrier
+  auto finish_tile = [&](int kt) {
     if (kt == nslab - 1) {
       // exchange sum of this g in FP64: lane-local pairs, diagonal blocks via LDS
       double xr = 0.0, xi = 0.0;
@@ -365,6 +346,37 @@ __device__ __forceinline__ void exchange_item(int Mp, int64_t X, int64_t nw, int
       zero_acc();
     }
     __syncthreads();
+  };
+
+  if constexpr (MODE == LO_FP32) {
+    for (int64_t t = 0; t < ntiles; ++t) {
+      const int buf = (int)(t & 1);
+      if (t + 1 < ntiles) load_tile(t + 1);
+      const int kt = (int)(t % nslab);
+      const int ktn = (kt + 1 == nslab) ? 0 : kt + 1;   // next tile's slab (same or next g)
+      const float* Lt = (const float*)(sTileBase + buf * TILE_BYTES);
+      const int rb = LP_SLAB * kt + lk;
+#pragma unroll
+      for (int s = 0; s < LP_SLAB / 4; s += 2) {
+        load_theta32(rb + 4 * (s + 1), tfb);
+        mma32(Lt, s, tfa);
+        const int rn = (s + 2 < LP_SLAB / 4) ? rb + 4 * (s + 2) : LP_SLAB * ktn + lk;
+        load_theta32(rn, tfa);
+        mma32(Lt, s + 1, tfb);
+      }
+      if (t + 1 < ntiles) store_tile(buf ^ 1);
+      finish_tile(kt);
+    }
+  } else {
+    for (int64_t t = 0; t < ntiles; ++t) {
+      const int buf = (int)(t & 1);
+      if (t + 1 < ntiles) load_tile(t + 1);
+      const int kt = (int)(t % nslab);
+      mmabf((const bf8*)(sTileBase + buf * TILE_BYTES), tba);
+      load_thetabf((kt + 1 == nslab) ? 0 : kt + 1, tba);
+      if (t + 1 < ntiles) store_tile(buf ^ 1);
+      finish_tile(kt);
+    }
   }
 
   accKr = wave_sum_lane0(accKr);
