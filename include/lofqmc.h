@@ -285,8 +285,9 @@ int local_energy_hr(lo_ctx* ctx, const lo_hr* h, int64_t nw, const double* theta
  * with n_det.  A determinant whose R_d is exactly singular has weight zero.
  *
  * build_md_trial:
- *   f          : LO factors of all n_cas orbitals (f->n_occ = n_cas); must
- *                outlive the handle (its rows are read at every evaluation)
+ *   f          : LO factors of all n_cas orbitals (f->n_occ = n_cas); the
+ *                handle keeps its own copy of the factor rows and tables, so
+ *                f may be destroyed once this call returns
  *   n_occ      : occupied orbitals per determinant, 1 <= n_occ <= min(n_cas, 112)
  *   n_act_occ  : 1..min(6, n_occ); n_cas - n_occ <= 6; n_cas <= 128
  *   orbitals   : [M][n_cas] double (device), the orbitals C; only the active
@@ -322,6 +323,7 @@ int lo_md_info(const lo_md* md, int64_t* n_occ, int64_t* n_cas, int64_t* n_det, 
  *                w_d = c_d det(R_d)^2 / sum_d' c_d' det(R_d')^2
  *   ovlp_ratio : complex [nw] or NULL: sum_d c_d det(R_d)^2, i.e.
  *                <psi_T|phi> / det(Phi_0^T phi)^2 (zero gives NaN energies)
+ * nw <= 2^24 (one workgroup per walker), else LO_EUNSUPPORTED.
  * The context workspace grows to out_rows x nw complex values plus
  * nw x (NA n_occ + NA^2 + NA^4) complex values, NA = max(n_act_occ, n_cas - n_occ),
  * plus the partial sums. */

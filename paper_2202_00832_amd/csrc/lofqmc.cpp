@@ -56,7 +56,6 @@ struct lo_factors {
 struct lo_md {
   int64_t M = 0, n = 0, ncas = 0, nao = 0, nav = 0, ndet = 0, maxe = 0;
   int na = 0;
-  const lo_factors* f = nullptr;  // not owned
   double* rows = nullptr;         // device [total_rows + nav][M]: the factor rows, then C_av^T
   int* d_exc = nullptr;           // [ndet]
   int* d_holes = nullptr;         // [ndet][na], relative to the first active occupied column
@@ -1006,7 +1005,6 @@ int build_md_trial(lo_ctx* ctx, const lo_factors* f, int64_t n_occ, int64_t n_ac
   md->ndet = n_det;
   md->maxe = max_exc;
   md->na = na;
-  md->f = f;
   md->n_out_rows = n_out;
   md->act_base = act_base;
   md->total_rows = total;
@@ -1081,6 +1079,8 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   ctx->err.clear();
   if (!md) return fail(ctx, LO_EINVAL, "null trial");
   if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
+  // one 256-thread workgroup per walker: the grid's work-item count must fit 32 bits
+  if (nw > ((int64_t)1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^24");
   if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   if (nw == 0) return LO_OK;
   if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");

@@ -155,11 +155,11 @@ class HrEri:
 
 class MdTrial:
     """Owner of a lo_md handle: a multi-determinant trial over the orbitals of an
-    LO factor handle (which must stay open while this one is used)."""
+    LO factor handle (the handle copies what it needs of the factors, which may
+    be closed afterwards)."""
 
     def __init__(self, handle: int, factors):
         self._h = ctypes.c_void_p(handle)
-        self._factors = factors
         vals = [ctypes.c_int64() for _ in range(5)]
         load().lo_md_info(self._h, *[ctypes.byref(v) for v in vals])
         self.n_occ, self.n_cas, self.n_det, self.npairs, self.out_rows = [v.value for v in vals]

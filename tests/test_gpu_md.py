@@ -9,7 +9,8 @@ Cholesky route; both are pinned on the CPU.  Cases: the small CAS chain (all
 spaces from 1 x 0 to 6 x 6 on random Cholesky sets with ragged walker counts
 (NA = 1..6 kernels); a lone reference determinant against the
 single-determinant LO call; both theta layouts; a walker with a zero overlap
-pivot; repeated calls bit for bit.
+pivot; repeated calls bit for bit; the handle used after its factors are
+released; a walker count above the launch limit.
 """
 import numpy as np
 import pytest
@@ -173,3 +174,24 @@ def test_bad_arguments_are_rejected(ctx):
         ctx.build_md_trial(f, cfg.n, 7, C, [()], [()], [1.0])      # more than 6 active occupied
     assert e.value.code == lofqmc.LO_EUNSUPPORTED
     f.close()
+
+
+def test_handle_outlives_its_factors_and_rejects_large_nw(ctx):
+    s = synth.make_cas_system(synth.CAS_SMALL, nw=8)
+    cfg = s.config
+    lbar = ctx.build_half_rotated_chol(dev(s.chol), dev(s.orbitals))
+    f = ctx.build_lo_factors(lbar, 1e-5)
+    md = ctx.build_md_trial(f, cfg.n, cfg.n_act_occ, dev(s.orbitals), s.holes, s.particles, s.coeffs)
+    theta, _, info = ctx.green_theta(dev(s.reference), dev(s.walkers))
+    before = host(ctx.local_energy_md(md, theta, info))
+    f.close()
+    del lbar
+    torch.cuda.empty_cache()
+    after = host(ctx.local_energy_md(md, theta, info))
+    assert np.array_equal(before.view(np.float64), after.view(np.float64))
+    # one workgroup per walker: a count past 2^24 is refused before any launch
+    energy = torch.empty((8, 2), dtype=torch.complex128, device="cuda")
+    rc = lofqmc.load().local_energy_md(ctx._h, md.handle, (1 << 24) + 1, theta.data_ptr(), None, 0,
+                                       energy.data_ptr(), None)
+    assert rc == lofqmc.LO_EUNSUPPORTED
+    md.close()
