@@ -427,13 +427,29 @@ __global__ __launch_bounds__(512, (MODE == LO_FP32 && NB <= 4) ? 2 : 1) void exc
 // workgroups until the list is exhausted; every item writes its own partial
 // slot, so the result does not depend on which workgroup took it.
 // ---------------------------------------------------------------------------
-constexpr int BATCH_TILE_BYTES = 2 * LpLds<LO_FP32, 6>::TILE_BYTES;
-constexpr int BATCH_NDH = LpCfg<6>::NDH;
+// Item of a system with NB orbital blocks, dispatched at compile time over
+// NB = 1 .. NBMAX (the plan's largest), so the kernel holds the registers of
+// the largest variant the plan uses and no more.
+template <int NB, int NBMAX>
+__device__ __forceinline__ void batched_item(const LpSys& d, int64_t chunk, int64_t grp, unsigned char* sTile,
+                                             float2* sDiag, double2* sK) {
+  static_assert(LpLds<LO_FP32, NB>::TILE_BYTES <= LpLds<LO_FP32, NBMAX>::TILE_BYTES &&
+                LpCfg<NB>::NDH <= LpCfg<NBMAX>::NDH, "LDS sized for NBMAX");
+  if constexpr (NB == NBMAX) {
+    exchange_item<LO_FP32, NB>(d.Mp, d.X, d.nw, d.gchunk, chunk, grp, d.lb, d.tb, d.partial, sTile, sDiag, sK);
+  } else {
+    if (d.nb == NB)
+      exchange_item<LO_FP32, NB>(d.Mp, d.X, d.nw, d.gchunk, chunk, grp, d.lb, d.tb, d.partial, sTile, sDiag, sK);
+    else
+      batched_item<NB + 1, NBMAX>(d, chunk, grp, sTile, sDiag, sK);
+  }
+}
 
+template <int NBMAX>
 __global__ __launch_bounds__(512, 1) void exchange_batched_kernel(int nsys, const LpSys* __restrict__ sys,
                                                                   int64_t nitems, unsigned* __restrict__ counter) {
-  __shared__ __attribute__((aligned(16))) unsigned char sTile[BATCH_TILE_BYTES];
-  __shared__ float2 sDiag[8 * BATCH_NDH * 256];
+  __shared__ __attribute__((aligned(16))) unsigned char sTile[2 * LpLds<LO_FP32, NBMAX>::TILE_BYTES];
+  __shared__ float2 sDiag[8 * LpCfg<NBMAX>::NDH * 256];
   __shared__ double2 sK[8];
   __shared__ int64_t sItem;
   for (;;) {
@@ -446,15 +462,7 @@ __global__ __launch_bounds__(512, 1) void exchange_batched_kernel(int nsys, cons
     while (s + 1 < nsys && sys[s + 1].item0 <= it) ++s;
     const LpSys d = sys[s];
     const int64_t local = it - d.item0;
-    const int64_t chunk = local % d.nchunk, grp = local / d.nchunk;
-    switch (d.nb) {
-      case 1: exchange_item<LO_FP32, 1>(d.Mp, d.X, d.nw, d.gchunk, chunk, grp, d.lb, d.tb, d.partial, sTile, sDiag, sK); break;
-      case 2: exchange_item<LO_FP32, 2>(d.Mp, d.X, d.nw, d.gchunk, chunk, grp, d.lb, d.tb, d.partial, sTile, sDiag, sK); break;
-      case 3: exchange_item<LO_FP32, 3>(d.Mp, d.X, d.nw, d.gchunk, chunk, grp, d.lb, d.tb, d.partial, sTile, sDiag, sK); break;
-      case 4: exchange_item<LO_FP32, 4>(d.Mp, d.X, d.nw, d.gchunk, chunk, grp, d.lb, d.tb, d.partial, sTile, sDiag, sK); break;
-      case 5: exchange_item<LO_FP32, 5>(d.Mp, d.X, d.nw, d.gchunk, chunk, grp, d.lb, d.tb, d.partial, sTile, sDiag, sK); break;
-      default: exchange_item<LO_FP32, 6>(d.Mp, d.X, d.nw, d.gchunk, chunk, grp, d.lb, d.tb, d.partial, sTile, sDiag, sK); break;
-    }
+    batched_item<1, NBMAX>(d, local % d.nchunk, local / d.nchunk, sTile, sDiag, sK);
     __syncthreads();
   }
 }
@@ -712,11 +720,20 @@ hipError_t launch_energy_full_lp(hipStream_t s, int precision, int M, int n, int
 }
 
 hipError_t launch_exchange_batched(hipStream_t s, int nsys, const LpSys* d_sys, int64_t nitems, unsigned* counter,
-                                   int grid) {
+                                   int grid, int nbmax) {
+  if (nbmax < 1 || nbmax > 6) return hipErrorInvalidValue;
   hipLaunchKernelGGL(batch_counter_reset_kernel, dim3(1), dim3(1), 0, s, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || nitems <= 0) return e;
-  hipLaunchKernelGGL(exchange_batched_kernel, dim3((unsigned)grid), dim3(512), 0, s, nsys, d_sys, nitems, counter);
+  const dim3 g((unsigned)grid), b(512);
+  switch (nbmax) {
+    case 1: hipLaunchKernelGGL(exchange_batched_kernel<1>, g, b, 0, s, nsys, d_sys, nitems, counter); break;
+    case 2: hipLaunchKernelGGL(exchange_batched_kernel<2>, g, b, 0, s, nsys, d_sys, nitems, counter); break;
+    case 3: hipLaunchKernelGGL(exchange_batched_kernel<3>, g, b, 0, s, nsys, d_sys, nitems, counter); break;
+    case 4: hipLaunchKernelGGL(exchange_batched_kernel<4>, g, b, 0, s, nsys, d_sys, nitems, counter); break;
+    case 5: hipLaunchKernelGGL(exchange_batched_kernel<5>, g, b, 0, s, nsys, d_sys, nitems, counter); break;
+    default: hipLaunchKernelGGL(exchange_batched_kernel<6>, g, b, 0, s, nsys, d_sys, nitems, counter); break;
+  }
   return hipGetLastError();
 }
 

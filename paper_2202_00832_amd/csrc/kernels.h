@@ -83,9 +83,10 @@ struct LpSys {
   double* partial;
 };
 // resets the item counter (a kernel, so the sequence can be captured in a
-// graph) and runs the persistent kernel over all items with `grid` workgroups
+// graph) and runs the persistent kernel over all items with `grid` workgroups;
+// nbmax (1..6): the largest nb of the systems, which selects the kernel
 hipError_t launch_exchange_batched(hipStream_t s, int nsys, const LpSys* d_sys, int64_t nitems, unsigned* counter,
-                                   int grid);
+                                   int grid, int nbmax);
 // theta [nw][M][n] complex -> FP32 [nw][Mp][NP] float2, or split BF16
 // [nw][4][NP][Mp] (re_hi, re_lo, im_hi, im_lo); lp_theta_bytes gives the size
 size_t lp_theta_bytes(int precision, int M, int n, int64_t nw);

@@ -1265,6 +1265,7 @@ struct lo_batch {
   std::vector<int64_t> chunk, nchunk;
   int64_t nitems = 0;
   int grid = 0;
+  int nbmax = 1;                            // largest orbital-block count of the systems
   void* mem = nullptr;                      // one device allocation for everything below
   std::vector<void*> lb, tb, cpart;         // per system
   std::vector<double*> partial;             // per system [nchunk + 1][nw][4]
@@ -1294,7 +1295,7 @@ hipError_t batch_enqueue(lo_batch* b, hipStream_t st) {
                                            b->lb[k], b->tb[k]);
     if (e != hipSuccess) return e;
   }
-  e = lofqmc::launch_exchange_batched(st, b->nsys, b->d_sys, b->nitems, b->d_counter, b->grid);
+  e = lofqmc::launch_exchange_batched(st, b->nsys, b->d_sys, b->nitems, b->d_counter, b->grid, b->nbmax);
   if (e != hipSuccess) return e;
   for (int k = 0; k < b->nsys; ++k) {
     const lo_system& s = b->sys[k];
@@ -1400,6 +1401,7 @@ int lo_batch_create(lo_ctx* ctx, int nsys, const lo_system* sys, int precision, 
     lofqmc::LpSys& d = table[q];
     d.Mp = lofqmc::lp_padded_m((int)s.M);
     d.nb = lofqmc::lp_orbital_blocks((int)s.n_occ);
+    b->nbmax = std::max(b->nbmax, d.nb);
     d.X = s.n_chol;
     d.nw = s.nw;
     d.gchunk = b->chunk[k];

@@ -2,7 +2,8 @@
 
 * With the chunk lengths of the single-system call, every work item and every
   partial sum is the same as in local_energy_full(precision=LO_FP32), so the
-  batch must reproduce it bit for bit.
+  batch must reproduce it bit for bit, for plans whose largest orbital-block
+  count is 6, 4, 3 and 1.
 * With the planner's default chunks, each system must lie within the FP32
   rounding bound of the CPU FP64 reference (the bound of the reduced-precision
   tests) and the Coulomb part within 1e-9.
@@ -84,7 +85,12 @@ def test_green_theta_wide_orbital_blocks(ctx, systems):
         assert np.abs(np.angle(np.exp(1j * (lg.imag - ld_ref.imag)))).max() <= 1e-10
 
 
-def test_batch_matches_single_system_bitwise(ctx, systems):
+# subsets whose largest orbital-block count is 6, 4, 3 and 1: the persistent
+# kernel is instantiated for the largest block count of the plan
+@pytest.mark.parametrize("pick", [None, [0, 2, 3, 4], [0, 2, 3], [3]])
+def test_batch_matches_single_system_bitwise(ctx, systems, pick):
+    systems = systems if pick is None else [systems[k] for k in pick]
+    print("batch bitwise: n = %s" % [s["n"] for s in systems], flush=True)
     singles = [host(ctx.local_energy_full(s["lbar"], s["theta"], precision=lofqmc.LO_FP32)) for s in systems]
     # chunk of the single-system call: ceil(X / nchunk) with the same chunk count
     chunk = []
