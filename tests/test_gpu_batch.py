@@ -27,7 +27,8 @@ if not torch.cuda.is_available():
 from paper_2202_00832_amd import autotune, lofqmc  # noqa: E402
 
 U = 2.0 ** -24
-SHAPES = [(37, 5, 11, 3), (131, 81, 23, 6), (70, 33, 30, 9), (20, 1, 7, 2), (100, 60, 40, 5), (96, 70, 17, 4)]
+SHAPES = [(37, 5, 11, 3), (131, 81, 23, 6), (70, 33, 30, 9), (20, 1, 7, 2), (100, 60, 40, 5), (96, 70, 17, 4),
+          (50, 24, 13, 3)]
 
 
 @pytest.fixture(scope="module")
@@ -85,9 +86,9 @@ def test_green_theta_wide_orbital_blocks(ctx, systems):
         assert np.abs(np.angle(np.exp(1j * (lg.imag - ld_ref.imag)))).max() <= 1e-10
 
 
-# subsets whose largest orbital-block count is 6, 4, 3 and 1: the persistent
-# kernel is instantiated for the largest block count of the plan
-@pytest.mark.parametrize("pick", [None, [0, 2, 3, 4], [0, 2, 3], [3]])
+# subsets whose largest orbital-block count is 6, 5, 4, 3, 2 and 1: the
+# persistent kernel is instantiated for the largest block count of the plan
+@pytest.mark.parametrize("pick", [None, [0, 2, 5], [0, 2, 3, 4], [0, 2, 3], [6, 0], [3]])
 def test_batch_matches_single_system_bitwise(ctx, systems, pick):
     systems = systems if pick is None else [systems[k] for k in pick]
     print("batch bitwise: n = %s" % [s["n"] for s in systems], flush=True)

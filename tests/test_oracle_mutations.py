@@ -80,3 +80,38 @@ def test_unnormalised_green_function_is_rejected():
     e_fock, _ = F.mixed_energy_restricted(eri, trial, phi)
     e_mut = sum(E.e2_wick(eri, G_wrong, G_wrong))
     assert abs(e_mut - e_fock) > 1e-6 * abs(e_fock)
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes in the truncation bound (Sec. 2.3.1)
+# ---------------------------------------------------------------------------
+
+def _bound_half(factors, theta):
+    return 0.5 * E.lo_error_bound(factors, theta)
+
+
+def _bound_last_kept(factors, theta):
+    # sigma_K (the last kept value) in place of the first discarded one
+    full = E.expand_upper(factors, theta.shape[1])
+    norms = np.linalg.norm(theta, axis=0)
+    return float(sum(3.0 * (s[Ub.shape[1] - 1] if Ub.shape[1] else 0.0) * norms[i] * norms[j]
+                     for (i, j), (Ub, _, s) in full.items()))
+
+
+def _bound_row_norms(factors, theta):
+    # norms of the rows of theta instead of its orbital columns
+    full = E.expand_upper(factors, theta.shape[1])
+    norms = np.linalg.norm(theta, axis=1)
+    return float(sum(3.0 * (s[Ub.shape[1]] if Ub.shape[1] < s.size else 0.0) * norms[i] * norms[j]
+                     for (i, j), (Ub, _, s) in full.items()))
+
+
+@pytest.mark.parametrize("mutant", [_bound_half, _bound_last_kept, _bound_row_norms], ids=lambda f: f.__name__)
+def test_bound_mutant_is_rejected(mutant):
+    """A bound must hold (|dE| <= bound) and, on the rank-one Coulomb case,
+    be tight to a factor of two (|dE| >= bound / 2)."""
+    from tests.test_oracle_pins import bound_case
+    fac, exact, theta, _, _, _ = bound_case("coulomb")
+    d = abs(sum(E.e2_lo(fac, theta)) - sum(E.e2_lo(exact, theta)))
+    b = mutant(fac, theta)
+    assert not (d <= b and d >= 0.5 * b)

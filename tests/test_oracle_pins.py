@@ -281,3 +281,53 @@ def test_localized_orbitals_compress_better():
     r_del = E.lo_ranks(E.lo_compress(E.half_rotate(sysm.chol, deloc), eps, "upper"), 8)
     M = sysm.config.M
     assert E.compression_percent(r_loc, M) > E.compression_percent(r_del, M) + 10.0
+
+
+def bound_case(channel: str, c0=1.7 * np.exp(0.4j), c1=0.6 * np.exp(-1.1j), sigma=0.1, seed=67):
+    """Two orbitals, M = 6, with pair blocks given by their SVDs (Eq. 18).
+
+    The diagonal blocks have exact rank 2 (nothing is discarded at eps = 0.5);
+    the off-diagonal block Y^[01] has singular values (2, 1, sigma, 0, 0, 0),
+    so at eps = 0.5 exactly the rank-one part Delta = sigma u v^T is dropped,
+    with u, v orthonormal.  channel "coulomb" puts theta_0 = c0 u,
+    theta_1 = c1 v: then only the direct term of Eq. 17 sees Delta, twice
+    (pairs 01 and 10), and |dE| = 4 sigma |c0 c1| (by hand: 2 x 2 sigma c0 c1);
+    channel "exchange" swaps the directions (theta_0 = c0 v, theta_1 = c1 u):
+    only the exchange term sees it and |dE| = 2 sigma |c0 c1|.  In both the
+    spectral-norm bound is 3 sigma ||theta_0|| ||theta_1|| per ordered pair,
+    6 sigma |c0 c1|.  Returns (factors at eps = 0.5, factors at eps = 0,
+    theta, expected |dE|, expected bound, last kept singular value)."""
+    rng = np.random.default_rng(seed)
+    Q = synth.random_orthogonal(6, rng)
+    A = synth.random_orthogonal(6, rng)
+    B = synth.random_orthogonal(6, rng)
+    diag_s = np.array([3.0, 2.0, 0.0, 0.0, 0.0, 0.0])
+    off_s = np.array([2.0, 1.0, sigma, 0.0, 0.0, 0.0])
+    V = Q[:, [1, 0, 3, 2, 5, 4]]             # v = V[:, 2] = Q[:, 3] is orthogonal to u = Q[:, 2]
+    decomp = {(0, 0): (A, diag_s, A.T), (1, 1): (B, diag_s, B.T), (0, 1): (Q, off_s, V.T)}
+    u, v = Q[:, 2], V[:, 2]
+    theta = np.zeros((6, 2), dtype=np.complex128)
+    if channel == "coulomb":
+        theta[:, 0], theta[:, 1] = c0 * u, c1 * v
+        expected = 4.0 * sigma * abs(c0 * c1)
+    else:
+        theta[:, 0], theta[:, 1] = c0 * v, c1 * u
+        expected = 2.0 * sigma * abs(c0 * c1)
+    return (E.lo_truncate(decomp, 0.5), E.lo_truncate(decomp, 0.0), theta, expected,
+            6.0 * sigma * abs(c0 * c1), off_s[1])
+
+
+@pytest.mark.parametrize("channel", ["coulomb", "exchange"])
+def test_lo_error_bound_closed_form(channel):
+    """The truncation bound and the LO error against closed forms worked out
+    by hand for a rank-one discarded part; in the Coulomb channel the error
+    reaches 2/3 of the bound, so a bound half as large is violated and one
+    built on the last kept singular value is ten times too loose."""
+    fac, exact, theta, expected, bound_expected, _ = bound_case(channel)
+    d = sum(E.e2_lo(fac, theta)) - sum(E.e2_lo(exact, theta))
+    assert abs(abs(d) - expected) < 1e-12 * expected
+    bound = E.lo_error_bound(fac, theta)
+    assert abs(bound - bound_expected) < 1e-12 * bound_expected
+    assert abs(d) <= bound
+    if channel == "coulomb":
+        assert abs(d) >= 0.5 * bound
