@@ -68,7 +68,10 @@ enum lo_precision {
 
 /* Creates a context bound to `hip_stream` (a hipStream_t; NULL = the null
  * stream).  The context owns only small metadata and a device workspace that
- * grows on first use of a size and is reused afterwards.  No device work. */
+ * grows on first use of a size and is reused afterwards.  No device work; on
+ * a host with a GPU it also looks up, once per device, the address of the
+ * fixed scratch of local_energy_lo_noalloc on the current device (LO_EHIP if
+ * that fails). */
 int lo_create(lo_ctx** ctx, void* hip_stream);
 
 /* Re-binds the context to another stream (no synchronisation). */
@@ -229,6 +232,24 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
  * workspace first.  flags may hold LO_THETA_ORBITAL_MAJOR only. */
 int local_energy_lo(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const double* theta,
                     const int32_t* info, int precision, unsigned flags, double* energy);
+
+/* local_energy_lo without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results as local_energy_lo;
+ * the intermediates live in a fixed scratch array of LO_NOALLOC_SCRATCH_BYTES
+ * (128 MiB) that every GPU the library runs on holds until the process ends,
+ * instead of the context workspace.  A call needs
+ *   16 nw n_out_rows + 32 nw n_chunks (+ the reduced-precision theta copy)
+ * bytes, each part rounded up to 256 (n_out_rows is the orbital-grouped row
+ * count of the factors, about 11 k at M = 400, n_occ = 60, eps = 1e-5, so
+ * about 700 walkers fit per call); a larger call returns LO_EUNSUPPORTED
+ * before any device work.  All calls on one GPU share that GPU's array:
+ * calls that overlap on one GPU (several streams or contexts, or several
+ * host threads) race, so serialise them.  The kernels write every scratch
+ * byte they read within the call, so no clearing is needed. */
+#define LO_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int local_energy_lo_noalloc(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const double* theta,
+                            const int32_t* info, int precision, unsigned flags, double* energy);
 
 /* ------------------------------------------------ half-rotated ERI route
  *

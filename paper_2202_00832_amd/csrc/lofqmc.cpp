@@ -14,6 +14,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -190,10 +191,41 @@ int prof_collect(lo_ctx* c) {
 }
 
 // RAII: closes the last kernel interval of a call on every return path.
+// Fixed device scratch of local_energy_lo_noalloc: the Q-bar intermediates,
+// the pass-2 partial sums and (reduced precision) the rewritten theta of one
+// call.  Every GPU the library runs on holds its own copy, at its own address,
+// until the process ends.  Host code never passes `scratch` itself to a kernel
+// (on the host it names a stand-in, not device memory): it uses the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = LO_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per device.
+int scratch_on_current_device(lo_ctx* c, void** out) {
+  int dev = -1;
+  HIP_OR_FAIL(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, LO_EUNSUPPORTED, "device index %d above %d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, LO_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LO_OK;
+}
+
 struct ProfScope {
   lo_ctx* c;
   lofqmc::ProfHook hook;
-  explicit ProfScope(lo_ctx* ctx) : c(ctx), hook{ctx, ctx->prof_on ? prof_record : nullptr} {}
+  explicit ProfScope(lo_ctx* ctx, bool allow_record = true)
+      : c(ctx), hook{ctx, (allow_record && ctx->prof_on) ? prof_record : nullptr} {}
   const lofqmc::ProfHook* get() const { return &hook; }
   void mark(const char* name) const { lofqmc::prof_mark(&hook, name); }
   ~ProfScope() { mark(nullptr); }
@@ -208,6 +240,19 @@ int lo_create(lo_ctx** ctx, void* hip_stream) {
   lo_ctx* c = new (std::nothrow) lo_ctx();
   if (!c) return LO_ENOMEM;
   c->stream = (hipStream_t)hip_stream;
+  // set-up of the fixed scratch on the current device (skipped on a host
+  // without a GPU; the allocation-free call then resolves it on first use)
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+    void* p = nullptr;
+    int rc = scratch_on_current_device(c, &p);
+    if (rc) {
+      delete c;
+      return rc;
+    }
+  } else {
+    (void)hipGetLastError();
+  }
   *ctx = c;
   return LO_OK;
 }
@@ -689,6 +734,71 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
   return LO_OK;
 #undef TRY_HIP
 #undef TRY_ALLOC
+}
+
+// Argument checks of the LO energy call and the scratch bytes it needs
+// (Q-bar intermediates, pass-2 partial sums, reduced-precision theta copy).
+int lo_energy_check(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const double* energy,
+                    int precision, unsigned flags, size_t* need) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!f) return fail(ctx, LO_EINVAL, "null factors");
+  if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
+  if (precision != LO_FP64 && precision != LO_FP32 && precision != LO_BF16X3)
+    return fail(ctx, LO_EINVAL, "unknown precision %d", precision);
+  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
+  if (precision != LO_FP64 && orbital_major)
+    return fail(ctx, LO_EUNSUPPORTED, "reduced precision reads walker-major theta only");
+  if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
+  if (precision != LO_FP64 && nw > 65535) return fail(ctx, LO_EUNSUPPORTED, "reduced precision: nw above 65535");
+  if (precision != LO_FP64 && f->n > (precision == LO_FP32 ? kMaxOccWide : kMaxOcc))
+    return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d for this precision",
+                precision == LO_FP32 ? kMaxOccWide : kMaxOcc);
+  *need = 0;
+  if (nw == 0) return LO_OK;
+  if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
+  const int nchunk = (int)(f->n_ent / lofqmc::lo_pass2_chunk());
+  const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
+  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
+  const size_t tbytes =
+      precision == LO_FP64 ? 0 : align256(lofqmc::lp_theta_bytes(precision, (int)f->M, (int)f->n, nw));
+  *need = qbytes + pbytes + tbytes;
+  return LO_OK;
+}
+
+// Queues the LO energy kernels on the context's stream with their scratch at
+// `base` (lo_energy_check's byte count); every byte they read there is
+// written first by an earlier kernel of the same call.
+int lo_energy_enqueue(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const int32_t* info,
+                      int precision, unsigned flags, double* energy, char* base, const ProfScope& prof) {
+  const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
+  const int64_t M = f->M, n = f->n;
+  const int nchunk = (int)(f->n_ent / lofqmc::lo_pass2_chunk());
+  const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
+  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
+  double* qbar = (double*)base;
+  double* partial = (double*)(base + qbytes);
+  if (precision == LO_FP64) {
+    prof.mark(lofqmc::lo_pass1_name((int)M));
+    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
+                                             f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
+                                             orbital_major ? 1 : 0, qbar, 0));
+  } else if (f->ntiles > 0) {
+    void* tlp = base + qbytes + pbytes;
+    prof.mark("lp_convert_kernel");
+    HIP_OR_FAIL(ctx, lofqmc::launch_lp_convert_theta(ctx->stream, precision, (int)M, (int)n, nw, theta, tlp));
+    prof.mark("lo_pass1_lp_kernel");
+    const void* rows_lp = precision == LO_FP32 ? (const void*)f->rows32 : (const void*)f->rowsbf;
+    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1_lp(ctx->stream, precision, (int)M, (int)n, nw, f->ntiles_lp, rows_lp,
+                                                f->d_rowidx, f->d_tiles_lp, f->d_tiles_lp + 3 * f->ntiles_lp,
+                                                f->nblk_lp, f->tmax_lp, tlp, qbar));
+  }
+  prof.mark("lo_pass2_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->n_ent, f->d_ent, f->d_entw, qbar, partial));
+  prof.mark("reduce_partials_kernel");
+  HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nchunk, partial, info, energy));
+  return LO_OK;
 }
 
 }  // namespace
@@ -1205,54 +1315,29 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
 
 int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const int32_t* info,
                     int precision, unsigned flags, double* energy) {
-  if (!ctx) return LO_EINVAL;
-  ctx->err.clear();
-  if (!f) return fail(ctx, LO_EINVAL, "null factors");
-  if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
-  if (precision != LO_FP64 && precision != LO_FP32 && precision != LO_BF16X3)
-    return fail(ctx, LO_EINVAL, "unknown precision %d", precision);
-  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
-  const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
-  if (precision != LO_FP64 && orbital_major)
-    return fail(ctx, LO_EUNSUPPORTED, "reduced precision reads walker-major theta only");
-  if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
-  if (precision != LO_FP64 && nw > 65535) return fail(ctx, LO_EUNSUPPORTED, "reduced precision: nw above 65535");
-  if (precision != LO_FP64 && f->n > (precision == LO_FP32 ? kMaxOccWide : kMaxOcc))
-    return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d for this precision",
-                precision == LO_FP32 ? kMaxOccWide : kMaxOcc);
-  if (nw == 0) return LO_OK;
-  if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
-  const int64_t M = f->M, n = f->n;
-  const int nchunk = (int)(f->n_ent / lofqmc::lo_pass2_chunk());
-  const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
-  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
-  const size_t tbytes = precision == LO_FP64 ? 0 : align256(lofqmc::lp_theta_bytes(precision, (int)M, (int)n, nw));
-  int rc = ensure_ws(ctx, qbytes + pbytes + tbytes);
+  size_t need = 0;
+  int rc = lo_energy_check(ctx, f, nw, theta, energy, precision, flags, &need);
+  if (rc || nw == 0) return rc;
+  rc = ensure_ws(ctx, need);
   if (rc) return rc;
-  char* base = (char*)ctx->ws;
-  double* qbar = (double*)base;
-  double* partial = (double*)(base + qbytes);
   ProfScope prof(ctx);
-  if (precision == LO_FP64) {
-    prof.mark(lofqmc::lo_pass1_name((int)M));
-    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
-                                             f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
-                                             orbital_major ? 1 : 0, qbar, 0));
-  } else if (f->ntiles > 0) {
-    void* tlp = base + qbytes + pbytes;
-    prof.mark("lp_convert_kernel");
-    HIP_OR_FAIL(ctx, lofqmc::launch_lp_convert_theta(ctx->stream, precision, (int)M, (int)n, nw, theta, tlp));
-    prof.mark("lo_pass1_lp_kernel");
-    const void* rows_lp = precision == LO_FP32 ? (const void*)f->rows32 : (const void*)f->rowsbf;
-    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1_lp(ctx->stream, precision, (int)M, (int)n, nw, f->ntiles_lp, rows_lp,
-                                                f->d_rowidx, f->d_tiles_lp, f->d_tiles_lp + 3 * f->ntiles_lp,
-                                                f->nblk_lp, f->tmax_lp, tlp, qbar));
-  }
-  prof.mark("lo_pass2_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->n_ent, f->d_ent, f->d_entw, qbar, partial));
-  prof.mark("reduce_partials_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nchunk, partial, info, energy));
-  return LO_OK;
+  return lo_energy_enqueue(ctx, f, nw, theta, info, precision, flags, energy, (char*)ctx->ws, prof);
+}
+
+int local_energy_lo_noalloc(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const int32_t* info,
+                            int precision, unsigned flags, double* energy) {
+  size_t need = 0;
+  int rc = lo_energy_check(ctx, f, nw, theta, energy, precision, flags, &need);
+  if (rc || nw == 0) return rc;
+  if (need > kNoAllocScratchBytes)
+    return fail(ctx, LO_EUNSUPPORTED,
+                "this batch needs %zu bytes of scratch, above the fixed %zu of local_energy_lo_noalloc "
+                "(use fewer walkers per call)", need, kNoAllocScratchBytes);
+  void* base = nullptr;
+  rc = scratch_on_current_device(ctx, &base);
+  if (rc) return rc;
+  ProfScope prof(ctx, /*allow_record=*/false);
+  return lo_energy_enqueue(ctx, f, nw, theta, info, precision, flags, energy, (char*)base, prof);
 }
 
 // ------------------------------------------------------ several systems

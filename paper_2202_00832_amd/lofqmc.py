@@ -43,6 +43,7 @@ _SIGS = {
     "local_energy_full": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _i64, _c_p, _c_p, _c_p, ctypes.c_int,
                                          ctypes.c_uint, _c_p]),
     "local_energy_lo": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p]),
+    "local_energy_lo_noalloc": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p]),
     "build_hr_eri": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, ctypes.POINTER(_c_p)]),
     "lo_hr_destroy": (ctypes.c_int, [_c_p]),
     "lo_hr_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p]),
@@ -447,8 +448,10 @@ class Context:
         return energy
 
     def local_energy_lo(self, factors: Factors, theta, info=None, energy=None, precision=LO_FP64, flags=0,
-                        orbital_major=False):
-        """theta is [nw][M][n], or [n][M][nw] when orbital_major."""
+                        orbital_major=False, noalloc=False):
+        """theta is [nw][M][n], or [n][M][nw] when orbital_major.  noalloc=True
+        calls local_energy_lo_noalloc (fixed scratch, no device allocation in
+        the library; `energy` should then be passed in by the caller)."""
         import torch
         if orbital_major:
             nw = theta.shape[2]
@@ -462,8 +465,9 @@ class Context:
         if energy is None:
             energy = torch.empty((nw, 2), dtype=torch.complex128, device=theta.device)
         _check_dev("energy", energy, torch.complex128, (nw, 2))
-        self._check(self._lib.local_energy_lo(self._h, factors.handle, nw, _ptr(theta), _ptr(info), int(precision),
-                                              int(flags), _ptr(energy)))
+        fn = self._lib.local_energy_lo_noalloc if noalloc else self._lib.local_energy_lo
+        self._check(fn(self._h, factors.handle, nw, _ptr(theta), _ptr(info), int(precision), int(flags),
+                       _ptr(energy)))
         return energy
 
     def local_energy_hr(self, hr: HrEri, theta, info=None, energy=None, orbital_major=False):

@@ -1,0 +1,121 @@
+"""local_energy_lo_noalloc: the LO energy with its intermediates in the
+library's fixed device scratch instead of the context workspace.
+
+It runs the same kernels on the same inputs as local_energy_lo, so the
+energies must agree bit for bit; two calls in a row (the second with fewer
+walkers, so it reads scratch the first call left behind) check that nothing
+of an earlier call leaks into a later one.  Both calls are also held to the
+CPU reference at the FP64 bar of 1e-9 Ha per walker.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import energy as E
+from paper_2202_00832_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_00832_amd import lofqmc  # noqa: E402
+
+TOL_E = 1e-9
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _system(M, n, X, nw, seed, sigma):
+    rng = np.random.default_rng(seed)
+    chol = synth.random_symmetric_cholesky(M, X, rng)
+    trial = np.linalg.qr(rng.standard_normal((M, n)))[0]
+    walkers = synth.noisy_walkers(trial, nw, sigma, rng)
+    return chol, trial, walkers
+
+
+@pytest.mark.parametrize("M,n,X,nw,nw2,eps", [(48, 8, 40, 16, 5, 1e-4), (120, 19, 70, 100, 37, 1e-3)])
+def test_noalloc_matches_workspace_call_twice(M, n, X, nw, nw2, eps):
+    print("noalloc case M=%d n=%d X=%d nw=%d then %d eps=%g" % (M, n, X, nw, nw2, eps), flush=True)
+    chol, trial, walkers = _system(M, n, X, nw, seed=71 + M, sigma=0.3)
+    ctx = lofqmc.Context()
+    try:
+        lbar = ctx.build_half_rotated_chol(dev(chol), dev(trial))
+        fac = ctx.build_lo_factors(lbar, eps)
+        theta, _, info = ctx.green_theta(dev(trial), dev(walkers))
+        ref_fac = E.lo_compress(E.half_rotate(chol, trial), eps, pairs="upper")
+        ths, _, _ = E.green_theta_batch(trial, walkers)
+        for count in (nw, nw2):
+            th = theta[:count].contiguous()
+            inf = info[:count].contiguous()
+            out = torch.full((count, 2), complex(np.nan, np.nan), dtype=torch.complex128, device="cuda")
+            e_na = ctx.local_energy_lo(fac, th, inf, energy=out, noalloc=True)
+            e_ws = ctx.local_energy_lo(fac, th, inf)
+            torch.cuda.synchronize()
+            assert torch.equal(e_na, e_ws), "no-alloc and workspace calls differ at nw=%d" % count
+            got = e_na.cpu().numpy()
+            ref = E.e2_lo_batch(ref_fac, ths[:count])
+            err = np.abs(got - ref).max()
+            assert err <= TOL_E, "max |dE| %.3e at nw=%d" % (err, count)
+        fac.close()
+    finally:
+        ctx.close()
+
+
+def test_noalloc_chain_many_walkers():
+    """The localized chain (low ranks): 600 walkers, then 33."""
+    s = synth.make_system(synth.CHAIN_SMALL, nw=600)
+    ctx = lofqmc.Context()
+    try:
+        lbar = ctx.build_half_rotated_chol(dev(s.chol), dev(s.trial))
+        fac = ctx.build_lo_factors(lbar, 1e-5)
+        theta, _, info = ctx.green_theta(dev(s.trial), dev(s.walkers))
+        for count in (600, 33):
+            th, inf = theta[:count].contiguous(), info[:count].contiguous()
+            out = torch.empty((count, 2), dtype=torch.complex128, device="cuda")
+            e_na = ctx.local_energy_lo(fac, th, inf, energy=out, noalloc=True)
+            e_ws = ctx.local_energy_lo(fac, th, inf)
+            torch.cuda.synchronize()
+            assert torch.equal(e_na, e_ws)
+        fac.close()
+    finally:
+        ctx.close()
+
+
+def test_noalloc_fp32_route_matches_workspace_call():
+    chol, trial, walkers = _system(64, 12, 50, 40, seed=9, sigma=0.3)
+    ctx = lofqmc.Context()
+    try:
+        lbar = ctx.build_half_rotated_chol(dev(chol), dev(trial))
+        fac = ctx.build_lo_factors(lbar, 1e-4)
+        theta, _, info = ctx.green_theta(dev(trial), dev(walkers))
+        for count in (40, 11):
+            th, inf = theta[:count].contiguous(), info[:count].contiguous()
+            out = torch.empty((count, 2), dtype=torch.complex128, device="cuda")
+            e_na = ctx.local_energy_lo(fac, th, inf, energy=out, precision=lofqmc.LO_FP32, noalloc=True)
+            e_ws = ctx.local_energy_lo(fac, th, inf, precision=lofqmc.LO_FP32)
+            torch.cuda.synchronize()
+            assert torch.equal(e_na, e_ws)
+        fac.close()
+    finally:
+        ctx.close()
+
+
+def test_noalloc_rejects_a_batch_beyond_its_scratch():
+    chol, trial, walkers = _system(48, 8, 40, 4, seed=3, sigma=0.3)
+    ctx = lofqmc.Context()
+    try:
+        lbar = ctx.build_half_rotated_chol(dev(chol), dev(trial))
+        fac = ctx.build_lo_factors(lbar, 1e-4)
+        lib = lofqmc.load()
+        fake = ctypes.c_void_p(0x1000)   # never dereferenced: the size check comes first
+        rc = lib.local_energy_lo_noalloc(ctx.handle, fac.handle, 1 << 30, fake, None, lofqmc.LO_FP64, 0, fake)
+        assert rc == lofqmc.LO_EUNSUPPORTED
+        assert b"scratch" in lib.lo_last_error(ctx.handle)
+        fac.close()
+    finally:
+        ctx.close()
