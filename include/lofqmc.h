@@ -398,21 +398,53 @@ int lo_batch_replay(lo_ctx* ctx, lo_batch* b);
  * Not part of the paper's method: a small network that predicts, per walker,
  * the energy that the LO truncation drops, Re(E_full - E_LO) ~ sum_i f(x_i),
  * from per-orbital features of occupied orbital i of a walker:
- *   x_i = (sum_j K_ij, sum_j m_ij, ||theta[:, i]||_2)
+ *   x_i = (sum_j K_ij, sum_j m_ij, ||theta[:, i]||_2, Re(g_i . theta[:, i]))
  * with K_ij the retained rank and m_ij the sum of the discarded singular
- * values of pair block Y^[ij] (Sec. 2.3.1).  f is 3 -> 128 -> 128 -> 1 with
+ * values of pair block Y^[ij] (Sec. 2.3.1), and g_i the gradient of the
+ * dropped energy E_HR - E_LO (Eq. 17 minus Eq. 22) with respect to column i
+ * of theta at the trial, theta = Psi (lo_residual_prepare).  The first three
+ * are the same for walkers whose columns have equal norms; the fourth is the
+ * first-order change of the dropped energy along the walker's own deviation
+ * from the trial.  f is 4 -> 128 -> 128 -> 1 with
  * tanh activations on standardised inputs z = (x - shift) * scale; the
  * parameters are one device float vector of lo_residual_nparam() entries:
- *   W1[128][3], b1[128], W2[128][128], b2[128], w3[128], b3, shift[3], scale[3]
+ *   W1[128][4], b1[128], W2[128][128], b2[128], w3[128], b3, shift[4], scale[4]
  * (shift and scale are set by the caller and never trained).  All arrays are
- * device pointers; every call is asynchronous on the context stream. */
+ * device pointers; every call except lo_residual_prepare is asynchronous on
+ * the context stream. */
 int lo_residual_nparam(void);
 
 /* Sum of the discarded singular values of every pair block, host double
  * [n_occ][n_occ] (symmetric). */
 int lo_factors_discarded(const lo_factors* f, double* mass);
 
-/* x : float [nw][n_occ][3] (output), theta : complex [nw][M][n_occ]. */
+/* Set-up of the fourth feature: forms, in FP64 on the device and stored with
+ * the factors, g[r][i] = d(E_HR - E_LO)/d theta[r][i] at theta = trial, from
+ *   lbar  : [n_chol][M][n_occ] double, the vectors the factors were built from
+ *   trial : [M][n_occ] double, the trial they were half-rotated with
+ * (shapes M, n_occ taken from the factors); grad_out (device double
+ * [M][n_occ]) receives a copy, or NULL.  Synchronous.  Must precede
+ * lo_residual_features (LO_EINVAL otherwise). */
+int lo_residual_prepare(lo_ctx* ctx, lo_factors* f, int64_t n_chol, const double* lbar, const double* trial,
+                        double* grad_out);
+
+/* Training target in mHa, standardised:
+ *   t[w] = (1000 Re(E_J + E_K of e_exact[w] - E_J - E_K of e_lo[w]) - shift) / scale
+ * e_exact, e_lo: complex [nw][2] (E_J, E_K) from an exact route and from
+ * local_energy_lo for the same walkers; t: double [nw] (output).  scale must
+ * be finite and non-zero. */
+int lo_residual_target(lo_ctx* ctx, int64_t nw, const double* e_exact, const double* e_lo, double shift, double scale,
+                       double* t);
+
+/* Walker energy with the learned correction:
+ *   out[w] = E_J + E_K + (pred[w] * scale + shift) / 1000   (the correction on the real part)
+ * energy: complex [nw][2] (E_J, E_K); pred: double [nw] from
+ * lo_residual_predict, whose network works on targets standardised by
+ * (shift, scale) mHa, or NULL for the plain sum E_J + E_K; out: complex [nw]. */
+int lo_residual_apply(lo_ctx* ctx, int64_t nw, const double* energy, const double* pred, double scale, double shift,
+                      double* out);
+
+/* x : float [nw][n_occ][4] (output), theta : complex [nw][M][n_occ]. */
 int lo_residual_features(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, float* x);
 
 /* pred[w] = sum_i f(x_wi) (double [nw], output).  precision LO_FP32 (FP32

@@ -9,13 +9,21 @@ from cheap per-orbital features x_i of occupied orbital i:
                                   m_ij = sum of the singular values of Y^[ij]
                                   below the threshold)
     x_i2 = || theta[:, i] ||_2   (norm of orbital i's column of Q)
-f is a 3-layer perceptron 3 -> 128 -> 128 -> 1 with tanh activations on
+    x_i3 = Re(g_i . theta[:, i]) (first-order change of the dropped energy
+                                  along orbital i's column; g_i is the
+                                  gradient of E_HR - E_LO with respect to
+                                  column i of Q at the trial, Q = Psi,
+                                  dropped_energy_gradient)
+The first three carry no walker-specific information about the sign of the
+dropped energy (only column norms vary between walkers), so on their own the
+best additive predictor is a constant; x_i3 is the walker-dependent part.
+f is a 3-layer perceptron 4 -> 128 -> 128 -> 1 with tanh activations on
 standardised inputs z = (x - shift) * scale.  The walker loss is the mean
 squared error over walkers of sum_i f(x_i) against the target.
 
 Parameters are one flat float vector, in this order:
-    W1 [128][3], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1],
-    shift [3], scale [3]          (shift and scale are not trained)
+    W1 [128][4], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1],
+    shift [4], scale [4]          (shift and scale are not trained)
 Everything here is float64 numpy; the backward pass is written out by hand.
 """
 from __future__ import annotations
@@ -23,7 +31,7 @@ from __future__ import annotations
 import numpy as np
 
 WIDTH = 128
-NFEAT = 3
+NFEAT = 4
 SIZES = [("W1", (WIDTH, NFEAT)), ("b1", (WIDTH,)), ("W2", (WIDTH, WIDTH)), ("b2", (WIDTH,)),
          ("w3", (WIDTH,)), ("b3", (1,)), ("shift", (NFEAT,)), ("scale", (NFEAT,))]
 NPARAM = sum(int(np.prod(s)) for _, s in SIZES)
@@ -43,14 +51,43 @@ def pack(d: dict) -> np.ndarray:
     return np.concatenate([np.asarray(d[name], dtype=np.float64).reshape(-1) for name, _ in SIZES])
 
 
-def features(ranks: np.ndarray, discarded: np.ndarray, theta: np.ndarray) -> np.ndarray:
-    """x[i] = (sum_j K_ij, sum_j m_ij, ||theta[:, i]||) for one walker; [n][3]."""
+def features(ranks: np.ndarray, discarded: np.ndarray, theta: np.ndarray, grad: np.ndarray) -> np.ndarray:
+    """x[i] = (sum_j K_ij, sum_j m_ij, ||theta[:, i]||, Re(grad[i] . theta[:, i]))
+    for one walker; grad is dropped_energy_gradient's [n][M]; returns [n][4]."""
     n = theta.shape[1]
     x = np.empty((n, NFEAT))
     x[:, 0] = ranks.sum(axis=1)
     x[:, 1] = discarded.sum(axis=1)
     x[:, 2] = np.sqrt(np.sum(np.abs(theta) ** 2, axis=0))
+    x[:, 3] = np.array([np.real(grad[i] @ theta[:, i]) for i in range(n)])
     return x
+
+
+def dropped_energy_gradient(lbar: np.ndarray, factors: dict, trial: np.ndarray) -> np.ndarray:
+    """g[i] = d(E_HR - E_LO)/d theta[:, i] at theta = trial; [n][M].
+
+    Both energies are the same quadratic form of Q (Eq. 17 and Eq. 22) with
+    pair matrices A^[ij] = Y^[ij] (exact, oracle.energy.pair_block) or
+    Ubar^[ij] Vbar^[ij] (LO, every ordered pair):
+        E(Q) = sum_ij 2 Q_i^T A^[ij] Q_j - Q_j^T A^[ij] Q_i,
+    whose gradient with respect to column i is
+        sum_j 2 (A^[ij] + A^[ji]^T) Q_j - (A^[ji] + A^[ij]^T) Q_j.
+    The dropped matrices D^[ij] = Y^[ij] - Ubar Vbar take the place of A.
+    lbar is oracle.energy.half_rotate's [X][n][M]; factors from lo_compress.
+    """
+    from oracle import energy as E
+    n = lbar.shape[1]
+    full = E.expand_upper(factors, n)
+    D = {}
+    for (i, j), (Ub, Vb, _) in full.items():
+        D[(i, j)] = E.pair_block(lbar, i, j) - Ub @ Vb
+    M = trial.shape[0]
+    g = np.zeros((n, M))
+    for i in range(n):
+        for j in range(n):
+            psi_j = trial[:, j]
+            g[i] += 2.0 * (D[(i, j)] + D[(j, i)].T) @ psi_j - (D[(j, i)] + D[(i, j)].T) @ psi_j
+    return g
 
 
 def forward(p: np.ndarray, x: np.ndarray):

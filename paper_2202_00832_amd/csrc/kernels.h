@@ -104,9 +104,23 @@ hipError_t launch_lo_pass1_lp(hipStream_t s, int precision, int M, int n, int64_
 int residual_nparam();
 size_t residual_train_workspace(int64_t nw, int n);
 size_t residual_predict_workspace(int bf16, int64_t nw, int n);
-// orb: device float [n][2] (sum_j K_ij, sum_j discarded mass); x: [nw][n][3]
+// orb: device float [n][2] (sum_j K_ij, sum_j discarded mass); grad: device
+// double [M][n] (gradient of the dropped energy at the trial); x: [nw][n][4]
 hipError_t launch_residual_features(hipStream_t s, int M, int n, int64_t nw, const double* theta, const float* orb,
-                                    float* x);
+                                    const double* grad, float* x);
+// grad [M][n] = d(E_HR - E_LO)/d theta at theta = trial, from lbar [X][M][n],
+// trial [M][n] and the stored factor rows (pair_of_row [total_rows][2],
+// pair_off int64 [n][n], pair_k int [n][n] for a <= b); work of
+// residual_gradient_workspace bytes
+size_t residual_gradient_workspace(int n, int64_t X, int64_t total_rows);
+// energies are complex [nw][2] (E_J, E_K); t, pred: double [nw]; out: complex [nw]
+hipError_t launch_residual_target(hipStream_t s, int64_t nw, const double* e_exact, const double* e_lo, double shift,
+                                  double scale, double* t);
+hipError_t launch_residual_apply(hipStream_t s, int64_t nw, const double* energy, const double* pred, double scale,
+                                 double shift, double* out);
+hipError_t launch_residual_gradient(hipStream_t s, int M, int n, int64_t X, const double* lbar, const double* trial,
+                                    int64_t total_rows, const double* rows, const int* pair_of_row,
+                                    const int64_t* pair_off, const int* pair_k, void* work, double* grad);
 hipError_t launch_residual_predict(hipStream_t s, int bf16, int64_t nw, int n, const float* params, const float* x,
                                    void* work, double* pred);
 // step <= 0: gradient (and loss, predictions) only, no update

@@ -52,6 +52,7 @@ struct lo_factors {
   int* d_ent = nullptr;                // [4][n_ent]: output rows of QL_i, QR_j, QL_j, QR_i of one rank row
   double* d_entw = nullptr;            // [n_ent]: pair weight (1 for i = j, 2 for i < j; 0 for padding)
   float* d_orbfeat = nullptr;          // [n][2]: sum_j K_ij, sum_j discarded mass (residual features)
+  double* d_grad = nullptr;            // [M][n]: gradient of the dropped energy at the trial (lo_residual_prepare)
 };
 
 struct lo_md {
@@ -149,6 +150,7 @@ void free_factors(lo_factors* f) {
   (void)hipFree(f->d_ent);
   (void)hipFree(f->d_entw);
   (void)hipFree(f->d_orbfeat);
+  (void)hipFree(f->d_grad);
   delete f;
 }
 
@@ -1592,9 +1594,87 @@ int lo_residual_features(lo_ctx* ctx, const lo_factors* f, int64_t nw, const dou
   if (nw == 0) return LO_OK;
   if (!theta || !x) return fail(ctx, LO_EINVAL, "null array");
   if (!f->d_orbfeat) return fail(ctx, LO_EINVAL, "factors hold no orbital table");
+  if (!f->d_grad) return fail(ctx, LO_EINVAL, "lo_residual_prepare has not been called for these factors");
   ProfScope prof(ctx);
   prof.mark("residual_features_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_residual_features(ctx->stream, (int)f->M, (int)f->n, nw, theta, f->d_orbfeat, x));
+  HIP_OR_FAIL(ctx, lofqmc::launch_residual_features(ctx->stream, (int)f->M, (int)f->n, nw, theta, f->d_orbfeat,
+                                                    f->d_grad, x));
+  return LO_OK;
+}
+
+int lo_residual_target(lo_ctx* ctx, int64_t nw, const double* e_exact, const double* e_lo, double shift, double scale,
+                       double* t) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
+  if (!(scale != 0.0) || !std::isfinite(scale) || !std::isfinite(shift))
+    return fail(ctx, LO_EINVAL, "scale must be finite and non-zero, shift finite");
+  if (nw == 0) return LO_OK;
+  if (!e_exact || !e_lo || !t) return fail(ctx, LO_EINVAL, "null array");
+  HIP_OR_FAIL(ctx, lofqmc::launch_residual_target(ctx->stream, nw, e_exact, e_lo, shift, scale, t));
+  return LO_OK;
+}
+
+int lo_residual_apply(lo_ctx* ctx, int64_t nw, const double* energy, const double* pred, double scale, double shift,
+                      double* out) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
+  if (!std::isfinite(scale) || !std::isfinite(shift)) return fail(ctx, LO_EINVAL, "scale and shift must be finite");
+  if (nw == 0) return LO_OK;
+  if (!energy || !out) return fail(ctx, LO_EINVAL, "null array");
+  HIP_OR_FAIL(ctx, lofqmc::launch_residual_apply(ctx->stream, nw, energy, pred, scale, shift, out));
+  return LO_OK;
+}
+
+int lo_residual_prepare(lo_ctx* ctx, lo_factors* f, int64_t n_chol, const double* lbar, const double* trial,
+                        double* grad_out) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!f) return fail(ctx, LO_EINVAL, "null factors");
+  if (n_chol < 0) return fail(ctx, LO_EINVAL, "n_chol < 0");
+  if ((n_chol > 0 && !lbar) || !trial) return fail(ctx, LO_EINVAL, "null array");
+  const int64_t M = f->M, n = f->n;
+  // host tables: the pair of every stored row, first row and rank of every pair a <= b
+  std::vector<int> pair_of_row(2 * (size_t)f->total_rows, 0);
+  std::vector<int64_t> pair_off(n * n, 0);
+  std::vector<int> pair_k(n * n, 0);
+  for (int64_t a = 0; a < n; ++a)
+    for (int64_t b = a; b < n; ++b) {
+      const int64_t off = f->row_offset[a * n + b];
+      const int K = f->ranks[a * n + b];
+      pair_off[a * n + b] = off;
+      pair_k[a * n + b] = K;
+      for (int64_t k = 0; k < 2 * (int64_t)K; ++k) {
+        pair_of_row[2 * (off + k)] = (int)a;
+        pair_of_row[2 * (off + k) + 1] = (int)b;
+      }
+    }
+  if (!f->d_grad && hipMalloc(&f->d_grad, sizeof(double) * (size_t)(M * n)) != hipSuccess) {
+    f->d_grad = nullptr;
+    return fail(ctx, LO_ENOMEM, "gradient allocation failed");
+  }
+  int rc = ensure_ws(ctx, lofqmc::residual_gradient_workspace((int)n, n_chol, f->total_rows));
+  if (rc) return rc;
+  int* d_por = nullptr;
+  int64_t* d_off = nullptr;
+  int* d_k = nullptr;
+  if ((rc = upload(ctx, &d_por, pair_of_row)) || (rc = upload(ctx, &d_off, pair_off)) ||
+      (rc = upload(ctx, &d_k, pair_k))) {
+    (void)hipFree(d_por);
+    (void)hipFree(d_off);
+    (void)hipFree(d_k);
+    return rc;
+  }
+  hipError_t e = lofqmc::launch_residual_gradient(ctx->stream, (int)M, (int)n, n_chol, lbar, trial, f->total_rows,
+                                                  f->rows, d_por, d_off, d_k, ctx->ws, f->d_grad);
+  if (e == hipSuccess && grad_out)
+    e = hipMemcpyAsync(grad_out, f->d_grad, sizeof(double) * (size_t)(M * n), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(d_por);
+  (void)hipFree(d_off);
+  (void)hipFree(d_k);
+  if (e != hipSuccess) return fail(ctx, LO_EHIP, "residual gradient: %s", hipGetErrorString(e));
   return LO_OK;
 }
 

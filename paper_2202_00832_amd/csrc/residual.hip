@@ -1,13 +1,15 @@
 // Learned correction of the LO energy (not part of the paper's method).
 //
-// A 3-layer perceptron f: R^3 -> R (3 -> 128 -> 128 -> 1, tanh, standardised
+// A 3-layer perceptron f: R^4 -> R (4 -> 128 -> 128 -> 1, tanh, standardised
 // inputs) maps per-orbital features of a walker to a share of the energy that
 // the LO truncation drops; the walker's prediction is sum_i f(x_i).  Features
 // of orbital i: x0 = sum_j K_ij (retained ranks), x1 = sum_j m_ij (discarded
-// singular-value mass), x2 = ||theta[:, i]||_2.
+// singular-value mass), x2 = ||theta[:, i]||_2, x3 = Re(g_i . theta[:, i]) with
+// g_i the gradient of the dropped energy E_HR - E_LO with respect to column i
+// of theta at the trial (theta = Psi), formed once per set of factors.
 //
-// Parameters: one float vector, W1[128][3], b1[128], W2[128][128], b2[128],
-// w3[128], b3, shift[3], scale[3] (shift and scale are not trained).
+// Parameters: one float vector, W1[128][4], b1[128], W2[128][128], b2[128],
+// w3[128], b3, shift[4], scale[4] (shift and scale are not trained).
 //
 // Kernels: features; FP32 forward that keeps the activations; per-walker sum
 // and loss; backward through the rows; weight gradients as fixed-order sums
@@ -23,31 +25,153 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int RW = 128;   // width
-constexpr int RF = 3;     // features
+constexpr int RF = 4;     // features
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + RW * RF, OFF_W2 = OFF_B1 + RW, OFF_B2 = OFF_W2 + RW * RW,
               OFF_W3 = OFF_B2 + RW, OFF_B3 = OFF_W3 + RW, OFF_SHIFT = OFF_B3 + 1, OFF_SCALE = OFF_SHIFT + RF,
               NPAR = OFF_SCALE + RF;
 
 int residual_nparam() { return NPAR; }
 
-// x[w][i] = (Ksum_i, mass_i, ||theta_w[:, i]||); one thread per (walker, orbital)
+// x[w][i] = (Ksum_i, mass_i, ||theta_w[:, i]||, Re(g_i . theta_w[:, i]));
+// one thread per (walker, orbital); grad is [M][n] like theta
 __global__ __launch_bounds__(256) void residual_features_kernel(int M, int n, int64_t nw,
                                                                 const double2* __restrict__ theta,
                                                                 const float* __restrict__ orb,
+                                                                const double* __restrict__ grad,
                                                                 float* __restrict__ x) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= nw * n) return;
   const int64_t w = e / n;
   const int i = (int)(e % n);
   const double2* t = theta + (size_t)w * M * n + i;
-  double s = 0.0;
+  double s = 0.0, d = 0.0;
   for (int r = 0; r < M; ++r) {
     const double2 v = t[(size_t)r * n];
     s += v.x * v.x + v.y * v.y;
+    d += grad[(size_t)r * n + i] * v.x;
   }
   x[e * RF + 0] = orb[2 * i];
   x[e * RF + 1] = orb[2 * i + 1];
   x[e * RF + 2] = (float)sqrt(s);
+  x[e * RF + 3] = (float)d;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient of the dropped energy at the trial (set-up, FP64).  Both E_HR
+// (Eq. 17) and E_LO (Eq. 22) are E(Q) = sum_ij 2 Q_i^T A^[ij] Q_j -
+// Q_j^T A^[ij] Q_i with A^[ji] = A^[ij]^T, so with Q = Psi
+//   grad_i = sum_j 4 A^[ij] psi_j - 2 A^[ji] psi_j.
+// Exact part, A^[ij] = sum_g Lbar_g[:, i] Lbar_g[:, j]^T and
+// T0_g[i][j] = Lbar_g[:, i] . psi_j, C_g = sum_i T0_g[i][i]:
+//   G_i = 4 sum_g C_g Lbar_g[:, i] - 2 sum_g sum_j Lbar_g[:, j] T0_g[i][j].
+// LO part from the stored rows u_k (of Ubar^T) and v_k (of Vbar) of pair
+// (a, b), a <= b, summed over k (both orderings of a < b counted):
+//   i = a < b: 4 u (v . psi_b) - 2 v (u . psi_b)
+//   i = b > a: 4 v (u . psi_a) - 2 u (v . psi_a)
+//   i = a = b: u (v . psi_a) + v (u . psi_a)
+// ---------------------------------------------------------------------------
+
+// T0[g][i][j]; one thread per (g, i, j)
+__global__ __launch_bounds__(256) void residual_t0_kernel(int M, int n, int64_t X, const double* __restrict__ lbar,
+                                                          const double* __restrict__ trial,
+                                                          double* __restrict__ t0) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (e >= X * nn) return;
+  const int64_t g = e / nn;
+  const int i = (int)((e % nn) / n), j = (int)(e % n);
+  const double* L = lbar + (size_t)g * M * n;
+  double s = 0.0;
+  for (int r = 0; r < M; ++r) s += L[(size_t)r * n + i] * trial[(size_t)r * n + j];
+  t0[e] = s;
+}
+
+// C[g] = sum_i T0[g][i][i]; one thread per g
+__global__ __launch_bounds__(256) void residual_trace_kernel(int n, int64_t X, const double* __restrict__ t0,
+                                                             double* __restrict__ c) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= X) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += t0[(size_t)g * n * n + (size_t)i * n + i];
+  c[g] = s;
+}
+
+// grad[r][i] = G_i[r] (exact part); one thread per (r, i)
+__global__ __launch_bounds__(256) void residual_grad_exact_kernel(int M, int n, int64_t X,
+                                                                  const double* __restrict__ lbar,
+                                                                  const double* __restrict__ t0,
+                                                                  const double* __restrict__ c,
+                                                                  double* __restrict__ grad) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)M * n) return;
+  const int r = (int)(e / n), i = (int)(e % n);
+  double acc = 0.0;
+  for (int64_t g = 0; g < X; ++g) {
+    const double* Lr = lbar + ((size_t)g * M + r) * n;
+    const double* T = t0 + (size_t)g * n * n + (size_t)i * n;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += Lr[j] * T[j];
+    acc += 4.0 * c[g] * Lr[i] - 2.0 * s;
+  }
+  grad[e] = acc;
+}
+
+// d[rho] = (row_rho . psi_a, row_rho . psi_b) for stored row rho of pair
+// (a, b) = pair_of_row[rho]; one wave per row, lanes over r, fixed-order sum
+__global__ __launch_bounds__(256) void residual_row_dots_kernel(int M, int n, int64_t total_rows,
+                                                                const double* __restrict__ rows,
+                                                                const int* __restrict__ pair_of_row,
+                                                                const double* __restrict__ trial,
+                                                                double* __restrict__ d) {
+  const int64_t rho = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (rho >= total_rows) return;
+  const int a = pair_of_row[2 * rho], b = pair_of_row[2 * rho + 1];
+  const double* row = rows + (size_t)rho * M;
+  double sa = 0.0, sb = 0.0;
+  for (int r = lane; r < M; r += 64) {
+    const double v = row[r];
+    sa += v * trial[(size_t)r * n + a];
+    sb += v * trial[(size_t)r * n + b];
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    sa += __shfl_xor(sa, off, 64);
+    sb += __shfl_xor(sb, off, 64);
+  }
+  if (lane == 0) {
+    d[2 * rho] = sa;
+    d[2 * rho + 1] = sb;
+  }
+}
+
+// grad[r][i] -= LO part; one thread per (r, i).  pair_off / pair_k: [n][n]
+// first row and rank of the stored pair (a, b), a <= b.
+__global__ __launch_bounds__(256) void residual_grad_lo_kernel(int M, int n, const double* __restrict__ rows,
+                                                               const int64_t* __restrict__ pair_off,
+                                                               const int* __restrict__ pair_k,
+                                                               const double* __restrict__ d,
+                                                               double* __restrict__ grad) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)M * n) return;
+  const int r = (int)(e / n), i = (int)(e % n);
+  double acc = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    const int64_t off = pair_off[a * n + b];
+    const int K = pair_k[a * n + b];
+    for (int k = 0; k < K; ++k) {
+      const int64_t ru = off + k, rv = off + K + k;
+      const double u = rows[(size_t)ru * M + r], v = rows[(size_t)rv * M + r];
+      const double du_a = d[2 * ru], du_b = d[2 * ru + 1], dv_a = d[2 * rv], dv_b = d[2 * rv + 1];
+      if (a == b)
+        acc += u * dv_a + v * du_a;
+      else if (i == a)
+        acc += 4.0 * u * dv_b - 2.0 * v * du_b;
+      else
+        acc += 4.0 * v * du_a - 2.0 * u * dv_a;
+    }
+  }
+  grad[e] -= acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -223,7 +347,7 @@ __global__ __launch_bounds__(256) void residual_weight_grad_kernel(int64_t N, in
 #pragma unroll
     for (int b = 0; b < 8; ++b) acc[a][b] = 0.0f;
   // small gradients: thread tid < 128 owns column tid of db1, db2, dw3, dW1
-  float s_db1 = 0.0f, s_db2 = 0.0f, s_dw3 = 0.0f, s_dw1[RF] = {0.0f, 0.0f, 0.0f}, s_db3 = 0.0f;
+  float s_db1 = 0.0f, s_db2 = 0.0f, s_dw3 = 0.0f, s_dw1[RF] = {}, s_db3 = 0.0f;
   for (int64_t c0 = r0; c0 < r1; c0 += RT) {
     __syncthreads();
     for (int e = tid; e < RT * RW; e += 256) {
@@ -384,11 +508,82 @@ size_t residual_train_workspace(int64_t nw, int n) {
 }
 
 hipError_t launch_residual_features(hipStream_t s, int M, int n, int64_t nw, const double* theta, const float* orb,
-                                    float* x) {
+                                    const double* grad, float* x) {
   if (nw <= 0) return hipSuccess;
   const int64_t tot = nw * n;
   hipLaunchKernelGGL(residual_features_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, n, nw,
-                     (const double2*)theta, orb, x);
+                     (const double2*)theta, orb, grad, x);
+  return hipGetLastError();
+}
+
+// t[w] = (1000 Re(sum_c e_exact[w][c] - sum_c e_lo[w][c]) - shift) / scale
+__global__ __launch_bounds__(256) void residual_target_kernel(int64_t nw, const double2* __restrict__ e_exact,
+                                                              const double2* __restrict__ e_lo, double shift,
+                                                              double scale, double* __restrict__ t) {
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= nw) return;
+  const double d = (e_exact[2 * w].x + e_exact[2 * w + 1].x) - (e_lo[2 * w].x + e_lo[2 * w + 1].x);
+  t[w] = (1000.0 * d - shift) / scale;
+}
+
+// out[w] = E_J + E_K (+ (pred[w] scale + shift) / 1000 on the real part)
+__global__ __launch_bounds__(256) void residual_apply_kernel(int64_t nw, const double2* __restrict__ e,
+                                                             const double* __restrict__ pred, double scale,
+                                                             double shift, double2* __restrict__ out) {
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= nw) return;
+  double2 v;
+  v.x = e[2 * w].x + e[2 * w + 1].x;
+  v.y = e[2 * w].y + e[2 * w + 1].y;
+  if (pred) v.x += (pred[w] * scale + shift) / 1000.0;
+  out[w] = v;
+}
+
+hipError_t launch_residual_target(hipStream_t s, int64_t nw, const double* e_exact, const double* e_lo, double shift,
+                                  double scale, double* t) {
+  if (nw <= 0) return hipSuccess;
+  hipLaunchKernelGGL(residual_target_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, nw,
+                     (const double2*)e_exact, (const double2*)e_lo, shift, scale, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_apply(hipStream_t s, int64_t nw, const double* energy, const double* pred, double scale,
+                                 double shift, double* out) {
+  if (nw <= 0) return hipSuccess;
+  hipLaunchKernelGGL(residual_apply_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, nw,
+                     (const double2*)energy, pred, scale, shift, (double2*)out);
+  return hipGetLastError();
+}
+
+size_t residual_gradient_workspace(int n, int64_t X, int64_t total_rows) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(sizeof(double) * (size_t)X * n * n) + al(sizeof(double) * (size_t)X) +
+         al(sizeof(double) * 2 * (size_t)total_rows);
+}
+
+hipError_t launch_residual_gradient(hipStream_t s, int M, int n, int64_t X, const double* lbar, const double* trial,
+                                    int64_t total_rows, const double* rows, const int* pair_of_row,
+                                    const int64_t* pair_off, const int* pair_k, void* work, double* grad) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  char* base = (char*)work;
+  double* t0 = (double*)base;
+  double* c = (double*)(base + al(sizeof(double) * (size_t)X * n * n));
+  double* d = (double*)((char*)c + al(sizeof(double) * (size_t)X));
+  const int64_t mn = (int64_t)M * n;
+  if (X > 0) {
+    const int64_t tot = X * n * n;
+    hipLaunchKernelGGL(residual_t0_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, n, X, lbar, trial,
+                       t0);
+    hipLaunchKernelGGL(residual_trace_kernel, dim3((unsigned)((X + 255) / 256)), dim3(256), 0, s, n, X, t0, c);
+  }
+  hipLaunchKernelGGL(residual_grad_exact_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, M, n, X, lbar,
+                     t0, c, grad);
+  if (total_rows > 0) {
+    hipLaunchKernelGGL(residual_row_dots_kernel, dim3((unsigned)((total_rows + 3) / 4)), dim3(256), 0, s, M, n,
+                       total_rows, rows, pair_of_row, trial, d);
+    hipLaunchKernelGGL(residual_grad_lo_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, M, n, rows,
+                       pair_off, pair_k, d, grad);
+  }
   return hipGetLastError();
 }
 

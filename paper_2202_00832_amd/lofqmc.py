@@ -20,6 +20,7 @@ HEADER_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__fil
 LO_OK, LO_EINVAL, LO_ENOMEM, LO_EHIP, LO_EUNSUPPORTED, LO_ESOLVER = 0, -1, -2, -3, -4, -5
 LO_FP64, LO_FP32, LO_BF16X3, LO_BF16 = 0, 1, 2, 3
 LO_THETA_ORBITAL_MAJOR = 1
+RESIDUAL_NFEAT = 4   # per-orbital features of the learned residual
 _NAMES = {0: "LO_OK", -1: "LO_EINVAL", -2: "LO_ENOMEM", -3: "LO_EHIP", -4: "LO_EUNSUPPORTED", -5: "LO_ESOLVER"}
 
 _c_p = ctypes.c_void_p
@@ -61,6 +62,9 @@ _SIGS = {
     "lo_batch_replay": (ctypes.c_int, [_c_p, _c_p]),
     "lo_residual_nparam": (ctypes.c_int, []),
     "lo_factors_discarded": (ctypes.c_int, [_c_p, _c_p]),
+    "lo_residual_prepare": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, _c_p]),
+    "lo_residual_target": (ctypes.c_int, [_c_p, _i64, _c_p, _c_p, ctypes.c_double, ctypes.c_double, _c_p]),
+    "lo_residual_apply": (ctypes.c_int, [_c_p, _i64, _c_p, _c_p, ctypes.c_double, ctypes.c_double, _c_p]),
     "lo_residual_features": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p]),
     "lo_residual_predict": (ctypes.c_int, [_c_p, _i64, _i64, _c_p, _c_p, ctypes.c_int, _c_p]),
     "lo_residual_train_step": (ctypes.c_int, [_c_p, _i64, _i64, _c_p, _c_p, _c_p, _i64, ctypes.c_double, _c_p,
@@ -548,14 +552,54 @@ class Context:
     def residual_nparam(self) -> int:
         return int(self._lib.lo_residual_nparam())
 
+    def residual_prepare(self, factors: Factors, lbar, trial, grad=None):
+        """Set-up of the fourth residual feature (the gradient of the dropped
+        energy at the trial); lbar [X][M][n] and trial [M][n] are the inputs the
+        factors were built from.  grad: optional device float64 [M][n] copy."""
+        import torch
+        X = lbar.shape[0]
+        _check_dev("lbar", lbar, torch.float64, (X, factors.M, factors.n_occ))
+        _check_dev("trial", trial, torch.float64, (factors.M, factors.n_occ))
+        if grad is not None:
+            _check_dev("grad", grad, torch.float64, (factors.M, factors.n_occ))
+        self._check(self._lib.lo_residual_prepare(self._h, factors.handle, X, _ptr(lbar), _ptr(trial), _ptr(grad)))
+        return grad
+
+    def residual_target(self, e_exact, e_lo, shift=0.0, scale=1.0, t=None):
+        """(1000 Re(sum e_exact - sum e_lo) - shift) / scale per walker, float64 [nw]."""
+        import torch
+        nw = e_lo.shape[0]
+        _check_dev("e_exact", e_exact, torch.complex128, (nw, 2))
+        _check_dev("e_lo", e_lo, torch.complex128, (nw, 2))
+        if t is None:
+            t = torch.empty((nw,), dtype=torch.float64, device=e_lo.device)
+        _check_dev("t", t, torch.float64, (nw,))
+        self._check(self._lib.lo_residual_target(self._h, nw, _ptr(e_exact), _ptr(e_lo), float(shift), float(scale),
+                                                 _ptr(t)))
+        return t
+
+    def residual_apply(self, energy, pred=None, scale=1.0, shift=0.0, out=None):
+        """E_J + E_K (+ (pred * scale + shift) / 1000 on the real part), complex128 [nw]."""
+        import torch
+        nw = energy.shape[0]
+        _check_dev("energy", energy, torch.complex128, (nw, 2))
+        if pred is not None:
+            _check_dev("pred", pred, torch.float64, (nw,))
+        if out is None:
+            out = torch.empty((nw,), dtype=torch.complex128, device=energy.device)
+        _check_dev("out", out, torch.complex128, (nw,))
+        self._check(self._lib.lo_residual_apply(self._h, nw, _ptr(energy), _ptr(pred), float(scale), float(shift),
+                                                _ptr(out)))
+        return out
+
     def residual_features(self, factors: Factors, theta, x=None):
-        """x [nw][n][3] float32 from walker-major theta [nw][M][n]."""
+        """x [nw][n][4] float32 from walker-major theta [nw][M][n]."""
         import torch
         nw = theta.shape[0]
         _check_dev("theta", theta, torch.complex128, (nw, factors.M, factors.n_occ))
         if x is None:
-            x = torch.empty((nw, factors.n_occ, 3), dtype=torch.float32, device=theta.device)
-        _check_dev("x", x, torch.float32, (nw, factors.n_occ, 3))
+            x = torch.empty((nw, factors.n_occ, RESIDUAL_NFEAT), dtype=torch.float32, device=theta.device)
+        _check_dev("x", x, torch.float32, (nw, factors.n_occ, RESIDUAL_NFEAT))
         self._check(self._lib.lo_residual_features(self._h, factors.handle, nw, _ptr(theta), _ptr(x)))
         return x
 
@@ -563,7 +607,7 @@ class Context:
         import torch
         nw, n, _ = x.shape
         _check_dev("params", params, torch.float32, (self.residual_nparam(),))
-        _check_dev("x", x, torch.float32, (nw, n, 3))
+        _check_dev("x", x, torch.float32, (nw, n, RESIDUAL_NFEAT))
         if pred is None:
             pred = torch.empty((nw,), dtype=torch.float64, device=x.device)
         _check_dev("pred", pred, torch.float64, (nw,))
@@ -576,7 +620,7 @@ class Context:
         nw, n, _ = x.shape
         npar = self.residual_nparam()
         _check_dev("params", params, torch.float32, (npar,))
-        _check_dev("x", x, torch.float32, (nw, n, 3))
+        _check_dev("x", x, torch.float32, (nw, n, RESIDUAL_NFEAT))
         _check_dev("target", target, torch.float64, (nw,))
         if step > 0:
             _check_dev("adam_m", adam_m, torch.float32, (npar,))

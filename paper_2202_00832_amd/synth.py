@@ -158,6 +158,23 @@ def noisy_walkers(trial: np.ndarray, nw: int, sigma: float,
     return out
 
 
+def random_walks(trial: np.ndarray, n_walks: int, n_steps: int, step: float,
+                 rng: np.random.Generator) -> np.ndarray:
+    """Walkers along random walks from the trial, [n_steps][n_walks][M][n]
+    complex128: phi <- Q of QR(phi + step (Z1 + i Z2)) at every step (a
+    stand-in for the propagation, which is not built)."""
+    M, n = trial.shape
+    out = np.empty((n_steps, n_walks, M, n), dtype=np.complex128)
+    phi = np.repeat(trial[None].astype(np.complex128), n_walks, axis=0)
+    for k in range(n_steps):
+        z = rng.standard_normal(phi.shape) + 1j * rng.standard_normal(phi.shape)
+        phi = phi + step * z
+        for w in range(n_walks):
+            phi[w] = np.linalg.qr(phi[w])[0]
+        out[k] = phi
+    return out
+
+
 def random_orthogonal(n: int, rng: np.random.Generator) -> np.ndarray:
     """Haar-ish random real orthogonal n x n matrix (used to delocalize a trial)."""
     q, r = np.linalg.qr(rng.standard_normal((n, n)))

@@ -86,6 +86,21 @@ def test_validation_errors_need_no_device(lib):
         assert lib.local_energy_hr(h, fake, 0, None, None, 0, None) == L.LO_OK            # empty batch
         assert lib.lo_hr_info(None, None, None, None) == L.LO_EINVAL
         assert lib.lo_hr_destroy(None) == L.LO_OK
+        # allocation-free LO energy: the same checks before any device work
+        assert lib.local_energy_lo_noalloc(h, None, 4, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_lo_noalloc(None, fake, 4, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_lo_noalloc(h, fake, 4, fake, None, 9, 0, fake) == L.LO_EINVAL
+        # learned residual: targets, corrected energies, gradient set-up
+        assert lib.lo_residual_target(h, 4, fake, fake, 0.0, 0.0, fake) == L.LO_EINVAL      # scale 0
+        assert lib.lo_residual_target(h, 4, fake, fake, 0.0, math.inf, fake) == L.LO_EINVAL
+        assert lib.lo_residual_target(h, 4, None, fake, 0.0, 1.0, fake) == L.LO_EINVAL
+        assert lib.lo_residual_target(h, -1, fake, fake, 0.0, 1.0, fake) == L.LO_EINVAL
+        assert lib.lo_residual_target(h, 0, None, None, 0.0, 1.0, None) == L.LO_OK
+        assert lib.lo_residual_apply(h, 4, None, None, 1.0, 0.0, fake) == L.LO_EINVAL
+        assert lib.lo_residual_apply(h, 4, fake, None, math.nan, 0.0, fake) == L.LO_EINVAL
+        assert lib.lo_residual_apply(h, 0, None, None, 1.0, 0.0, None) == L.LO_OK
+        assert lib.lo_residual_prepare(h, None, 3, fake, fake, None) == L.LO_EINVAL
+        assert lib.lo_residual_features(h, None, 4, fake, fake) == L.LO_EINVAL
     finally:
         assert lib.lo_destroy(h) == L.LO_OK
     assert lib.lo_destroy(None) == L.LO_OK

@@ -115,3 +115,71 @@ def test_bound_mutant_is_rejected(mutant):
     d = abs(sum(E.e2_lo(fac, theta)) - sum(E.e2_lo(exact, theta)))
     b = mutant(fac, theta)
     assert not (d <= b and d >= 0.5 * b)
+
+
+# ---------------------------------------------------------------------------
+# the learned residual's fourth feature: the gradient of the dropped energy
+# ---------------------------------------------------------------------------
+
+def _grad_mutants():
+    from oracle import residual as R
+
+    def no_transposed_term(lbar, fac, trial):
+        n = lbar.shape[1]
+        full = E.expand_upper(fac, n)
+        g = np.zeros((n, trial.shape[0]))
+        for (i, j), (Ub, Vb, _) in full.items():
+            D = E.pair_block(lbar, i, j) - Ub @ Vb
+            g[i] += 4.0 * D @ trial[:, j] - 2.0 * D @ trial[:, j]    # A^[ji]^T taken as A^[ij]
+        return g
+
+    def exchange_sign(lbar, fac, trial):
+        n = lbar.shape[1]
+        full = E.expand_upper(fac, n)
+        D = {k: E.pair_block(lbar, *k) - v[0] @ v[1] for k, v in full.items()}
+        g = np.zeros((n, trial.shape[0]))
+        for i in range(n):
+            for j in range(n):
+                g[i] += 2.0 * (D[(i, j)] + D[(j, i)].T) @ trial[:, j] + (D[(j, i)] + D[(i, j)].T) @ trial[:, j]
+        return g
+
+    def kept_not_dropped(lbar, fac, trial):
+        n = lbar.shape[1]
+        full = E.expand_upper(fac, n)
+        g = np.zeros((n, trial.shape[0]))
+        for i in range(n):
+            for j in range(n):
+                A, B = full[(i, j)], full[(j, i)]
+                Aij, Aji = A[0] @ A[1], B[0] @ B[1]
+                g[i] += 2.0 * (Aij + Aji.T) @ trial[:, j] - (Aji + Aij.T) @ trial[:, j]
+        return g
+
+    return [R.dropped_energy_gradient, no_transposed_term, exchange_sign, kept_not_dropped]
+
+
+def test_dropped_energy_gradient_mutants_fail_central_differences():
+    """On a random (non-symmetric-pair) system every planted gradient mistake
+    disagrees with the central difference of E_HR - E_LO; the reference
+    gradient (first in the list) agrees."""
+    rng = np.random.default_rng(17)
+    M, n = 10, 3
+    chol = synth.random_symmetric_cholesky(M, 12, rng)
+    trial = np.linalg.qr(rng.standard_normal((M, n)))[0]
+    lbar = E.half_rotate(chol, trial)
+    fac = E.lo_compress(lbar, 0.05, pairs="upper")
+    direction = rng.standard_normal(M)
+    results = []
+    for fn in _grad_mutants():
+        g = fn(lbar, fac, trial)
+        ok = True
+        for i in range(n):
+            tp, tm = trial.astype(complex), trial.astype(complex)
+            tp[:, i] += 1e-3 * direction
+            tm[:, i] -= 1e-3 * direction
+            dp = sum(E.e2_hr_eri(lbar, tp)) - sum(E.e2_lo(fac, tp))
+            dm = sum(E.e2_hr_eri(lbar, tm)) - sum(E.e2_lo(fac, tm))
+            fd = (dp - dm) / 2e-3
+            ok &= abs(fd - g[i] @ direction) <= 1e-9 * max(1.0, np.abs(g[i]).sum())
+        results.append(bool(ok))
+    assert results[0] is True
+    assert not any(results[1:]), results

@@ -2,18 +2,24 @@
 
 The gradient is pinned by central finite differences, the forward pass by
 networks whose output has a closed form, and the optimiser by the known first
-step of Adam (bias-corrected, the update is -lr * sign(g) up to eps).
+step of Adam (bias-corrected, the update is -lr * sign(g) up to eps).  The
+fourth feature's gradient of the dropped energy is pinned by central
+differences of the half-rotated ERI and LO energies themselves (both are
+quadratic in Q, so the difference quotient is exact up to rounding), and by
+the first-order prediction of the dropped energy of walkers near the trial.
 """
 import numpy as np
 import pytest
 
+from oracle import energy as E
 from oracle import residual as R
+from paper_2202_00832_amd import synth
 
 
 def _rand_case(seed, nw=5, n=4):
     rng = np.random.default_rng(seed)
     x = np.stack([rng.integers(1, 9, (nw, n)).astype(float), rng.uniform(0, 1e-3, (nw, n)),
-                  rng.uniform(0.5, 2.0, (nw, n))], axis=-1)
+                  rng.uniform(0.5, 2.0, (nw, n)), rng.normal(0, 1e-3, (nw, n))], axis=-1)
     p = R.init_params(x, seed=seed)
     q = R.unpack(p)
     q["b1"][...] = rng.normal(0, 0.1, R.WIDTH)
@@ -24,7 +30,7 @@ def _rand_case(seed, nw=5, n=4):
 
 
 def test_parameter_count_and_packing():
-    assert R.NPARAM == 128 * 3 + 128 + 128 * 128 + 128 + 128 + 1 + 3 + 3
+    assert R.NPARAM == 128 * 4 + 128 + 128 * 128 + 128 + 128 + 1 + 4 + 4
     p = np.arange(R.NPARAM, dtype=float)
     assert np.array_equal(R.pack(R.unpack(p)), p)
 
@@ -89,10 +95,64 @@ def test_features_of_unit_columns():
     theta[:, 2] = 0.5 + 0.5j
     ranks = np.array([[1, 2, 0], [2, 3, 1], [0, 1, 4]])
     disc = np.array([[0.1, 0.0, 0.2], [0.0, 0.3, 0.0], [0.2, 0.0, 0.0]])
-    x = R.features(ranks, disc, theta)
+    grad = np.zeros((n, M))
+    grad[0, 0], grad[0, 1] = 2.0, 5.0     # Re(2 * 3 + 5 * 4i) = 6
+    grad[1, 2] = -1.5
+    grad[2, :] = 1.0                      # Re(sum (0.5 + 0.5i)) = M / 2
+    x = R.features(ranks, disc, theta, grad)
     assert np.allclose(x[:, 0], [3, 6, 5])
     assert np.allclose(x[:, 1], [0.3, 0.3, 0.2])
     assert np.allclose(x[:, 2], [5.0, 1.0, np.sqrt(M * 0.5)])
+    assert np.allclose(x[:, 3], [6.0, -1.5, M * 0.5])
+
+
+def _dropped(lbar, fac, theta):
+    return sum(E.e2_hr_eri(lbar, theta)) - sum(E.e2_lo(fac, theta))
+
+
+@pytest.fixture(scope="module")
+def chain_case():
+    s = synth.make_system(synth.CHAIN_SMALL, nw=1)
+    lbar = E.half_rotate(s.chol, s.trial)
+    fac = E.lo_compress(lbar, 1e-3, pairs="upper")
+    return s, lbar, fac, R.dropped_energy_gradient(lbar, fac, s.trial)
+
+
+def test_dropped_energy_gradient_matches_central_differences(chain_case):
+    s, lbar, fac, g = chain_case
+    M, n = s.trial.shape
+    rng = np.random.default_rng(11)
+    base = s.trial.astype(complex)
+    for i in (0, 3, n - 1):
+        for direction in (rng.standard_normal(M), 1j * rng.standard_normal(M)):
+            h = 1e-3
+            tp, tm = base.copy(), base.copy()
+            tp[:, i] += h * direction
+            tm[:, i] -= h * direction
+            fd = (_dropped(lbar, fac, tp) - _dropped(lbar, fac, tm)) / (2 * h)
+            want = g[i] @ direction
+            assert abs(fd - want) <= 1e-9 * max(1.0, np.abs(g[i]).sum()), (i, fd, want)
+    # the gradient of the dropped part is small but not zero at eps = 1e-3
+    assert 0 < np.abs(g).max() < 1e-1
+
+
+def test_dropped_energy_first_order_prediction(chain_case):
+    """sum_i Re(g_i . (theta_i - psi_i)) predicts the change of the dropped
+    energy from the trial to a nearby walker, with a remainder quadratic in
+    the distance (halving the noise quarters it)."""
+    s, lbar, fac, g = chain_case
+    M, n = s.trial.shape
+    d0 = _dropped(lbar, fac, s.trial.astype(complex)).real
+    rem = []
+    for sigma in (1e-3, 5e-4):
+        rng = np.random.default_rng(5)
+        w = synth.noisy_walkers(s.trial, 1, sigma, rng)[0]
+        th = E.green_theta(s.trial, w)[0]
+        first = sum(np.real(g[i] @ (th[:, i] - s.trial[:, i])) for i in range(n))
+        change = _dropped(lbar, fac, th).real - d0
+        assert abs(first) > 5 * abs(change - first)
+        rem.append(abs(change - first))
+    assert 0.15 < rem[1] / rem[0] < 0.35
 
 
 def test_training_reduces_the_loss():
