@@ -220,10 +220,22 @@ def few_walker_study(torch, ctx, lbar, trial_d, phi_d, factors, nw=16):
     return out
 
 
-def precision_study(torch, lofqmc, synth, steps):
-    """Full route with the exchange contraction in FP64, FP32 and split BF16 on
-    the 500-site chain (48 orbitals, 1024 walkers): time per step and error of
-    each walker's energy against the FP64 result of the same inputs."""
+def _err_stats(e, ref):
+    """Per-walker errors of E2 = E_J + E_K against the FP64 result."""
+    d = np.abs(e.sum(axis=1) - ref.sum(axis=1))
+    rel = d / np.maximum(np.abs(ref.sum(axis=1)), 1e-300)
+    return {"max_abs_dE_Ha": float(d.max()), "mean_abs_dE_Ha": float(d.mean()),
+            "p99_abs_dE_Ha": float(np.percentile(d, 99)), "median_abs_dE_Ha": float(np.median(d)),
+            "max_rel_dE": float(rel.max()), "walkers_within_1e-5_Ha": round(float(np.mean(d <= 1e-5)), 4)}
+
+
+def precision_study(torch, lofqmc, synth, steps, eps=1e-4):
+    """The full route and the LO route (eps = 1e-4) with their contractions in
+    FP64, FP32 and split BF16 on the 500-site chain (48 orbitals, 1024
+    walkers): time per call and error of each walker's energy against the
+    FP64 result of the same route and inputs.  The FP64 results equal the CPU
+    reference to 1e-9 Ha per walker (the parity tests), so these errors are
+    the errors against the reference to within 1e-9 Ha."""
     cfg = synth.CHAIN_PRECISION
     log("precision study: generating %s" % cfg.name)
     system = synth.make_system(cfg)
@@ -237,29 +249,32 @@ def precision_study(torch, lofqmc, synth, steps):
     theta, logov, info = ctx.green_theta(trial_d, phi_d)
     energy = torch.empty((nw, 2), dtype=torch.complex128, device="cuda")
     ref = ctx.local_energy_full(lbar, theta, info, precision=lofqmc.LO_FP64).cpu().numpy()
-    out = {"workload": cfg.name, "M": M, "n_occ": n, "n_chol": X, "walkers": nw, "runs": {}}
+    fac = ctx.build_lo_factors(lbar, eps)
+    finfo = fac.info()
+    ref_lo = ctx.local_energy_lo(fac, theta, info, precision=lofqmc.LO_FP64).cpu().numpy()
+    out = {"workload": cfg.name, "M": M, "n_occ": n, "n_chol": X, "walkers": nw,
+           "error_reference": "the FP64 result of the same route (equal to the CPU reference within 1e-9 Ha)",
+           "runs": {}, "lo": {"epsilon": eps, "mean_rank": float(finfo["ranks"].mean()),
+                              "lo_fp64_vs_full_fp64": _err_stats(ref_lo, ref), "runs": {}}}
     names = {lofqmc.LO_FP64: "fp64", lofqmc.LO_FP32: "fp32", lofqmc.LO_BF16X3: "bf16x3"}
     for p in (lofqmc.LO_FP64, lofqmc.LO_FP32, lofqmc.LO_BF16X3):
         def step(ev, p=p):
             ctx.local_energy_full(lbar, theta, info, energy, precision=p)
         tot, _, kern = time_route(torch, ctx, step, steps, 1, ["a"])
         e = ctx.local_energy_full(lbar, theta, info, precision=p).cpu().numpy()
-        d = np.abs(e.sum(axis=1) - ref.sum(axis=1))
         dk = np.abs(e[:, 1] - ref[:, 1])
-        rel = d / np.maximum(np.abs(ref.sum(axis=1)), 1e-300)
         r = {"ms_per_call": round(tot / steps, 3), "walker_energies_per_s": round(nw / (tot / steps * 1e-3), 1),
-             "max_abs_dE_Ha": float(d.max()), "mean_abs_dE_Ha": float(d.mean()),
-             "p99_abs_dE_Ha": float(np.percentile(d, 99)), "max_rel_dE": float(rel.max()),
-             "max_abs_dEK_Ha": float(dk.max()),
+             **_err_stats(e, ref), "max_abs_dEK_Ha": float(dk.max()),
              "kernel_us": {k: round(t / c * 1e3, 1) for k, (c, t) in kern.items()}}
         # rooflines of the contraction kernels against the peak of the dtype
-        # they run in (algorithmic flops on unpadded sizes): the exchange
-        # contraction T = Lbar^T theta (real x complex, 4 M n^2 per walker and
-        # vector; split BF16 runs it as three BF16 products) and the FP64
-        # Coulomb traces (4 M n per walker and vector)
+        # they run in, on the method's own flops (unpadded sizes, each product
+        # counted once also where split BF16 runs it as three BF16 products):
+        # the exchange contraction T = Lbar^T theta (real x complex, 4 M n^2 per
+        # walker and vector) and the FP64 Coulomb traces (4 M n per walker and
+        # vector)
         contraction = 4.0 * M * n * n * X * nw
         spec = {"energy_full_kernel": (contraction + 8.0 * n * n * X * nw, PEAK_FP64_TFLOPS, "fp64"),
-                "exchange_lp_kernel": ((3.0 if p == lofqmc.LO_BF16X3 else 1.0) * contraction,
+                "exchange_lp_kernel": (contraction,
                                        PEAK_BF16_TFLOPS if p == lofqmc.LO_BF16X3 else PEAK_FP32_TFLOPS,
                                        "bf16" if p == lofqmc.LO_BF16X3 else "fp32"),
                 "coulomb_trace_kernel": (4.0 * M * n * X * nw, PEAK_FP64_TFLOPS, "fp64")}
@@ -272,7 +287,22 @@ def precision_study(torch, lofqmc, synth, steps):
                                    "us_per_launch": round(kern[k][1] / kern[k][0] * 1e3, 2),
                                    "algorithmic_flops_per_launch": flops}
         out["runs"][names[p]] = r
-        log("precision %s: %.3f ms/call, max |dE| %.2e Ha" % (names[p], r["ms_per_call"], r["max_abs_dE_Ha"]))
+        log("precision full %s: %.3f ms/call, max |dE| %.2e Ha, mean %.2e, %.1f %% of walkers within 1e-5 Ha"
+            % (names[p], r["ms_per_call"], r["max_abs_dE_Ha"], r["mean_abs_dE_Ha"],
+               100 * r["walkers_within_1e-5_Ha"]))
+        # LO route at eps, same precision
+        def step_lo(ev, p=p):
+            ctx.local_energy_lo(fac, theta, info, energy, precision=p)
+        tot, _, kern = time_route(torch, ctx, step_lo, max(steps, 20), 3, ["a"])
+        e = ctx.local_energy_lo(fac, theta, info, precision=p).cpu().numpy()
+        r = {"ms_per_call": round(tot / max(steps, 20), 4),
+             "walker_energies_per_s": round(nw / (tot / max(steps, 20) * 1e-3), 1), **_err_stats(e, ref_lo),
+             "kernel_us": {k: round(t / c * 1e3, 1) for k, (c, t) in kern.items()}}
+        out["lo"]["runs"][names[p]] = r
+        log("precision LO %s: %.4f ms/call, max |dE| %.2e Ha, mean %.2e, %.1f %% of walkers within 1e-5 Ha"
+            % (names[p], r["ms_per_call"], r["max_abs_dE_Ha"], r["mean_abs_dE_Ha"],
+               100 * r["walkers_within_1e-5_Ha"]))
+    fac.close()
     ctx.close()
     return out
 
@@ -348,11 +378,21 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
     return out
 
 
+def _orthonormalize(torch, a):
+    """Orthonormal columns spanning those of each a[w] (Cholesky QR,
+    a = Q L^H with L L^H = a^H a).  Q differs from a Householder QR's only by
+    column phases, which the circular walk noise does not see."""
+    ah = a.conj().transpose(-1, -2).contiguous()
+    L = torch.linalg.cholesky(ah @ a)
+    return torch.linalg.solve_triangular(L.conj().transpose(-1, -2).contiguous(), a, upper=True,
+                                         left=False).contiguous()
+
+
 def residual_study(torch, lofqmc, synth, n_train=20480, n_test=2048, steps=2000, step_sigmas=(0.005, 0.02),
                    sketch=24):
     """Learned correction of the LO energy on the 800-site chain (100 orbitals
     per spin, 2048 walkers, eps = 1e-3): LO factors from the randomized SVD,
-    exact energies from the half-rotated ERI route, walker pairs along random
+    exact energies from the full (Cholesky) route, walker pairs along random
     walks from the trial (walk steps 0.005 and 0.02), training on the GPU,
     held-out error of plain LO, of LO plus a constant offset (the training mean
     of the dropped energy), of LO plus the first-order term alone (a
@@ -380,18 +420,14 @@ def residual_study(torch, lofqmc, synth, n_train=20480, n_test=2048, steps=2000,
     t0 = time.perf_counter()
     ctx.residual_prepare(f, lbar, trial_d)
     prep_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    hr = ctx.build_hr_eri(lbar)
-    torch.cuda.synchronize()
-    hr_s = time.perf_counter() - t0
-    exact = lambda th, inf: ctx.local_energy_hr(hr, th, inf)  # noqa: E731
+    exact = lambda th, inf: ctx.local_energy_full(lbar, th, inf)  # noqa: E731
     ranks = f.info()["ranks"]
-    log("residual study: randomized LO factors %.2f s (<K> = %.3f), gradient set-up %.2f s, pair blocks %.1f GB %.2f s"
-        % (factor_s, ranks.mean(), prep_s, hr.bytes / 1e9, hr_s))
+    log("residual study: randomized LO factors %.2f s (<K> = %.3f), gradient set-up %.2f s"
+        % (factor_s, ranks.mean(), prep_s))
     out = {"workload": cfg.name, "M": M, "n_occ": n, "n_chol": base.n_chol, "epsilon": eps,
            "factors": "randomized SVD, sketch %d, 2 power steps" % sketch, "factor_build_s": round(factor_s, 2),
            "gradient_setup_s": round(prep_s, 2), "mean_rank": float(ranks.mean()),
-           "exact_route": "half-rotated ERI (Eq. 17)", "features": "sum_j K_ij, sum_j m_ij, ||theta_i||, "
+           "exact_route": "full Cholesky route (Eq. 16)", "features": "sum_j K_ij, sum_j m_ij, ||theta_i||, "
            "Re(g_i . theta_i) with g the gradient of E_HR - E_LO at the trial", "walks": {}}
     rms = lambda d: float(np.sqrt(np.mean(d ** 2)) * 1e3)  # noqa: E731
     mx = lambda d: float(np.abs(d).max() * 1e3)  # noqa: E731
@@ -406,7 +442,7 @@ def residual_study(torch, lofqmc, synth, n_train=20480, n_test=2048, steps=2000,
         for _ in range(nsteps):
             z = torch.complex(torch.randn(phi.shape, dtype=torch.float64, device="cuda", generator=gen),
                               torch.randn(phi.shape, dtype=torch.float64, device="cuda", generator=gen))
-            phi = torch.linalg.qr(phi + step_sigma * z)[0].contiguous()
+            phi = _orthonormalize(torch, phi + step_sigma * z)
             theta, _, info = ctx.green_theta(trial_d, phi)
             EF.append(exact(theta, info))
             EL.append(ctx.local_energy_lo(f, theta, info))
@@ -464,7 +500,6 @@ def residual_study(torch, lofqmc, synth, n_train=20480, n_test=2048, steps=2000,
             rec["corrected_lo_ms_per_call"] = round(e0.elapsed_time(e1) / reps, 3)
         out["walks"]["%g" % step_sigma] = rec
         del x, ef, el, xtr, xte
-    hr.close()
     f.close()
     ctx.close()
     return out

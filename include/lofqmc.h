@@ -47,7 +47,11 @@ enum lo_status {
  * LO_THETA_ORBITAL_MAJOR: orbital-major complex [n_occ][M][nw] (walkers
  * contiguous), the layout the LO energy multiplies directly. */
 enum lo_flags {
-  LO_THETA_ORBITAL_MAJOR = 1u
+  LO_THETA_ORBITAL_MAJOR = 1u,
+  /* local_energy_lo: E_J from the FP64 Cholesky traces Tr(Lbar_g^T theta)
+   * (Eq. 16, exact) instead of the LO pair sums; E_K stays LO.  Needs the
+   * lbar argument and walker-major theta. */
+  LO_EXACT_COULOMB = 2u
 };
 
 /* Arithmetic of the energy contractions.  Reduced precision applies to the
@@ -211,7 +215,8 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
  *               FP32 or split-BF16 copy in the context workspace and support
  *               nw <= 65535 and n_chol <= 65535
  *   energy    : complex [nw][2] (output) = (E_J, E_K) per walker
- * flags must be 0.  Supports n_occ <= 64 (LO_FP64, LO_BF16X3) or <= 96 (LO_FP32). */
+ * flags must be 0.  Supports n_occ <= 112 (LO_FP64), <= 96 (LO_FP32) or <= 64
+ * (LO_BF16X3). */
 int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int64_t nw,
                       const double* lbar, const double* theta, const int32_t* info,
                       int precision, unsigned flags, double* energy);
@@ -224,14 +229,17 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
  *   theta   : complex [nw][M][n_occ], or [n_occ][M][nw] with flags
  *             LO_THETA_ORBITAL_MAJOR (both are read in place)
  *   info    : int32 [nw] or NULL
+ *   lbar    : NULL, or with LO_EXACT_COULOMB the [n_chol][M][n_occ] vectors
+ *             the factors were built from (E_J then comes from their traces)
  *   energy  : complex [nw][2] (output) = (E_J, E_K)
  * precision: LO_FP64, LO_FP32 or LO_BF16X3 (enum lo_precision); the reduced
  * ones need walker-major theta (LO_EUNSUPPORTED otherwise), nw <= 65535 and
  * n_occ <= 96 (LO_FP32) or <= 64 (LO_BF16X3),
  * and rewrite theta into a padded FP32 or split-BF16 copy in the context
- * workspace first.  flags may hold LO_THETA_ORBITAL_MAJOR only. */
+ * workspace first.  flags may hold LO_THETA_ORBITAL_MAJOR or LO_EXACT_COULOMB
+ * (not both). */
 int local_energy_lo(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const double* theta,
-                    const int32_t* info, int precision, unsigned flags, double* energy);
+                    const int32_t* info, int precision, unsigned flags, const double* lbar, double* energy);
 
 /* local_energy_lo without any device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses that
@@ -239,7 +247,8 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const do
  * the intermediates live in a fixed scratch array of LO_NOALLOC_SCRATCH_BYTES
  * (128 MiB) that every GPU the library runs on holds until the process ends,
  * instead of the context workspace.  A call needs
- *   16 nw n_out_rows + 32 nw n_chunks (+ the reduced-precision theta copy)
+ *   16 nw n_out_rows + 32 nw n_chunks (+ the reduced-precision theta copy,
+ *   + the Cholesky-trace partials of LO_EXACT_COULOMB)
  * bytes, each part rounded up to 256 (n_out_rows is the orbital-grouped row
  * count of the factors, about 11 k at M = 400, n_occ = 60, eps = 1e-5, so
  * about 700 walkers fit per call); a larger call returns LO_EUNSUPPORTED
@@ -249,7 +258,28 @@ int local_energy_lo(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const do
  * byte they read within the call, so no clearing is needed. */
 #define LO_NOALLOC_SCRATCH_BYTES (128ull << 20)
 int local_energy_lo_noalloc(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const double* theta,
-                            const int32_t* info, int precision, unsigned flags, double* energy);
+                            const int32_t* info, int precision, unsigned flags, const double* lbar, double* energy);
+
+/* ------------------------------------------------ localization (set-up)
+ *
+ * Foster-Boys localization of the occupied trial orbitals (Sec. 3: the
+ * orbitals are localized before the pair blocks are compressed, so that each
+ * pair block has low numerical rank).  Maximises
+ *   B = sum_i sum_d (C[:, i]^T diag(x_d) C[:, i])^2
+ * over orthogonal rotations of the columns by Jacobi sweeps: pairs i < j in
+ * row order, each rotated by the angle that maximises its part of B
+ * (4t = atan2(2 sum_d c_d h_d, sum_d (h_d^2 - c_d^2)), h_d half the difference
+ * of the two centroids, c_d the cross term), until a sweep raises B by at
+ * most tol * B or max_sweeps sweeps have run.
+ *   positions : device double [n_pos][M], the diagonal of each position
+ *               operator in the basis (n_pos <= 3; the chain: x = p)
+ *   orbitals  : device double [M][n_occ], orthonormal columns; replaced by
+ *               the localized orbitals (same span)
+ *   stats     : host double [3] or NULL: B before, B after, sweeps run
+ * Requires n_pos * n_occ^2 <= 15360 (the rotated matrices stay in LDS: up to
+ * 112 orbitals with one position operator, 71 with three).  Synchronous. */
+int lo_localize_boys(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_pos, const double* positions, double* orbitals,
+                     int max_sweeps, double tol, double* stats);
 
 /* ------------------------------------------------ half-rotated ERI route
  *

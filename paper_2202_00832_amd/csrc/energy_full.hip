@@ -3,50 +3,64 @@
 // For walker w and Cholesky vector g:  T = Lbar_g^T theta_w  (n x n complex),
 //   Coulomb  c_{wg} = Tr T,          E_J[w] = 2 sum_g c_{wg}^2
 //   exchange x_{wg} = Tr(T T),       E_K[w] = -sum_g x_{wg}.
-// T is never written to memory.  Each wave owns one walker and holds the
-// whole T of the current g in MFMA accumulators, as 16x16 blocks.  For an
-// off-diagonal block pair (I < J) the wave accumulates T[I,J] = Lbar^T theta
-// and the transposed block (T^T)[I,J] = theta^T Lbar: with the same operand
-// fragments both land with every element's exchange partner T_ji in the same
-// lane and register as T_ij, so sum_ij T_ij T_ji is a lane-local product.
-// Diagonal blocks are transposed through LDS.  The Lbar tile of each K-step
-// is staged once in LDS (double-buffered) and shared by the four walkers of
-// the workgroup.  Per-chunk partial sums are reduced in a fixed order by a
-// second kernel, so results are deterministic.
+// T is never written to memory.  T is cut into 16x16 blocks; the block pairs
+// (I < J) and the diagonal blocks are dealt out over S = 2 P wave slices: the
+// two waves of a walker in a workgroup, times P passes (a second grid
+// dimension, P = 1 up to 64 orbitals).  For an off-diagonal block pair a wave
+// accumulates T[I,J] = Lbar^T theta and the transposed block
+// (T^T)[I,J] = theta^T Lbar: with the same operand fragments both land with
+// every element's exchange partner T_ji in the same lane and register as
+// T_ij, so sum_ij T_ij T_ji is a lane-local product.  Diagonal blocks are
+// transposed through LDS.  The Coulomb trace is summed by one wave per walker
+// straight from its operand fragments (each lane holds Lbar[r][i] and
+// theta[r][i] of the same r and i).  The Lbar tile of each K-step is staged
+// once in LDS (double-buffered) and shared by the four walkers of the
+// workgroup.  Per-(pass, chunk) partial sums are reduced in a fixed order by
+// a second kernel, so results are deterministic.
 #include "common.h"
 #include "kernels.h"
 
 namespace lofqmc {
 
-template <int NB>
+template <int NB, int P>
 struct FullCfg {
   static constexpr int NP = 16 * NB;
+  static constexpr int S = 2 * P;                       // wave slices per walker
   static constexpr int NPAIR = NB * (NB - 1) / 2;
-  static constexpr int NPH = (NPAIR + 1) / 2;          // off-diagonal pairs per half
-  static constexpr int NDH = (NB + 1) / 2;             // diagonal blocks per half
-  static constexpr int TILE = 16 * NP;                 // 16 rows of r, NP orbitals
+  static constexpr int NPS = (NPAIR + S - 1) / S;       // off-diagonal pairs per slice
+  static constexpr int NDS = (NB + S - 1) / S;          // diagonal blocks per slice
+  static constexpr int TILE = 16 * NP;                  // 16 rows of r, NP orbitals
   static constexpr int PER_THREAD = (TILE + 511) / 512;
 };
 
+// Passes per orbital-block count: the accumulators of one slice stay within
+// about 112 registers (3 block pairs and one diagonal block from 65 orbitals up).
+constexpr int full_passes(int NB) { return NB <= 4 ? 1 : (NB == 5 ? 2 : (NB == 6 ? 3 : 4)); }
+
 // 8 waves: walker slot ws = wave / 2 (four walkers per workgroup) and half
-// h = wave % 2; half h owns the off-diagonal pairs q with q % 2 == h and the
-// diagonal blocks I with I % 2 == h.
-template <int NB>
+// h = wave % 2; with pass p = blockIdx.y, slice sl = 2 p + h owns the
+// off-diagonal pairs q with q % S == sl and the diagonal blocks I with
+// I % S == sl.
+template <int NB, int P>
 __global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64_t X, int64_t nw, int64_t gchunk,
                                                              int nchunk, int64_t ngrp,
                                                              const double* __restrict__ lbar,
                                                              const double2* __restrict__ theta,
                                                              double* __restrict__ partial) {
-  using C = FullCfg<NB>;
+  using C = FullCfg<NB, P>;
   constexpr int NP = C::NP;
+  constexpr int S = C::S;
   __shared__ double sL[2][C::TILE];
-  __shared__ double2 sDiag[8][C::NDH][256];
-  __shared__ double2 sTr[8];
+  __shared__ double2 sDiag[8][C::NDS][256];
+  __shared__ double2 sK[8];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int ws = wv >> 1, h = wv & 1;
+  const int pass = (int)blockIdx.y;
+  const int sl = 2 * pass + h;
+  const bool coulomb = (sl == 0);
   const int lr = lane & 15, lk = lane >> 4;
   // XCD-aware order (workgroups go round-robin over 8 XCDs): the workgroups
   // of one XCD share a chunk of Cholesky vectors, so each Lbar tile is read
@@ -107,15 +121,16 @@ __global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64
     }
   };
 
-  d4 dRe[C::NPH > 0 ? C::NPH : 1], dIm[C::NPH > 0 ? C::NPH : 1];
-  d4 tRe[C::NPH > 0 ? C::NPH : 1], tIm[C::NPH > 0 ? C::NPH : 1];
-  d4 gRe[C::NDH], gIm[C::NDH];
+  d4 dRe[C::NPS > 0 ? C::NPS : 1], dIm[C::NPS > 0 ? C::NPS : 1];
+  d4 tRe[C::NPS > 0 ? C::NPS : 1], tIm[C::NPS > 0 ? C::NPS : 1];
+  d4 gRe[C::NDS], gIm[C::NDS];
+  double cr = 0.0, ci = 0.0;                       // Coulomb trace of the current g (this lane's share)
   double accJr = 0.0, accJi = 0.0, accKr = 0.0, accKi = 0.0;
   auto zero_acc = [&]() {
 #pragma unroll
-    for (int q = 0; q < C::NPH; ++q) { dRe[q] = d4zero(); dIm[q] = d4zero(); tRe[q] = d4zero(); tIm[q] = d4zero(); }
+    for (int q = 0; q < C::NPS; ++q) { dRe[q] = d4zero(); dIm[q] = d4zero(); tRe[q] = d4zero(); tIm[q] = d4zero(); }
 #pragma unroll
-    for (int q = 0; q < C::NDH; ++q) { gRe[q] = d4zero(); gIm[q] = d4zero(); }
+    for (int q = 0; q < C::NDS; ++q) { gRe[q] = d4zero(); gIm[q] = d4zero(); }
   };
   zero_acc();
 
@@ -123,11 +138,18 @@ __global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64
     double Lf[NB];
 #pragma unroll
     for (int I = 0; I < NB; ++I) Lf[I] = Lt[(4 * s + lk) * NP + 16 * I + lr];
+    if (coulomb) {
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        cr = fma(Lf[I], tf[I].x, cr);
+        ci = fma(Lf[I], tf[I].y, ci);
+      }
+    }
 #pragma unroll
     for (int I = 0; I < NB; ++I) {
-      if ((I & 1) == h) {
-        gRe[I >> 1] = mfma16(Lf[I], tf[I].x, gRe[I >> 1]);
-        gIm[I >> 1] = mfma16(Lf[I], tf[I].y, gIm[I >> 1]);
+      if (I % S == sl) {
+        gRe[I / S] = mfma16(Lf[I], tf[I].x, gRe[I / S]);
+        gIm[I / S] = mfma16(Lf[I], tf[I].y, gIm[I / S]);
       }
     }
     int q = 0;   // flattened pair index (static after unrolling)
@@ -135,11 +157,11 @@ __global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64
     for (int I = 0; I < NB; ++I) {
 #pragma unroll
       for (int J = I + 1; J < NB; ++J, ++q) {
-        if ((q & 1) == h) {
-          dRe[q >> 1] = mfma16(Lf[I], tf[J].x, dRe[q >> 1]);
-          dIm[q >> 1] = mfma16(Lf[I], tf[J].y, dIm[q >> 1]);
-          tRe[q >> 1] = mfma16(tf[I].x, Lf[J], tRe[q >> 1]);
-          tIm[q >> 1] = mfma16(tf[I].y, Lf[J], tIm[q >> 1]);
+        if (q % S == sl) {
+          dRe[q / S] = mfma16(Lf[I], tf[J].x, dRe[q / S]);
+          dIm[q / S] = mfma16(Lf[I], tf[J].y, dIm[q / S]);
+          tRe[q / S] = mfma16(tf[I].x, Lf[J], tRe[q / S]);
+          tIm[q / S] = mfma16(tf[I].y, Lf[J], tIm[q / S]);
         }
       }
     }
@@ -172,47 +194,44 @@ __global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64
 
     if (kt == nkt - 1) {
       // ---- epilogue for this g: Coulomb trace and exchange sum
-      double xr = 0.0, xi = 0.0, cr = 0.0, ci = 0.0;
+      double xr = 0.0, xi = 0.0;
 #pragma unroll
-      for (int q2 = 0; q2 < C::NPH; ++q2) {
-        if (2 * q2 + h < C::NPAIR) {
+      for (int q = 0; q < C::NPAIR; ++q) {
+        if (q % S == sl) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            xr += 2.0 * (dRe[q2][v] * tRe[q2][v] - dIm[q2][v] * tIm[q2][v]);
-            xi += 2.0 * (dRe[q2][v] * tIm[q2][v] + dIm[q2][v] * tRe[q2][v]);
+            xr += 2.0 * (dRe[q / S][v] * tRe[q / S][v] - dIm[q / S][v] * tIm[q / S][v]);
+            xi += 2.0 * (dRe[q / S][v] * tIm[q / S][v] + dIm[q / S][v] * tRe[q / S][v]);
           }
         }
       }
 #pragma unroll
-      for (int q = 0; q < C::NDH; ++q) {
-        if (2 * q + h < NB) {
+      for (int I = 0; I < NB; ++I) {
+        if (I % S == sl) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            sDiag[wv][q][(4 * v + lk) * 16 + lr] = make_double2(gRe[q][v], gIm[q][v]);
-            if (4 * v + lk == lr) { cr += gRe[q][v]; ci += gIm[q][v]; }
-          }
+          for (int v = 0; v < 4; ++v) sDiag[wv][I / S][(4 * v + lk) * 16 + lr] = make_double2(gRe[I / S][v], gIm[I / S][v]);
         }
       }
-      cr = wave_sum_lane0(cr);
-      ci = wave_sum_lane0(ci);
-      if (lane == 0) sTr[wv] = make_double2(cr, ci);
+      if (coulomb) {
+        const double tr = wave_sum_lane0(cr), ti = wave_sum_lane0(ci);
+        if (lane == 0) {
+          accJr += tr * tr - ti * ti;
+          accJi += 2.0 * tr * ti;
+        }
+        cr = 0.0;
+        ci = 0.0;
+      }
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < C::NDH; ++q) {
-        if (2 * q + h < NB) {
+      for (int I = 0; I < NB; ++I) {
+        if (I % S == sl) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double2 pv = sDiag[wv][q][lr * 16 + 4 * v + lk];
-            xr += gRe[q][v] * pv.x - gIm[q][v] * pv.y;
-            xi += gRe[q][v] * pv.y + gIm[q][v] * pv.x;
+            const double2 pv = sDiag[wv][I / S][lr * 16 + 4 * v + lk];
+            xr += gRe[I / S][v] * pv.x - gIm[I / S][v] * pv.y;
+            xi += gRe[I / S][v] * pv.y + gIm[I / S][v] * pv.x;
           }
         }
-      }
-      if (h == 0 && lane == 0) {
-        const double2 c0 = sTr[wv], c1 = sTr[wv + 1];
-        const double tr = c0.x + c1.x, ti = c0.y + c1.y;
-        accJr += tr * tr - ti * ti;
-        accJi += 2.0 * tr * ti;
       }
       accKr += xr;
       accKi += xi;
@@ -221,14 +240,15 @@ __global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64
     __syncthreads();
   }
 
-  // per-walker partial: the two halves are combined through LDS in a fixed order
+  // per-walker partial of this (pass, chunk): the two halves are combined
+  // through LDS in a fixed order; E_J comes from slice 0 only
   accKr = wave_sum_lane0(accKr);
   accKi = wave_sum_lane0(accKi);
-  if (lane == 0) sTr[wv] = make_double2(accKr, accKi);
+  if (lane == 0) sK[wv] = make_double2(accKr, accKi);
   __syncthreads();
   if (wok && h == 0 && lane == 0) {
-    const double2 k0 = sTr[wv], k1 = sTr[wv + 1];
-    double* out = partial + ((size_t)chunk * nw + w) * 4;
+    const double2 k0 = sK[wv], k1 = sK[wv + 1];
+    double* out = partial + (((size_t)pass * nchunk + chunk) * nw + w) * 4;
     out[0] = 2.0 * accJr;
     out[1] = 2.0 * accJi;
     out[2] = -(k0.x + k1.x);
@@ -266,6 +286,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t nw, int nc
 template <int NB>
 static hipError_t launch_full_nb(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* lbar,
                                  const double* theta, double* partial, int nchunk) {
+  constexpr int P = full_passes(NB);
   const int64_t ngrp = (nw + 3) / 4;
   const int64_t gchunk = (X + nchunk - 1) / nchunk;
   // grid covers every (group, chunk); the XCD-aware order may leave a few
@@ -277,10 +298,12 @@ static hipError_t launch_full_nb(hipStream_t s, int M, int n, int64_t X, int64_t
     const int64_t slots = per_xcd_chunks * ((ngrp + xcds_per_chunk - 1) / xcds_per_chunk);
     grid = 8 * slots;
   }
-  hipLaunchKernelGGL(energy_full_kernel<NB>, dim3((unsigned)grid), dim3(512), 0, s, M, n, X, nw, gchunk, nchunk,
-                     ngrp, lbar, (const double2*)theta, partial);
+  hipLaunchKernelGGL((energy_full_kernel<NB, P>), dim3((unsigned)grid, P), dim3(512), 0, s, M, n, X, nw, gchunk,
+                     nchunk, ngrp, lbar, (const double2*)theta, partial);
   return hipGetLastError();
 }
+
+int full_num_passes(int n) { return full_passes((n + 15) / 16); }
 
 int full_num_chunks(int64_t X, int64_t nw) {
   // one workgroup (8 waves) per compute unit (256 CUs): chunks of Cholesky
@@ -294,10 +317,16 @@ int full_num_chunks(int64_t X, int64_t nw) {
 hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* lbar,
                               const double* theta, double* partial, int nchunk) {
   if (nw <= 0) return hipSuccess;
-  if (n <= 16) return launch_full_nb<1>(s, M, n, X, nw, lbar, theta, partial, nchunk);
-  if (n <= 32) return launch_full_nb<2>(s, M, n, X, nw, lbar, theta, partial, nchunk);
-  if (n <= 48) return launch_full_nb<3>(s, M, n, X, nw, lbar, theta, partial, nchunk);
-  return launch_full_nb<4>(s, M, n, X, nw, lbar, theta, partial, nchunk);
+  switch ((n + 15) / 16) {
+    case 1: return launch_full_nb<1>(s, M, n, X, nw, lbar, theta, partial, nchunk);
+    case 2: return launch_full_nb<2>(s, M, n, X, nw, lbar, theta, partial, nchunk);
+    case 3: return launch_full_nb<3>(s, M, n, X, nw, lbar, theta, partial, nchunk);
+    case 4: return launch_full_nb<4>(s, M, n, X, nw, lbar, theta, partial, nchunk);
+    case 5: return launch_full_nb<5>(s, M, n, X, nw, lbar, theta, partial, nchunk);
+    case 6: return launch_full_nb<6>(s, M, n, X, nw, lbar, theta, partial, nchunk);
+    case 7: return launch_full_nb<7>(s, M, n, X, nw, lbar, theta, partial, nchunk);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_reduce_partials(hipStream_t s, int64_t nw, int nchunk, const double* partial, const int* info,

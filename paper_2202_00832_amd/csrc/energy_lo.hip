@@ -335,7 +335,7 @@ constexpr int LO_P2_WAVES = 4;
 __global__ __launch_bounds__(256) void lo_pass2_kernel(int64_t nw, const int* __restrict__ ent, int64_t nent,
                                                        const double* __restrict__ entw,
                                                        const double2* __restrict__ qbar,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, int with_j) {
   __shared__ double4 sRed[LO_P2_WAVES][64];
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int64_t w = (int64_t)blockIdx.x * 64 + lane;
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void lo_pass2_kernel(int64_t nw, const int* __
     xr += wt * (ql_j[e].x * qr_i[e].x - ql_j[e].y * qr_i[e].y);
     xi += wt * (ql_j[e].x * qr_i[e].y + ql_j[e].y * qr_i[e].x);
   }
-  sRed[q][lane] = make_double4(2.0 * jr, 2.0 * ji, -xr, -xi);
+  sRed[q][lane] = with_j ? make_double4(2.0 * jr, 2.0 * ji, -xr, -xi) : make_double4(0.0, 0.0, -xr, -xi);
   __syncthreads();
   if (q == 0 && w < nw) {
     double4 t = sRed[0][lane];
@@ -377,11 +377,11 @@ __global__ __launch_bounds__(256) void lo_pass2_kernel(int64_t nw, const int* __
 int lo_pass2_chunk() { return LO_P2_CHUNK * LO_P2_WAVES; }
 
 hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int64_t nent, const int* ent, const double* entw,
-                           const double* qbar, double* partial) {
+                           const double* qbar, double* partial, int with_j) {
   if (nw <= 0 || nent <= 0) return hipSuccess;
   dim3 grid((unsigned)((nw + 63) / 64), (unsigned)(nent / (LO_P2_CHUNK * LO_P2_WAVES)));
   hipLaunchKernelGGL(lo_pass2_kernel, grid, dim3(64 * LO_P2_WAVES), 0, s, nw, ent, nent, entw,
-                     (const double2*)qbar, partial);
+                     (const double2*)qbar, partial, with_j);
   return hipGetLastError();
 }
 

@@ -29,6 +29,8 @@ hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, int64_t w
                               double* work, const ProfHook* prof);
 
 int full_num_chunks(int64_t X, int64_t nw);
+// passes of the FP64 full route at n orbitals (partial rows = passes x chunks)
+int full_num_passes(int n);
 hipError_t launch_energy_full(hipStream_t s, int M, int n, int64_t X, int64_t nw, const double* lbar,
                               const double* theta, double* partial, int nchunk);
 // reduced-precision variant (precision LO_FP32 or LO_BF16X3): work is a device
@@ -60,8 +62,9 @@ int lo_orbital_block();
 // multiple of lo_pass2_chunk() (entries per partial slot),
 // partial [nent / lo_pass2_chunk()][nw][4]
 int lo_pass2_chunk();
+// with_j = 0 leaves the Coulomb part of every partial at zero (exchange only)
 hipError_t launch_lo_pass2(hipStream_t s, int64_t nw, int64_t nent, const int* ent, const double* entw,
-                           const double* qbar, double* partial);
+                           const double* qbar, double* partial, int with_j);
 
 // ---- reduced precision helpers (M padded to a multiple of 32, n to 16 NB)
 int lp_padded_m(int M);
@@ -175,6 +178,13 @@ hipError_t launch_md_pairs(hipStream_t s, const MdArgs& g, void* work, int nchun
 hipError_t launch_gemm_setup(hipStream_t s, int Mr, int Nc, int K, const double* A, int64_t a_m, int64_t a_k,
                              const double* B, int64_t b_k, int64_t b_n, double* C, int64_t c_m, int64_t c_n,
                              const int64_t* bases, int batch);
+// Foster-Boys localization of C [M][n] in place (D diagonal position
+// operators pos [D][M], D n^2 <= boys_max_lds_doubles()); stats_dev [3]:
+// functional before, after, sweeps run
+int boys_max_lds_doubles();
+size_t boys_workspace(int M, int n, int D);
+hipError_t launch_boys(hipStream_t s, int M, int n, int D, const double* pos, double* C, int max_sweeps, double tol,
+                       void* work, double* stats_dev);
 // orthonormal basis of the columns of each M x L block (L <= 64), in place
 hipError_t launch_orth(hipStream_t s, int M, int L, int nb, double* A, int64_t stride);
 // lbar[g][r][i] -> lbarT[i][g][r]

@@ -34,7 +34,7 @@ struct lo_ctx {
 };
 
 struct lo_factors {
-  int64_t M = 0, n = 0, total_rows = 0, n_out_rows = 0;
+  int64_t M = 0, n = 0, X = 0, total_rows = 0, n_out_rows = 0;   // X: Cholesky vectors the factors came from
   double* rows = nullptr;  // device [total_rows][M]
   float* rows32 = nullptr;   // device [total_rows][Mp] (reduced-precision copies, M padded to Mp)
   __bf16* rowsbf = nullptr;  // device [total_rows][2][Mp] (hi, lo)
@@ -81,7 +81,7 @@ struct lo_hr {
 
 namespace {
 
-constexpr int kMaxOcc = 64;     // FP64 full route
+constexpr int kMaxOcc = 64;     // split-BF16 energies
 constexpr int kMaxOccWide = 96;  // the reduced-precision energies
 constexpr int kMaxOccTheta = 112;  // green_theta
 
@@ -469,6 +469,7 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
   f = new lo_factors();
   f->M = M;
   f->n = n;
+  f->X = n_chol;
   f->ranks.assign(n * n, 0);
   f->first_dropped.assign(n * n, 0.0);
   f->discarded.assign(n * n, 0.0);
@@ -740,18 +741,21 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
 
 // Argument checks of the LO energy call and the scratch bytes it needs
 // (Q-bar intermediates, pass-2 partial sums, reduced-precision theta copy).
-int lo_energy_check(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const double* energy,
-                    int precision, unsigned flags, size_t* need) {
+int lo_energy_check(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const double* lbar,
+                    const double* energy, int precision, unsigned flags, size_t* need) {
   if (!ctx) return LO_EINVAL;
   ctx->err.clear();
   if (!f) return fail(ctx, LO_EINVAL, "null factors");
   if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
   if (precision != LO_FP64 && precision != LO_FP32 && precision != LO_BF16X3)
     return fail(ctx, LO_EINVAL, "unknown precision %d", precision);
-  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(unsigned)(LO_THETA_ORBITAL_MAJOR | LO_EXACT_COULOMB))
+    return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
+  const bool exact_j = (flags & LO_EXACT_COULOMB) != 0;
   if (precision != LO_FP64 && orbital_major)
     return fail(ctx, LO_EUNSUPPORTED, "reduced precision reads walker-major theta only");
+  if (exact_j && orbital_major) return fail(ctx, LO_EUNSUPPORTED, "LO_EXACT_COULOMB reads walker-major theta only");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
   if (precision != LO_FP64 && nw > 65535) return fail(ctx, LO_EUNSUPPORTED, "reduced precision: nw above 65535");
   if (precision != LO_FP64 && f->n > (precision == LO_FP32 ? kMaxOccWide : kMaxOcc))
@@ -760,12 +764,14 @@ int lo_energy_check(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
   *need = 0;
   if (nw == 0) return LO_OK;
   if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
+  if (exact_j && !lbar) return fail(ctx, LO_EINVAL, "LO_EXACT_COULOMB needs lbar");
   const int nchunk = (int)(f->n_ent / lofqmc::lo_pass2_chunk());
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
-  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
+  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)(nchunk + (exact_j ? 1 : 0)) * nw);
   const size_t tbytes =
       precision == LO_FP64 ? 0 : align256(lofqmc::lp_theta_bytes(precision, (int)f->M, (int)f->n, nw));
-  *need = qbytes + pbytes + tbytes;
+  const size_t cbytes = exact_j ? align256(lofqmc::coulomb_cpart_bytes((int)f->M, (int)f->n, f->X, nw)) : 0;
+  *need = qbytes + pbytes + tbytes + cbytes;
   return LO_OK;
 }
 
@@ -773,12 +779,17 @@ int lo_energy_check(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
 // `base` (lo_energy_check's byte count); every byte they read there is
 // written first by an earlier kernel of the same call.
 int lo_energy_enqueue(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const int32_t* info,
-                      int precision, unsigned flags, double* energy, char* base, const ProfScope& prof) {
+                      int precision, unsigned flags, const double* lbar, double* energy, char* base,
+                      const ProfScope& prof) {
   const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
+  const bool exact_j = (flags & LO_EXACT_COULOMB) != 0;
   const int64_t M = f->M, n = f->n;
   const int nchunk = (int)(f->n_ent / lofqmc::lo_pass2_chunk());
+  const int nrows = nchunk + (exact_j ? 1 : 0);
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)f->n_out_rows * nw);
-  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
+  const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nrows * nw);
+  const size_t tbytes =
+      precision == LO_FP64 ? 0 : align256(lofqmc::lp_theta_bytes(precision, (int)M, (int)n, nw));
   double* qbar = (double*)base;
   double* partial = (double*)(base + qbytes);
   if (precision == LO_FP64) {
@@ -797,15 +808,47 @@ int lo_energy_enqueue(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double
                                                 f->nblk_lp, f->tmax_lp, tlp, qbar));
   }
   prof.mark("lo_pass2_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->n_ent, f->d_ent, f->d_entw, qbar, partial));
+  HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass2(ctx->stream, nw, f->n_ent, f->d_ent, f->d_entw, qbar, partial,
+                                           exact_j ? 0 : 1));
+  if (exact_j) {
+    // E_J from the FP64 Cholesky traces (Eq. 16) as one more partial row
+    HIP_OR_FAIL(ctx, lofqmc::launch_coulomb_fp64(ctx->stream, (int)M, (int)n, f->X, nw, theta, lbar,
+                                                 base + qbytes + pbytes + tbytes, partial + (size_t)nchunk * nw * 4,
+                                                 prof.get()));
+  }
   prof.mark("reduce_partials_kernel");
-  HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nchunk, partial, info, energy));
+  HIP_OR_FAIL(ctx, lofqmc::launch_reduce_partials(ctx->stream, nw, nrows, partial, info, energy));
   return LO_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+int lo_localize_boys(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_pos, const double* positions, double* orbitals,
+                     int max_sweeps, double tol, double* stats) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (M <= 0 || n_occ <= 0 || n_pos <= 0) return fail(ctx, LO_EINVAL, "sizes must be positive");
+  if (n_occ > M) return fail(ctx, LO_EINVAL, "n_occ exceeds M");
+  if (max_sweeps < 1) return fail(ctx, LO_EINVAL, "max_sweeps must be >= 1");
+  if (!(tol >= 0.0) || std::isinf(tol)) return fail(ctx, LO_EINVAL, "tol must be finite and >= 0");
+  if (!positions || !orbitals) return fail(ctx, LO_EINVAL, "null array");
+  if (M > (1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "M above 2^24");
+  if (n_pos > 3 || n_pos * n_occ * n_occ > lofqmc::boys_max_lds_doubles())
+    return fail(ctx, LO_EUNSUPPORTED, "n_pos * n_occ^2 above %d (n_pos <= 3)", lofqmc::boys_max_lds_doubles());
+  const size_t wbytes = lofqmc::boys_workspace((int)M, (int)n_occ, (int)n_pos);
+  int rc = ensure_ws(ctx, wbytes);
+  if (rc) return rc;
+  double* dstats = (double*)((char*)ctx->ws + wbytes - align256(sizeof(double) * 4));
+  HIP_OR_FAIL(ctx, lofqmc::launch_boys(ctx->stream, (int)M, (int)n_occ, (int)n_pos, positions, orbitals, max_sweeps,
+                                       tol, ctx->ws, dstats));
+  double h[3] = {0.0, 0.0, 0.0};
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(h, dstats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+  if (stats) std::memcpy(stats, h, sizeof(h));
+  return LO_OK;
+}
 
 int build_lo_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar, double epsilon,
                      lo_factors** out) {
@@ -1278,9 +1321,8 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
   if (precision != LO_FP64 && precision != LO_FP32 && precision != LO_BF16X3)
     return fail(ctx, LO_EINVAL, "unknown precision %d", precision);
   if (flags != 0) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
-  if (n_occ > (precision == LO_FP32 ? kMaxOccWide : kMaxOcc))
-    return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d for this precision",
-                precision == LO_FP32 ? kMaxOccWide : kMaxOcc);
+  const int max_occ = precision == LO_FP64 ? kMaxOccTheta : (precision == LO_FP32 ? kMaxOccWide : kMaxOcc);
+  if (n_occ > max_occ) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d for this precision", max_occ);
   if (M > (1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "M above 2^24");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
   if (precision != LO_FP64 && (n_chol > 65535 || nw > 65535))
@@ -1289,8 +1331,10 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
   if ((n_chol > 0 && !lbar) || !theta || !energy) return fail(ctx, LO_EINVAL, "null array");
   // with no Cholesky vectors there are no chunks and the reduction writes zeros
   const int nchunk = n_chol > 0 ? lofqmc::full_num_chunks(n_chol, nw) : 0;
-  // reduced precision adds one chunk row for the FP64 Coulomb sums
-  const int nrows = (precision != LO_FP64 && n_chol > 0) ? nchunk + 1 : nchunk;
+  // FP64: one row per (pass, chunk); reduced precision adds one chunk row for
+  // the FP64 Coulomb sums
+  const int nrows = precision == LO_FP64 ? nchunk * lofqmc::full_num_passes((int)n_occ)
+                                         : (n_chol > 0 ? nchunk + 1 : nchunk);
   const size_t pbytes = align256(sizeof(double) * 4 * (size_t)std::max(nrows, 1) * nw);
   const size_t lbytes = (precision != LO_FP64 && n_chol > 0)
                             ? lofqmc::full_lp_workspace(precision, (int)M, (int)n_occ, n_chol, nw)
@@ -1316,20 +1360,20 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
 }
 
 int local_energy_lo(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const int32_t* info,
-                    int precision, unsigned flags, double* energy) {
+                    int precision, unsigned flags, const double* lbar, double* energy) {
   size_t need = 0;
-  int rc = lo_energy_check(ctx, f, nw, theta, energy, precision, flags, &need);
+  int rc = lo_energy_check(ctx, f, nw, theta, lbar, energy, precision, flags, &need);
   if (rc || nw == 0) return rc;
   rc = ensure_ws(ctx, need);
   if (rc) return rc;
   ProfScope prof(ctx);
-  return lo_energy_enqueue(ctx, f, nw, theta, info, precision, flags, energy, (char*)ctx->ws, prof);
+  return lo_energy_enqueue(ctx, f, nw, theta, info, precision, flags, lbar, energy, (char*)ctx->ws, prof);
 }
 
 int local_energy_lo_noalloc(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const int32_t* info,
-                            int precision, unsigned flags, double* energy) {
+                            int precision, unsigned flags, const double* lbar, double* energy) {
   size_t need = 0;
-  int rc = lo_energy_check(ctx, f, nw, theta, energy, precision, flags, &need);
+  int rc = lo_energy_check(ctx, f, nw, theta, lbar, energy, precision, flags, &need);
   if (rc || nw == 0) return rc;
   if (need > kNoAllocScratchBytes)
     return fail(ctx, LO_EUNSUPPORTED,
@@ -1339,7 +1383,7 @@ int local_energy_lo_noalloc(lo_ctx* ctx, const lo_factors* f, int64_t nw, const 
   rc = scratch_on_current_device(ctx, &base);
   if (rc) return rc;
   ProfScope prof(ctx, /*allow_record=*/false);
-  return lo_energy_enqueue(ctx, f, nw, theta, info, precision, flags, energy, (char*)base, prof);
+  return lo_energy_enqueue(ctx, f, nw, theta, info, precision, flags, lbar, energy, (char*)base, prof);
 }
 
 // ------------------------------------------------------ several systems

@@ -210,4 +210,137 @@ hipError_t launch_orth(hipStream_t s, int M, int L, int nb, double* A, int64_t s
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Foster-Boys localization of the occupied orbitals (set-up, Sec. 3): Jacobi
+// sweeps maximising B = sum_i sum_d (X_d[i][i])^2, X_d = C^T diag(x_d) C.
+// For the pair i < j (row order) with h_d = (X_d[i][i] - X_d[j][j]) / 2 and
+// c_d = X_d[i][j], the rotation i' = cs i + sn j, j' = -sn i + cs j by
+// 4t = atan2(2 sum_d c_d h_d, sum_d (h_d^2 - c_d^2)) maximises the pair's part
+// of B; every rotation is applied, columns of X_d first, then rows.  X lives in
+// LDS, the accumulated rotation (transposed, Ut[i][k] = U[k][i]) in global
+// memory.  One workgroup; every thread computes the angle from LDS.
+// ---------------------------------------------------------------------------
+constexpr int BOYS_LDS_DOUBLES = 15360;   // 120 KB: D n^2 <= 15360
+
+// X[d][i][j] = sum_r C[r][i] x_d[r] C[r][j]; one thread per (d, i, j)
+__global__ __launch_bounds__(256) void boys_project_kernel(int M, int n, int D, const double* __restrict__ C,
+                                                           const double* __restrict__ pos,
+                                                           double* __restrict__ X) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= D * n * n) return;
+  const int d = e / (n * n), i = (e / n) % n, j = e % n;
+  double s = 0.0;
+  for (int r = 0; r < M; ++r) s += C[(size_t)r * n + i] * pos[(size_t)d * M + r] * C[(size_t)r * n + j];
+  X[e] = s;
+}
+
+__global__ __launch_bounds__(256) void boys_jacobi_kernel(int n, int D, int max_sweeps, double tol,
+                                                          const double* __restrict__ Xg, double* __restrict__ Ut,
+                                                          double* __restrict__ stats) {
+  __shared__ double sX[BOYS_LDS_DOUBLES];
+  const int tid = threadIdx.x;
+  const int nn = n * n;
+  for (int e = tid; e < D * nn; e += 256) sX[e] = Xg[e];
+  for (int e = tid; e < nn; e += 256) Ut[e] = (e / n == e % n) ? 1.0 : 0.0;
+  __syncthreads();
+  auto functional = [&]() {
+    double b = 0.0;
+    for (int d = 0; d < D; ++d)
+      for (int i = 0; i < n; ++i) {
+        const double v = sX[d * nn + i * n + i];
+        b += v * v;
+      }
+    return b;
+  };
+  double prev = functional();
+  const double first = prev;
+  int sweeps = 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    for (int i = 0; i < n; ++i) {
+      for (int j = i + 1; j < n; ++j) {
+        double ch = 0.0, hc = 0.0;
+        for (int d = 0; d < D; ++d) {
+          const double h = 0.5 * (sX[d * nn + i * n + i] - sX[d * nn + j * n + j]);
+          const double c = sX[d * nn + i * n + j];
+          ch += c * h;
+          hc += h * h - c * c;
+        }
+        const double t = 0.25 * atan2(2.0 * ch, hc);
+        const double cs = cos(t), sn = sin(t);
+        __syncthreads();   // every thread has read the pair's entries
+        // columns i and j of every X_d
+        for (int e = tid; e < D * n; e += 256) {
+          const int d = e / n, k = e % n;
+          double* row = sX + d * nn + k * n;
+          const double xi = row[i], xj = row[j];
+          row[i] = xi * cs + xj * sn;
+          row[j] = -xi * sn + xj * cs;
+        }
+        // rows i and j of Ut (columns of U)
+        for (int k = tid; k < n; k += 256) {
+          const double ui = Ut[(size_t)i * n + k], uj = Ut[(size_t)j * n + k];
+          Ut[(size_t)i * n + k] = cs * ui + sn * uj;
+          Ut[(size_t)j * n + k] = -sn * ui + cs * uj;
+        }
+        __syncthreads();
+        // rows i and j of every X_d
+        for (int e = tid; e < D * n; e += 256) {
+          const int d = e / n, k = e % n;
+          double* Xd = sX + d * nn;
+          const double xi = Xd[i * n + k], xj = Xd[j * n + k];
+          Xd[i * n + k] = cs * xi + sn * xj;
+          Xd[j * n + k] = -sn * xi + cs * xj;
+        }
+        __syncthreads();
+      }
+    }
+    ++sweeps;
+    const double b = functional();
+    const bool done = b - prev <= tol * fabs(b);
+    prev = b;
+    if (done) break;
+  }
+  if (tid == 0) {
+    stats[0] = first;
+    stats[1] = prev;
+    stats[2] = (double)sweeps;
+  }
+}
+
+// out[r][i] = sum_k C[r][k] Ut[i][k]; one thread per (r, i)
+__global__ __launch_bounds__(256) void boys_apply_kernel(int M, int n, const double* __restrict__ C,
+                                                         const double* __restrict__ Ut, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)M * n) return;
+  const int r = (int)(e / n), i = (int)(e % n);
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += C[(size_t)r * n + k] * Ut[(size_t)i * n + k];
+  out[e] = s;
+}
+
+int boys_max_lds_doubles() { return BOYS_LDS_DOUBLES; }
+
+size_t boys_workspace(int M, int n, int D) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(sizeof(double) * (size_t)D * n * n) + al(sizeof(double) * (size_t)n * n) +
+         al(sizeof(double) * (size_t)M * n) + al(sizeof(double) * 4);
+}
+
+hipError_t launch_boys(hipStream_t s, int M, int n, int D, const double* pos, double* C, int max_sweeps, double tol,
+                       void* work, double* stats_dev) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  char* base = (char*)work;
+  double* X = (double*)base;
+  double* Ut = (double*)(base + al(sizeof(double) * (size_t)D * n * n));
+  double* C0 = (double*)((char*)Ut + al(sizeof(double) * (size_t)n * n));
+  hipError_t e = hipMemcpyAsync(C0, C, sizeof(double) * (size_t)M * n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(boys_project_kernel, dim3((unsigned)((D * n * n + 255) / 256)), dim3(256), 0, s, M, n, D, C0, pos,
+                     X);
+  hipLaunchKernelGGL(boys_jacobi_kernel, dim3(1), dim3(256), 0, s, n, D, max_sweeps, tol, X, Ut, stats_dev);
+  hipLaunchKernelGGL(boys_apply_kernel, dim3((unsigned)(((int64_t)M * n + 255) / 256)), dim3(256), 0, s, M, n, C0, Ut,
+                     C);
+  return hipGetLastError();
+}
+
 }  // namespace lofqmc

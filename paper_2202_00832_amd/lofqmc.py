@@ -20,6 +20,7 @@ HEADER_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__fil
 LO_OK, LO_EINVAL, LO_ENOMEM, LO_EHIP, LO_EUNSUPPORTED, LO_ESOLVER = 0, -1, -2, -3, -4, -5
 LO_FP64, LO_FP32, LO_BF16X3, LO_BF16 = 0, 1, 2, 3
 LO_THETA_ORBITAL_MAJOR = 1
+LO_EXACT_COULOMB = 2
 RESIDUAL_NFEAT = 4   # per-orbital features of the learned residual
 _NAMES = {0: "LO_OK", -1: "LO_EINVAL", -2: "LO_ENOMEM", -3: "LO_EHIP", -4: "LO_EUNSUPPORTED", -5: "LO_ESOLVER"}
 
@@ -43,9 +44,11 @@ _SIGS = {
     "green_theta": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p, _c_p, _c_p, ctypes.c_uint]),
     "local_energy_full": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _i64, _c_p, _c_p, _c_p, ctypes.c_int,
                                          ctypes.c_uint, _c_p]),
-    "local_energy_lo": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p]),
-    "local_energy_lo_noalloc": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p]),
+    "local_energy_lo": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p, _c_p]),
+    "local_energy_lo_noalloc": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_uint, _c_p,
+                                                _c_p]),
     "build_hr_eri": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, ctypes.POINTER(_c_p)]),
+    "lo_localize_boys": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, ctypes.c_int, ctypes.c_double, _c_p]),
     "lo_hr_destroy": (ctypes.c_int, [_c_p]),
     "lo_hr_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p]),
     "local_energy_hr": (ctypes.c_int, [_c_p, _c_p, _i64, _c_p, _c_p, ctypes.c_uint, _c_p]),
@@ -452,11 +455,16 @@ class Context:
         return energy
 
     def local_energy_lo(self, factors: Factors, theta, info=None, energy=None, precision=LO_FP64, flags=0,
-                        orbital_major=False, noalloc=False):
+                        orbital_major=False, noalloc=False, lbar=None):
         """theta is [nw][M][n], or [n][M][nw] when orbital_major.  noalloc=True
         calls local_energy_lo_noalloc (fixed scratch, no device allocation in
-        the library; `energy` should then be passed in by the caller)."""
+        the library; `energy` should then be passed in by the caller).  With
+        lbar ([X][M][n], the vectors the factors were built from) E_J comes
+        from the Cholesky traces (LO_EXACT_COULOMB)."""
         import torch
+        if lbar is not None:
+            _check_dev("lbar", lbar, torch.float64, (lbar.shape[0], factors.M, factors.n_occ))
+            flags = flags | LO_EXACT_COULOMB
         if orbital_major:
             nw = theta.shape[2]
             _check_dev("theta", theta, torch.complex128, (factors.n_occ, factors.M, nw))
@@ -471,7 +479,7 @@ class Context:
         _check_dev("energy", energy, torch.complex128, (nw, 2))
         fn = self._lib.local_energy_lo_noalloc if noalloc else self._lib.local_energy_lo
         self._check(fn(self._h, factors.handle, nw, _ptr(theta), _ptr(info), int(precision), int(flags),
-                       _ptr(energy)))
+                       _ptr(lbar), _ptr(energy)))
         return energy
 
     def local_energy_hr(self, hr: HrEri, theta, info=None, energy=None, orbital_major=False):
@@ -564,6 +572,20 @@ class Context:
             _check_dev("grad", grad, torch.float64, (factors.M, factors.n_occ))
         self._check(self._lib.lo_residual_prepare(self._h, factors.handle, X, _ptr(lbar), _ptr(trial), _ptr(grad)))
         return grad
+
+    def localize_boys(self, positions, orbitals, max_sweeps=50, tol=1e-14):
+        """Foster-Boys localization of orbitals [M][n] (device float64, in
+        place) for position operators positions [D][M]; returns (B before,
+        B after, sweeps run)."""
+        import torch
+        M, n = orbitals.shape
+        _check_dev("orbitals", orbitals, torch.float64, (M, n))
+        D = positions.shape[0]
+        _check_dev("positions", positions, torch.float64, (D, M))
+        st = (ctypes.c_double * 3)()
+        self._check(self._lib.lo_localize_boys(self._h, M, n, D, _ptr(positions), _ptr(orbitals), int(max_sweeps),
+                                               float(tol), ctypes.addressof(st)))
+        return st[0], st[1], int(st[2])
 
     def residual_target(self, e_exact, e_lo, shift=0.0, scale=1.0, t=None):
         """(1000 Re(sum e_exact - sum e_lo) - shift) / scale per walker, float64 [nw]."""

@@ -175,6 +175,21 @@ def random_walks(trial: np.ndarray, n_walks: int, n_steps: int, step: float,
     return out
 
 
+def delocalized_trial(trial: np.ndarray) -> np.ndarray:
+    """Canonical-like orbitals spanning the same space as `trial`: the
+    eigenvectors of the chain's nearest-neighbour hopping operator projected
+    onto that space (standing waves over the whole chain), C V with
+    C^T H C = V diag V^T, H[p][p +- 1] = -1.  Input for the localization
+    tests; column signs fixed so that each column's largest entry is
+    positive."""
+    M = trial.shape[0]
+    H = -(np.eye(M, k=1) + np.eye(M, k=-1))
+    _, V = np.linalg.eigh(trial.T @ H @ trial)
+    C = trial @ V
+    big = np.argmax(np.abs(C), axis=0)
+    return C * np.sign(C[big, np.arange(C.shape[1])])[None, :]
+
+
 def random_orthogonal(n: int, rng: np.random.Generator) -> np.ndarray:
     """Haar-ish random real orthogonal n x n matrix (used to delocalize a trial)."""
     q, r = np.linalg.qr(rng.standard_normal((n, n)))

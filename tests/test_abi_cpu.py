@@ -41,21 +41,26 @@ def test_validation_errors_need_no_device(lib):
         assert lib.green_theta(h, 0, 2, 1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert lib.green_theta(h, 4, 5, 1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL   # n > M
         assert lib.green_theta(h, 200, 113, 1, fake, fake, fake, None, fake, 0) == L.LO_EUNSUPPORTED
-        assert lib.local_energy_full(h, 100, 65, 3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_full(h, 200, 113, 3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_full(h, 100, 65, 3, 4, fake, fake, None, L.LO_BF16X3, 0, fake) == L.LO_EUNSUPPORTED
         assert lib.local_energy_full(h, 100, 97, 3, 4, fake, fake, None, L.LO_FP32, 0, fake) == L.LO_EUNSUPPORTED
         assert lib.green_theta(h, 8, 2, -1, fake, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert lib.green_theta(h, 8, 2, 3, None, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert b"null" in lib.lo_last_error(h)
         assert lib.green_theta(h, 8, 2, 0, None, None, None, None, None, 0) == L.LO_OK   # empty batch
         assert lib.green_theta(h, 8, 2, 3, fake, fake, fake, None, fake, 6) == L.LO_EINVAL  # unknown flag
-        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, 2, fake) == L.LO_EINVAL
+        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, 4, None, fake) == L.LO_EINVAL
+        # LO_EXACT_COULOMB needs lbar and walker-major theta
+        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, L.LO_EXACT_COULOMB, None, fake) == L.LO_EINVAL
+        assert b"lbar" in lib.lo_last_error(h)
+        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, 3, fake, fake) == L.LO_EUNSUPPORTED
         assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, 7, 0, fake) == L.LO_EINVAL   # precision
-        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP32, 1, fake) == L.LO_EUNSUPPORTED
-        assert lib.local_energy_lo(h, fake, 4, fake, None, 9, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP32, 1, None, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_lo(h, fake, 4, fake, None, 9, 0, None, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP64, 7, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, -3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, 3, 0, None, None, None, L.LO_FP64, 0, None) == L.LO_OK
-        assert lib.local_energy_lo(h, None, 4, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_lo(h, None, 4, fake, None, L.LO_FP64, 0, None, fake) == L.LO_EINVAL
         out = ctypes.c_void_p()
         for eps in (-1e-4, math.nan, math.inf):
             assert lib.build_lo_factors(h, 8, 2, 3, fake, eps, ctypes.byref(out)) == L.LO_EINVAL
@@ -87,9 +92,9 @@ def test_validation_errors_need_no_device(lib):
         assert lib.lo_hr_info(None, None, None, None) == L.LO_EINVAL
         assert lib.lo_hr_destroy(None) == L.LO_OK
         # allocation-free LO energy: the same checks before any device work
-        assert lib.local_energy_lo_noalloc(h, None, 4, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
-        assert lib.local_energy_lo_noalloc(None, fake, 4, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
-        assert lib.local_energy_lo_noalloc(h, fake, 4, fake, None, 9, 0, fake) == L.LO_EINVAL
+        assert lib.local_energy_lo_noalloc(h, None, 4, fake, None, L.LO_FP64, 0, None, fake) == L.LO_EINVAL
+        assert lib.local_energy_lo_noalloc(None, fake, 4, fake, None, L.LO_FP64, 0, None, fake) == L.LO_EINVAL
+        assert lib.local_energy_lo_noalloc(h, fake, 4, fake, None, 9, 0, None, fake) == L.LO_EINVAL
         # learned residual: targets, corrected energies, gradient set-up
         assert lib.lo_residual_target(h, 4, fake, fake, 0.0, 0.0, fake) == L.LO_EINVAL      # scale 0
         assert lib.lo_residual_target(h, 4, fake, fake, 0.0, math.inf, fake) == L.LO_EINVAL
@@ -100,6 +105,14 @@ def test_validation_errors_need_no_device(lib):
         assert lib.lo_residual_apply(h, 4, fake, None, math.nan, 0.0, fake) == L.LO_EINVAL
         assert lib.lo_residual_apply(h, 0, None, None, 1.0, 0.0, None) == L.LO_OK
         assert lib.lo_residual_prepare(h, None, 3, fake, fake, None) == L.LO_EINVAL
+        # Foster-Boys localization
+        assert lib.lo_localize_boys(h, 10, 11, 1, fake, fake, 5, 1e-12, None) == L.LO_EINVAL     # n > M
+        assert lib.lo_localize_boys(h, 10, 4, 0, fake, fake, 5, 1e-12, None) == L.LO_EINVAL
+        assert lib.lo_localize_boys(h, 10, 4, 1, fake, fake, 0, 1e-12, None) == L.LO_EINVAL
+        assert lib.lo_localize_boys(h, 10, 4, 1, fake, fake, 5, -1.0, None) == L.LO_EINVAL
+        assert lib.lo_localize_boys(h, 10, 4, 1, None, fake, 5, 1e-12, None) == L.LO_EINVAL
+        assert lib.lo_localize_boys(h, 200, 4, 4, fake, fake, 5, 1e-12, None) == L.LO_EUNSUPPORTED
+        assert lib.lo_localize_boys(h, 200, 72, 3, fake, fake, 5, 1e-12, None) == L.LO_EUNSUPPORTED
         assert lib.lo_residual_features(h, None, 4, fake, fake) == L.LO_EINVAL
     finally:
         assert lib.lo_destroy(h) == L.LO_OK

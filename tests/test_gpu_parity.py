@@ -160,7 +160,10 @@ def test_green_theta_zero_pivot_and_nan_energy(ctx):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("M,n,X,nw", [(37, 5, 11, 3), (50, 17, 23, 7), (100, 60, 40, 5), (64, 64, 9, 4),
-                                      (20, 1, 7, 2), (131, 47, 30, 6), (33, 32, 1, 1), (48, 16, 17, 9)])
+                                      (20, 1, 7, 2), (131, 47, 30, 6), (33, 32, 1, 1), (48, 16, 17, 9),
+                                      # beyond 64 orbitals: block pairs over 2, 3 and 4 passes
+                                      (90, 65, 13, 5), (97, 80, 21, 6), (130, 100, 17, 9), (120, 112, 11, 4),
+                                      (113, 96, 3, 1)])
 def test_full_energy_from_reference_theta(ctx, M, n, X, nw):
     print("full M=%d n=%d X=%d nw=%d" % (M, n, X, nw), flush=True)
     chol, trial, walkers = random_system(M, n, X, nw, seed=M * n + X)
@@ -239,6 +242,37 @@ def test_lo_energy_ragged(ctx, M, n, X, nw, eps):
     f, got, ref, rg, rr, _, _ = _lo_case(ctx, chol, trial, walkers, eps)
     assert np.array_equal(rg, rr)
     assert_energy_close(got, ref)
+
+
+@pytest.mark.parametrize("M,n,X,nw,eps,chain", [(48, 8, 95, 16, 1e-3, True), (70, 33, 30, 5, 1e-4, False),
+                                                (96, 20, 15, 40, 1e-3, False)])
+def test_lo_exact_coulomb(ctx, M, n, X, nw, eps, chain):
+    """LO_EXACT_COULOMB: E_J from the Cholesky traces (the Cholesky-route
+    E_J of the reference), E_K from the LO pair sums (the LO-route E_K)."""
+    print("lo exact coulomb M=%d n=%d X=%d nw=%d eps=%g" % (M, n, X, nw, eps), flush=True)
+    if chain:
+        s = synth.make_system(synth.CHAIN_SMALL)
+        chol, trial, walkers = s.chol, s.trial, s.walkers
+    else:
+        chol, trial, walkers = random_system(M, n, X, nw, seed=5 * M + n)
+    lbar_ref = E.half_rotate(chol, trial)
+    lbar = ctx.build_half_rotated_chol(dev(chol), dev(trial))
+    f = ctx.build_lo_factors(lbar, eps)
+    theta, _, info = ctx.green_theta(dev(trial), dev(walkers))
+    got = host(ctx.local_energy_lo(f, theta, info, lbar=lbar))
+    thetas, _ = oracle_thetas(trial, walkers)
+    ref_full = E.e2_cholesky_batch(lbar_ref, thetas)
+    ref_lo = E.e2_lo_batch(E.lo_compress(lbar_ref, eps, pairs="upper"), thetas)
+    ref = np.stack([ref_full[:, 0], ref_lo[:, 1]], axis=1)
+    assert_energy_close(got, ref)
+    # the plain LO call is unchanged, and the two share E_K bit for bit
+    plain = host(ctx.local_energy_lo(f, theta, info))
+    assert_energy_close(plain, ref_lo)
+    assert np.array_equal(np.ascontiguousarray(plain[:, 1]).view(np.float64),
+                          np.ascontiguousarray(got[:, 1]).view(np.float64))
+    with pytest.raises(lofqmc.LoError):
+        theta_om, _, _ = ctx.green_theta(dev(trial), dev(walkers), orbital_major=True)
+        ctx.local_energy_lo(f, theta_om, orbital_major=True, lbar=lbar)
 
 
 def test_lo_threshold_above_every_singular_value_gives_zero(ctx):

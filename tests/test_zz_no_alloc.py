@@ -113,7 +113,7 @@ def test_noalloc_rejects_a_batch_beyond_its_scratch():
         fac = ctx.build_lo_factors(lbar, 1e-4)
         lib = lofqmc.load()
         fake = ctypes.c_void_p(0x1000)   # never dereferenced: the size check comes first
-        rc = lib.local_energy_lo_noalloc(ctx.handle, fac.handle, 1 << 30, fake, None, lofqmc.LO_FP64, 0, fake)
+        rc = lib.local_energy_lo_noalloc(ctx.handle, fac.handle, 1 << 30, fake, None, lofqmc.LO_FP64, 0, None, fake)
         assert rc == lofqmc.LO_EUNSUPPORTED
         assert b"scratch" in lib.lo_last_error(ctx.handle)
         fac.close()
