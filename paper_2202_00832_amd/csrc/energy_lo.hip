@@ -176,7 +176,12 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_reg_kernel(int M, int64_t nw,
 // by 2 (r & 3): the 4 rows x 2 column pairs of one MFMA operand read fall in 8
 // distinct 16-byte bank groups.  Rows past the tile and walkers past nw load
 // a valid address and their outputs are discarded.
-__global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
+// NWV = 8 waves (192-row tiles, two workgroups per CU) or 16 waves (384-row
+// tiles for orbitals that touch more than 192 rows, one workgroup per CU:
+// each orbital's rows, and its theta column, are then gathered once per
+// walker tile instead of twice).
+template <int NWV>
+__global__ __launch_bounds__(64 * NWV, NWV == 8 ? 2 : 1) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
                                                              const int* __restrict__ rowidx,
                                                              const int* __restrict__ tile_orb,
                                                              const int* __restrict__ tile_row0,
@@ -188,8 +193,10 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
   // two buffers as distinct objects (and the slab loop unrolled by two), so
   // the compiler sees that the reads of one buffer and the loads in flight
   // into the other cannot alias and does not wait for the loads before reading
-  __shared__ __attribute__((aligned(16))) double sA0[LO_TILE_ROWS * 16];   // swizzled [row][r]
-  __shared__ __attribute__((aligned(16))) double sA1[LO_TILE_ROWS * 16];
+  constexpr int TILE = LO_WROWS * NWV;
+  constexpr int NT = 64 * NWV;
+  __shared__ __attribute__((aligned(16))) double sA0[TILE * 16];   // swizzled [row][r]
+  __shared__ __attribute__((aligned(16))) double sA1[TILE * 16];
   __shared__ __attribute__((aligned(16))) double2 sB0[16 * LO_WT];         // [r][walker]
   __shared__ __attribute__((aligned(16))) double2 sB1[16 * LO_WT];
   int t;
@@ -214,29 +221,31 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
   const bool active = rw < nrows;
   const double2* tho = theta + o * so;
 
-  // A: 192 rows x 8 column pairs = 1536 16-byte slots, three per thread: slot
-  // S = 512 k + tid holds row S / 8, column pair (S % 8) ^ (2 (row & 3))
-  constexpr int A_LD = LO_TILE_ROWS * 8 / 512;   // 3
+  // A: TILE rows x 8 column pairs of 16-byte slots, three per thread: slot
+  // S = NT k + tid holds row S / 8, column pair (S % 8) ^ (2 (row & 3))
+  constexpr int A_LD = TILE * 8 / NT;   // 3
   const double* asrc[A_LD];
 #pragma unroll
   for (int k = 0; k < A_LD; ++k) {
-    const int S = 512 * k + tid;
+    const int S = NT * k + tid;
     const int row = S >> 3;
     const int cp = (S & 7) ^ (2 * (row & 3));
     const int ar = rowidx[row0 + (row < nrows ? row : 0)];
     asrc[k] = rows + (size_t)ar * M + 2 * cp;
   }
-  // B: slot tid holds r = tid / 32, walker tid % 32 (clamped to a valid walker)
+  // B: 16 x 32 slots, slot tid (tid < 512, the first eight waves) holds
+  // r = tid / 32, walker tid % 32 (clamped to a valid walker)
   const int64_t bw = w0 + (tid % LO_WT) < nw ? w0 + (tid % LO_WT) : nw - 1;
-  const double2* bsrc = tho + (tid / LO_WT) * sr + bw * sw;
-  auto issue = [&](int c, double* sa, double2* sb) {
+  const double2* bsrc = tho + ((tid & 511) / LO_WT) * sr + bw * sw;
+  auto issue = [&](int c, double* sa, double2* sb) __attribute__((always_inline)) {
 #pragma unroll
     for (int k = 0; k < A_LD; ++k)
       __builtin_amdgcn_global_load_lds((const void*)(asrc[k] + 16 * c),
-                                       (__attribute__((address_space(3))) void*)(sa + (512 * k + 64 * wv) * 2), 16, 0,
+                                       (__attribute__((address_space(3))) void*)(sa + (NT * k + 64 * wv) * 2), 16, 0,
                                        0);
-    __builtin_amdgcn_global_load_lds((const void*)(bsrc + 16 * c * sr),
-                                     (__attribute__((address_space(3))) void*)(sb + 64 * wv), 16, 0, 0);
+    if (NWV == 8 || wv < 8)
+      __builtin_amdgcn_global_load_lds((const void*)(bsrc + 16 * c * sr),
+                                       (__attribute__((address_space(3))) void*)(sb + 64 * wv), 16, 0, 0);
   };
 
   // acc[q][c]: rows rw + 4q + lk, walker column c (block h = c / 2, part = c % 2)
@@ -250,7 +259,10 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
   const int e2 = 2 * (lane & 3);
   const int abase = (rw + (lane & 3)) * 16 + (lk & 1);
   const int nchunk = M / 16;
-  auto compute = [&](const double* sa, const double2* sb) {
+  // 4-row groups of this wave that hold rows of the tile (wave-uniform): the
+  // last busy wave of a tile skips the products of the groups past its end
+  const int qv = active ? min(LO_QG, (nrows - rw + 3) / 4) : 0;
+  auto compute = [&](const double* sa, const double2* sb, int nq) __attribute__((always_inline)) {
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const int rr = 4 * s4 + lk;
@@ -259,25 +271,34 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_kernel(int M, int64_t nw, con
       const int aoff = abase + 2 * (((2 * s4) ^ e2) | (lk >> 1));
 #pragma unroll
       for (int q = 0; q < LO_QG; ++q) {
-        const double a = sa[aoff + 64 * q];
-        acc[q][0] = mfma4(a, b0.x, acc[q][0]);
-        acc[q][1] = mfma4(a, b0.y, acc[q][1]);
-        acc[q][2] = mfma4(a, b1.x, acc[q][2]);
-        acc[q][3] = mfma4(a, b1.y, acc[q][3]);
+        if (q < nq) {
+          const double a = sa[aoff + 64 * q];
+          acc[q][0] = mfma4(a, b0.x, acc[q][0]);
+          acc[q][1] = mfma4(a, b0.y, acc[q][1]);
+          acc[q][2] = mfma4(a, b1.x, acc[q][2]);
+          acc[q][3] = mfma4(a, b1.y, acc[q][3]);
+        }
       }
     }
+  };
+  // the common case (every group busy) is compiled without the row tests
+  auto compute_wave = [&](const double* sa, const double2* sb) __attribute__((always_inline)) {
+    if (qv == LO_QG)
+      compute(sa, sb, LO_QG);
+    else if (qv > 0)
+      compute(sa, sb, qv);
   };
   issue(0, sA0, sB0);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   for (int c = 0; c < nchunk; c += 2) {
     if (c + 1 < nchunk) issue(c + 1, sA1, sB1);
-    if (active) compute(sA0, sB0);
+    compute_wave(sA0, sB0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (c + 1 < nchunk) {
       if (c + 2 < nchunk) issue(c + 2, sA0, sB0);
-      if (active) compute(sA1, sB1);
+      compute_wave(sA1, sB1);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
     }
@@ -303,9 +324,12 @@ const char* lo_pass1_name(int M) { return M % 16 == 0 ? "lo_pass1_kernel" : "lo_
 int lo_tile_rows() { return LO_TILE_ROWS; }
 int lo_orbital_block() { return LO_OBLK; }
 
+int lo_wide_tile_rows() { return 2 * LO_TILE_ROWS; }
+
 hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
                            const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
-                           const double* theta, int orbital_major, double* qbar, int64_t out_walker_stride) {
+                           const double* theta, int orbital_major, double* qbar, int64_t out_walker_stride,
+                           int tile_rows) {
   if (nw <= 0 || ntiles <= 0) return hipSuccess;
   const int nwt = (int)((nw + LO_WT - 1) / LO_WT);
   const int64_t units = (int64_t)nblk * nwt;
@@ -313,7 +337,10 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
   const int64_t so = orbital_major ? (int64_t)M * nw : 1;
   const int64_t sr = orbital_major ? nw : n;
   const int64_t sw = orbital_major ? 1 : (int64_t)M * n;
-  hipLaunchKernelGGL(M % 16 == 0 ? lo_pass1_kernel : lo_pass1_reg_kernel, dim3((unsigned)grid), dim3(512), 0, s, M,
+  const bool wide = tile_rows == 2 * LO_TILE_ROWS;
+  if (wide && M % 16 != 0) return hipErrorInvalidValue;   // the wide tile has no register-staged form
+  auto kern = wide ? lo_pass1_kernel<16> : (M % 16 == 0 ? lo_pass1_kernel<8> : lo_pass1_reg_kernel);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(wide ? 1024 : 512), 0, s, M,
                      nw, rows, rowidx, tiles,
                      tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax, (const double2*)theta, so, sr, sw,
                      (double2*)qbar, out_walker_stride ? (int64_t)1 : nw,

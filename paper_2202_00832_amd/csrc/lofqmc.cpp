@@ -43,6 +43,7 @@ struct lo_factors {
   std::vector<double> discarded;       // [n][n], sum of the discarded singular values
   std::vector<int64_t> row_offset;     // [n][n], -1 for i > j
   int ntiles = 0, npairs = 0, nblk = 0, tmax = 0;
+  int tile_rows = 0;                   // pass-1 tile size the FP64 tiles were cut at
   int ntiles_lp = 0, nblk_lp = 0, tmax_lp = 0;
   int* d_rowidx = nullptr;             // [n_out_rows]
   int* d_tiles = nullptr;              // [3][ntiles]: orbital, first output row, row count;
@@ -617,13 +618,24 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
   }
 
   // ---- tables of the two energy passes
+  // A diagonal block Y^[ii] is symmetric positive semidefinite, so every left
+  // singular vector with sigma > 0 equals its right one (Y v = sigma u and
+  // Y v = sigma v): Vbar^[ii] = Ubar^[ii]T and QR_i = QL_i.  With the exact SVD
+  // the pass-1 product of orbital i then takes only the Ubar^T rows of its
+  // diagonal pair; the randomized SVD only approximates the singular vectors,
+  // so its factors keep both.
+  const bool diag_u_only = (L == 0);
+  auto out_rows = [&](int o, int k) -> int64_t {
+    const int64_t K = f->ranks[o * n + k];
+    return (o == k && diag_u_only) ? K : 2 * K;
+  };
   std::vector<int64_t> obase(n + 1, 0);
   std::vector<int64_t> loc(n * n, 0);  // local output row of pair (o, k) within orbital o
   for (int o = 0; o < n; ++o) {
     int64_t R = 0;
     for (int k = 0; k < n; ++k) {
       loc[o * n + k] = R;
-      R += 2 * (int64_t)f->ranks[o * n + k];
+      R += out_rows(o, k);
     }
     obase[o + 1] = obase[o] + R;
   }
@@ -639,7 +651,7 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
     for (int k = 0; k < n; ++k) {
       const int i = std::min(o, k), j = std::max(o, k);
       const int64_t src = f->row_offset[i * n + j];
-      const int64_t cnt = 2 * (int64_t)f->ranks[o * n + k];
+      const int64_t cnt = out_rows(o, k);
       for (int64_t q = 0; q < cnt; ++q) rowidx[obase[o] + loc[o * n + k] + q] = (int)(src + q);
     }
   }
@@ -676,7 +688,13 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
     tiles.insert(tiles.end(), blk.begin(), blk.end());
     return tiles;
   };
-  const std::vector<int> tiles = build_tiles(lofqmc::lo_tile_rows(), &f->ntiles, &f->nblk, &f->tmax);
+  // FP64 pass 1: 384-row tiles (16 waves) when an orbital touches more than
+  // 192 rows and M is a multiple of 16, so each orbital stays one tile
+  int64_t rmax = 0;
+  for (int o = 0; o < n; ++o) rmax = std::max<int64_t>(rmax, obase[o + 1] - obase[o]);
+  f->tile_rows = (rmax > lofqmc::lo_tile_rows() && M % 16 == 0) ? lofqmc::lo_wide_tile_rows()
+                                                                 : lofqmc::lo_tile_rows();
+  const std::vector<int> tiles = build_tiles(f->tile_rows, &f->ntiles, &f->nblk, &f->tmax);
   const std::vector<int> tiles_lp = build_tiles(lofqmc::lo_lp_tile_rows(), &f->ntiles_lp, &f->nblk_lp, &f->tmax_lp);
   // pass-2 entries: one per rank row K of every stored pair i <= j, the
   // output rows of QL_i, QR_j (Coulomb) and QL_j, QR_i (exchange), padded
@@ -690,11 +708,13 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
       if (K == 0) continue;
       ++nstored;
       const int64_t oi = obase[i] + loc[i * n + j], oj = obase[j] + loc[j * n + i];
+      // the QR rows follow the QL rows, or are the QL rows (diagonal, exact SVD)
+      const int64_t vr = (i == j && diag_u_only) ? 0 : K;
       for (int k = 0; k < K; ++k) {
         e_li.push_back((int)(oi + k));
-        e_rj.push_back((int)(oj + K + k));
+        e_rj.push_back((int)(oj + vr + k));
         e_lj.push_back((int)(oj + k));
-        e_ri.push_back((int)(oi + K + k));
+        e_ri.push_back((int)(oi + vr + k));
         e_w.push_back(i == j ? 1.0 : 2.0);
       }
     }
@@ -796,7 +816,7 @@ int lo_energy_enqueue(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double
     prof.mark(lofqmc::lo_pass1_name((int)M));
     HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
                                              f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
-                                             orbital_major ? 1 : 0, qbar, 0));
+                                             orbital_major ? 1 : 0, qbar, 0, f->tile_rows));
   } else if (f->ntiles > 0) {
     void* tlp = base + qbytes + pbytes;
     prof.mark("lp_convert_kernel");
@@ -1278,7 +1298,8 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   prof.mark(lofqmc::lo_pass1_name((int)md->M));
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)md->M, (int)md->n, nw, md->ntiles, md->rows,
                                            md->d_rowidx, md->d_tiles, md->d_tiles + 3 * md->ntiles, md->nblk,
-                                           md->tmax, theta, om ? 1 : 0, qbar, md->n_out_rows));
+                                           md->tmax, theta, om ? 1 : 0, qbar, md->n_out_rows,
+                                           lofqmc::lo_tile_rows()));
   prof.mark("md_prep_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_md_prep(ctx->stream, g, mwork, ovlp_ratio));
   prof.mark("md_energy_kernel");

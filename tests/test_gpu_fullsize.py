@@ -23,6 +23,7 @@ from paper_2202_00832_amd import lofqmc  # noqa: E402
 
 SAMPLE = [0, 1, 173, 300, 511]
 EPS = 1e-5
+EPS_TIGHT = 1e-7
 
 
 @pytest.fixture(scope="module")
@@ -39,11 +40,16 @@ def run():
     fac = ctx.build_lo_factors(lbar, EPS)
     theta_om, _, info_om = ctx.green_theta(trial, phi, orbital_major=True)
     e_lo = ctx.local_energy_lo(fac, theta_om, info_om, orbital_major=True)
+    # the headline threshold: orbitals touch more than 192 factor rows, so
+    # pass 1 runs its 384-row tiles; walker-major theta as in the bench
+    fac7 = ctx.build_lo_factors(lbar, EPS_TIGHT)
+    e_lo7 = ctx.local_energy_lo(fac7, theta, info)
     torch.cuda.synchronize()
     out = dict(system=s, theta=theta.cpu().numpy(), logov=logov.cpu().numpy(), info=info.cpu().numpy(),
                e_full=e_full.cpu().numpy(), e_lo=e_lo.cpu().numpy(), ranks=fac.info()["ranks"],
-               theta_om=theta_om.cpu().numpy())
+               theta_om=theta_om.cpu().numpy(), e_lo7=e_lo7.cpu().numpy(), ranks7=fac7.info()["ranks"])
     fac.close()
+    fac7.close()
     ctx.close()
     return out
 
@@ -79,9 +85,34 @@ def test_full_energy_sampled_walkers(run, ref):
 
 
 @pytest.fixture(scope="module")
-def ref_lo(ref, run):
+def ref_svd(ref, run):
     print("reference SVD of the 1830 pair blocks", flush=True)
-    return E.lo_compress(ref["lbar"], EPS, pairs="upper")
+    return E.lo_decompose(ref["lbar"], pairs="upper")
+
+
+@pytest.fixture(scope="module")
+def ref_lo(ref_svd):
+    return E.lo_truncate(ref_svd, EPS)
+
+
+def _check_lo(run_ranks, run_e, ref_f, ref, eps):
+    ranks = E.lo_ranks(ref_f, run_ranks.shape[0])
+    # integer decisions taken in FP64 on both sides; a mismatch is only allowed
+    # for a singular value within rounding of the threshold
+    for i, j in np.argwhere(ranks != run_ranks):
+        s = ref_f[(min(i, j), max(i, j))][2]
+        K = min(ranks[i, j], run_ranks[i, j])
+        assert abs(s[K] - eps) <= 1e-12 * s[0], (i, j)
+    for k, w in enumerate(SAMPLE):
+        e = np.array(E.e2_lo(ref_f, ref["thetas"][k]))
+        assert np.abs(run_e[w] - e).max() <= 1e-9, (w, run_e[w], e)
+
+
+def test_lo_energy_at_the_headline_threshold(run, ref, ref_svd):
+    """eps = 1e-7 (the largest threshold whose per-walker error stays within
+    1 mHa on this workload), 384-row pass-1 tiles."""
+    assert 2 * run["ranks7"].sum() - np.trace(run["ranks7"]) > 192 * run["ranks7"].shape[0]
+    _check_lo(run["ranks7"], run["e_lo7"], E.lo_truncate(ref_svd, EPS_TIGHT), ref, EPS_TIGHT)
 
 
 def test_lo_energy_sampled_walkers_and_ranks(run, ref, ref_lo):
