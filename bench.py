@@ -311,10 +311,11 @@ def precision_study(torch, lofqmc, synth, steps, eps=1e-4):
 
 def batch_study(torch, lofqmc, synth, evaluations=50):
     """Eight chain systems of uneven size (M uniform in [100, 600], n = M // 7,
-    64-512 walkers): FP32 full-route energies of all systems per evaluation,
-    one persistent exchange launch per evaluation, `evaluations` evaluations
-    captured in one HIP graph; against the same evaluations as one
-    local_energy_full call per system."""
+    64-512 walkers): per evaluation, from the walkers of every system, FP64
+    green_theta and FP32 full-route energies, one persistent exchange launch
+    for all systems; `evaluations` evaluations captured in one HIP graph;
+    against the same evaluations as green_theta + local_energy_full per
+    system.  The autotuner scales each bucket's chunk by 1/4 ... 4."""
     from paper_2202_00832_amd import autotune
     cfgs = synth.batch_configs()
     log("batching: %s" % ", ".join(c.name for c in cfgs))
@@ -323,13 +324,14 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
     systems, total_w = [], 0
     for c in cfgs:
         sysm = synth.make_system(c)
-        lbar = ctx.build_half_rotated_chol(dev(sysm.chol), dev(sysm.trial))
-        theta, _, info = ctx.green_theta(dev(sysm.trial), dev(sysm.walkers))
-        systems.append({"lbar": lbar, "theta": theta, "info": info})
+        trial, phi = dev(sysm.trial), dev(sysm.walkers)
+        lbar = ctx.build_half_rotated_chol(dev(sysm.chol), trial)
+        theta, _, info = ctx.green_theta(trial, phi)
+        systems.append({"lbar": lbar, "theta": theta, "info": info, "trial": trial, "phi": phi})
         total_w += c.nw
         del sysm
     torch.cuda.synchronize()
-    tuned = autotune.tune(ctx, systems, factors=(0.5, 2.0), reps=2, log=log)
+    tuned = autotune.tune(ctx, systems, factors=(0.25, 0.5, 2.0, 4.0), reps=2, log=log)
     b = lofqmc.Batch(ctx, systems, tuned["chunk"])
     b.capture(evaluations)
     b.replay()
@@ -343,13 +345,18 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
     graph_ms = e0.elapsed_time(e1) / evaluations
     # the same work as separate calls, one per system and evaluation
     outs = [torch.empty((sd["theta"].shape[0], 2), dtype=torch.complex128, device="cuda") for sd in systems]
-    for sd, o in zip(systems, outs):
-        ctx.local_energy_full(sd["lbar"], sd["theta"], sd["info"], o, precision=lofqmc.LO_FP32)
+    ths = [torch.empty_like(sd["theta"]) for sd in systems]
+    infs = [torch.empty_like(sd["info"]) for sd in systems]
+
+    def separate():
+        for sd, o, th, inf in zip(systems, outs, ths, infs):
+            ctx.green_theta(sd["trial"], sd["phi"], th, None, inf)
+            ctx.local_energy_full(sd["lbar"], th, inf, o, precision=lofqmc.LO_FP32)
+    separate()
     torch.cuda.synchronize()
     e0.record()
     for _ in range(evaluations):
-        for sd, o in zip(systems, outs):
-            ctx.local_energy_full(sd["lbar"], sd["theta"], sd["info"], o, precision=lofqmc.LO_FP32)
+        separate()
     e1.record()
     torch.cuda.synchronize()
     seq_ms = e0.elapsed_time(e1) / evaluations
@@ -359,13 +366,19 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
     # holds the FP64 Coulomb sums and reductions)
     xflops = sum(4.0 * sd["lbar"].shape[1] * sd["lbar"].shape[2] ** 2 * sd["lbar"].shape[0] * sd["theta"].shape[0]
                  for sd in systems)
+    # green_theta per walker: overlap 4 M n^2, inverse 8 n^3, apply 8 M n^2 (FP64)
+    gflops = sum(sd["theta"].shape[0] * (12.0 * sd["lbar"].shape[1] * sd["lbar"].shape[2] ** 2
+                                         + 8.0 * sd["lbar"].shape[2] ** 3) for sd in systems)
     info = b.info()
     b.close()
     ctx.close()
     out = {"systems": [c.name for c in cfgs], "walkers": total_w, "evaluations_per_graph": evaluations,
            "work_items": int(info["items"]), "chunk": [int(x) for x in info["chunk"]],
            "autotune_ms": {"default": round(tuned["default_ms"], 3), "tuned": round(tuned["ms"], 3),
-                           "trials": len(tuned["trials"])},
+                           "trials": len(tuned["trials"]), "factors": [0.25, 0.5, 2.0, 4.0],
+                           "tuned_over_default": round(tuned["ms"] / tuned["default_ms"], 4)},
+           "evaluation": "green_theta (FP64) + FP32 full route of every system, from the walkers",
+           "green_theta_flops_per_evaluation": gflops,
            "graph_ms_per_evaluation": round(graph_ms, 3),
            "walker_energies_per_s": round(total_w / (graph_ms * 1e-3), 1),
            "separate_calls_ms_per_evaluation": round(seq_ms, 3),

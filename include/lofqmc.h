@@ -388,13 +388,21 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
  * (the LO_FP32 arithmetic of local_energy_full).  The exchange work of all
  * systems forms one list of items (4 walkers x a chunk of Cholesky vectors of
  * one system) that ONE persistent kernel launch works through; per system
- * there are the operand rewrite, the Coulomb sums and the reduction. */
+ * there are the operand rewrite, the Coulomb sums and the reduction.  A
+ * system that gives its trial and walkers (trial, phi) also has its theta
+ * and info formed by green_theta (Eq. 11, 14, 15; FP64) at the start of every
+ * evaluation, so an evaluation (and a captured graph of evaluations) goes
+ * from the walkers to the energies. */
 typedef struct lo_system {
   int64_t M, n_occ, n_chol, nw;
   const double* lbar;    /* device [n_chol][M][n_occ] */
-  const double* theta;   /* device complex [nw][M][n_occ] (walker-major) */
-  const int32_t* info;   /* device int32 [nw] or NULL */
+  double* theta;         /* device complex [nw][M][n_occ] (walker-major): input,
+                            or output when phi is given */
+  int32_t* info;         /* device int32 [nw] or NULL: input, or output
+                            (required) when phi is given */
   double* energy;        /* device complex [nw][2] (output) = (E_J, E_K) */
+  const double* trial;   /* NULL, or device [M][n_occ] (real, orthonormal) */
+  const double* phi;     /* NULL, or device complex [nw][M][n_occ] walkers */
 } lo_system;
 
 typedef struct lo_batch lo_batch;
@@ -405,8 +413,9 @@ typedef struct lo_batch lo_batch;
  * Cholesky vectors per work item of each system (the tile shape; <= 0 or a
  * NULL array picks a size that makes items of all systems cost about the
  * same).  precision must be LO_FP32; each system needs n_occ <= 96,
- * nw <= 65535, n_chol <= 65535.  Allocates every device buffer the
- * evaluations need, so lo_batch_execute allocates nothing. */
+ * nw <= 65535, n_chol <= 65535, and trial and phi both or neither (with
+ * them, info non-NULL).  Allocates every device buffer the evaluations need
+ * (also green_theta's workspace), so lo_batch_execute allocates nothing. */
 int lo_batch_create(lo_ctx* ctx, int nsys, const lo_system* sys, int precision, const int64_t* chunk,
                     lo_batch** out);
 int lo_batch_destroy(lo_batch* b);

@@ -1420,6 +1420,7 @@ struct lo_batch {
   int nbmax = 1;                            // largest orbital-block count of the systems
   void* mem = nullptr;                      // one device allocation for everything below
   std::vector<void*> lb, tb, cpart;         // per system
+  std::vector<double*> gws;                 // per system: green_theta workspace (systems given phi)
   std::vector<double*> partial;             // per system [nchunk + 1][nw][4]
   lofqmc::LpSys* d_sys = nullptr;
   unsigned* d_counter = nullptr;
@@ -1441,6 +1442,14 @@ void batch_free(lo_batch* b) {
 
 hipError_t batch_enqueue(lo_batch* b, hipStream_t st) {
   hipError_t e;
+  // theta of the systems given their walkers (FP64 green_theta)
+  for (int k = 0; k < b->nsys; ++k) {
+    const lo_system& s = b->sys[k];
+    if (!s.phi) continue;
+    e = lofqmc::launch_green_theta(st, (int)s.M, (int)s.n_occ, s.nw, 0, s.nw, s.trial, s.phi, s.theta, nullptr,
+                                   s.info, 0, b->gws[k], nullptr);
+    if (e != hipSuccess) return e;
+  }
   for (int k = 0; k < b->nsys; ++k) {
     const lo_system& s = b->sys[k];
     e = lofqmc::launch_lp_convert_operands(st, LO_FP32, (int)s.M, (int)s.n_occ, s.n_chol, s.nw, s.lbar, s.theta,
@@ -1478,6 +1487,8 @@ int lo_batch_create(lo_ctx* ctx, int nsys, const lo_system* sys, int precision, 
     if (s.n_occ > kMaxOccWide || s.nw > 65535 || s.n_chol > 65535 || s.M > (1 << 20))
       return fail(ctx, LO_EUNSUPPORTED, "system %d: outside n_occ <= 96, nw, n_chol <= 65535", k);
     if (!s.lbar || !s.theta || !s.energy) return fail(ctx, LO_EINVAL, "system %d: null array", k);
+    if (!s.trial != !s.phi) return fail(ctx, LO_EINVAL, "system %d: trial and phi go together", k);
+    if (s.phi && !s.info) return fail(ctx, LO_EINVAL, "system %d: green_theta needs an info array", k);
   }
   int dev = 0, ncu = 0;
   HIP_OR_FAIL(ctx, hipGetDevice(&dev));
@@ -1514,10 +1525,12 @@ int lo_batch_create(lo_ctx* ctx, int nsys, const lo_system* sys, int precision, 
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int c) { return unit[a] * b->chunk[a] > unit[c] * b->chunk[c]; });
   // one allocation: per system lb, tb, cpart, partial; then the table and the counter
-  std::vector<size_t> off_lb(nsys), off_tb(nsys), off_cp(nsys), off_pa(nsys);
+  std::vector<size_t> off_lb(nsys), off_tb(nsys), off_cp(nsys), off_pa(nsys), off_gw(nsys);
   size_t at = 0;
   for (int k = 0; k < nsys; ++k) {
     const lo_system& s = b->sys[k];
+    off_gw[k] = at;
+    if (s.phi) at += align256(lofqmc::green_theta_workspace((int)s.n_occ, s.nw));
     off_lb[k] = at;
     at += align256(lofqmc::lp_lbar_bytes(LO_FP32, (int)s.M, (int)s.n_occ, s.n_chol));
     off_tb[k] = at;
@@ -1541,6 +1554,9 @@ int lo_batch_create(lo_ctx* ctx, int nsys, const lo_system* sys, int precision, 
   b->tb.resize(nsys);
   b->cpart.resize(nsys);
   b->partial.resize(nsys);
+  b->gws.assign(nsys, nullptr);
+  for (int k = 0; k < nsys; ++k)
+    if (b->sys[k].phi) b->gws[k] = (double*)(base + off_gw[k]);
   std::vector<lofqmc::LpSys> table(nsys);
   int64_t item = 0;
   for (int q = 0; q < nsys; ++q) {

@@ -79,7 +79,7 @@ _SIGS = {
 class _System(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("n_occ", ctypes.c_int64), ("n_chol", ctypes.c_int64), ("nw", ctypes.c_int64),
                 ("lbar", ctypes.c_void_p), ("theta", ctypes.c_void_p), ("info", ctypes.c_void_p),
-                ("energy", ctypes.c_void_p)]
+                ("energy", ctypes.c_void_p), ("trial", ctypes.c_void_p), ("phi", ctypes.c_void_p)]
 
 
 _lib = None
@@ -262,7 +262,9 @@ class Batch:
 
     def __init__(self, ctx: "Context", systems, chunk=None):
         """systems: list of dicts with lbar [X][M][n] f64, theta [nw][M][n] c128,
-        optional info [nw] i32 and energy [nw][2] c128 (device tensors)."""
+        optional info [nw] i32 and energy [nw][2] c128 (device tensors), and
+        optionally trial [M][n] f64 and phi [nw][M][n] c128: then every
+        evaluation first forms theta and info from them (green_theta)."""
         import torch
         self.ctx = ctx
         self.systems = []
@@ -280,8 +282,15 @@ class Batch:
             if energy is None:
                 energy = torch.empty((nw, 2), dtype=torch.complex128, device=theta.device)
             _check_dev("energy", energy, torch.complex128, (nw, 2))
-            self.systems.append({"lbar": lbar, "theta": theta, "info": info, "energy": energy})
-            arr[k] = _System(M, n, X, nw, _ptr(lbar), _ptr(theta), _ptr(info), _ptr(energy))
+            trial, phi = sd.get("trial"), sd.get("phi")
+            if phi is not None:
+                _check_dev("trial", trial, torch.float64, (M, n))
+                _check_dev("phi", phi, torch.complex128, (nw, M, n))
+                if info is None:
+                    info = torch.zeros((nw,), dtype=torch.int32, device=theta.device)
+            self.systems.append({"lbar": lbar, "theta": theta, "info": info, "energy": energy, "trial": trial,
+                                 "phi": phi})
+            arr[k] = _System(M, n, X, nw, _ptr(lbar), _ptr(theta), _ptr(info), _ptr(energy), _ptr(trial), _ptr(phi))
         ch = None
         if chunk is not None:
             ch = np.ascontiguousarray(chunk, dtype=np.int64)

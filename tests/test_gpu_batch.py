@@ -10,6 +10,9 @@
 * A captured graph of several evaluations, replayed with eager work and
   synchronisations in between, must give the eager result bit for bit after
   every replay.
+* Systems given their trial and walkers: every evaluation forms theta by
+  green_theta first; a graph replay from the walkers must reproduce
+  green_theta + local_energy_full(LO_FP32) per system bit for bit.
 Shapes: uneven M, n (one to six 16-orbital blocks), n_chol and walkers.
 """
 import numpy as np
@@ -59,7 +62,8 @@ def systems():
         thetas, _, info = E.green_theta_batch(trial, walkers)
         assert (info == 0).all()
         out.append({"M": M, "n": n, "X": X, "nw": nw, "lbar_ref": lbar_ref, "thetas": thetas,
-                    "lbar": dev(lbar_ref.transpose(0, 2, 1)), "theta": dev(thetas)})
+                    "lbar": dev(lbar_ref.transpose(0, 2, 1)), "theta": dev(thetas), "trial": trial,
+                    "walkers": walkers})
     return out
 
 
@@ -140,6 +144,48 @@ def test_graph_replays_match_eager(ctx, systems):
         b.replay()
         for got, ref in zip(b.energies, eager):
             assert np.array_equal(host(got).view(np.float64), ref.view(np.float64)), rep
+    b.close()
+
+
+def _single_chunks(systems):
+    chunk = []
+    for s in systems:
+        nw, X = s["nw"], s["X"]
+        ngrp, c = (nw + 3) // 4, 1
+        while c < 4096 and ngrp * c < 256 and c < X:
+            c *= 2
+        chunk.append((X + c - 1) // c)
+    return chunk
+
+
+def test_graph_from_walkers_matches_per_system_calls(ctx, systems):
+    desc = []
+    for s in systems:
+        desc.append({"lbar": s["lbar"], "theta": torch.zeros_like(s["theta"]),
+                     "info": torch.full((s["nw"],), -7, dtype=torch.int32, device="cuda"),
+                     "trial": dev(s["trial"]), "phi": dev(s["walkers"])})
+    expect = []
+    for s, d in zip(systems, desc):
+        th, _, inf = ctx.green_theta(d["trial"], d["phi"])
+        expect.append((host(th), host(ctx.local_energy_full(s["lbar"], th, inf, precision=lofqmc.LO_FP32))))
+    b = lofqmc.Batch(ctx, desc, _single_chunks(systems))
+    b.capture(2)
+    for rep in range(3):
+        for d, e in zip(desc, b.energies):
+            d["theta"].zero_()
+            d["info"].fill_(-7)
+            e.zero_()
+        ctx.local_energy_full(systems[0]["lbar"], systems[0]["theta"], precision=lofqmc.LO_FP32)
+        torch.cuda.synchronize()
+        b.replay()
+        for s, d, got, (th_ref, e_ref) in zip(systems, desc, b.energies, expect):
+            assert (host(d["info"]) == 0).all()
+            assert np.array_equal(host(d["theta"]).view(np.float64), th_ref.view(np.float64)), (s["M"], s["n"])
+            assert np.array_equal(host(got).view(np.float64), e_ref.view(np.float64)), (rep, s["M"], s["n"])
+    # and the Coulomb part against the CPU reference
+    for s, got in zip(systems, b.energies):
+        ref = np.asarray(E.e2_cholesky_batch(s["lbar_ref"], s["thetas"]))
+        assert np.abs(host(got)[:, 0] - ref[:, 0]).max() <= 1e-9
     b.close()
 
 
