@@ -11,7 +11,9 @@
 // (T^T)[I,J] = theta^T Lbar: with the same operand fragments both land with
 // every element's exchange partner T_ji in the same lane and register as
 // T_ij, so sum_ij T_ij T_ji is a lane-local product.  Diagonal blocks are
-// transposed through LDS.  The Coulomb trace is summed by one wave per walker
+// transposed through LDS.  With one pass the Coulomb trace comes from the
+// diagonal blocks (the two halves combined through LDS); with several, where
+// no workgroup holds every diagonal block, one wave per walker sums it
 // straight from its operand fragments (each lane holds Lbar[r][i] and
 // theta[r][i] of the same r and i).  The Lbar tile of each K-step is staged
 // once in LDS (double-buffered) and shared by the four walkers of the
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64
     double Lf[NB];
 #pragma unroll
     for (int I = 0; I < NB; ++I) Lf[I] = Lt[(4 * s + lk) * NP + 16 * I + lr];
-    if (coulomb) {
+    if (P > 1 && coulomb) {
 #pragma unroll
       for (int I = 0; I < NB; ++I) {
         cr = fma(Lf[I], tf[I].x, cr);
@@ -209,19 +211,35 @@ __global__ __launch_bounds__(512, 1) void energy_full_kernel(int M, int n, int64
       for (int I = 0; I < NB; ++I) {
         if (I % S == sl) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) sDiag[wv][I / S][(4 * v + lk) * 16 + lr] = make_double2(gRe[I / S][v], gIm[I / S][v]);
+          for (int v = 0; v < 4; ++v) {
+            sDiag[wv][I / S][(4 * v + lk) * 16 + lr] = make_double2(gRe[I / S][v], gIm[I / S][v]);
+            // one pass: the trace from this slice's diagonal blocks
+            if (P == 1 && 4 * v + lk == lr) {
+              cr += gRe[I / S][v];
+              ci += gIm[I / S][v];
+            }
+          }
         }
       }
-      if (coulomb) {
+      if (P == 1) {
+        // the two halves' diagonal traces, combined through LDS by half 0
+        const double tr = wave_sum_lane0(cr), ti = wave_sum_lane0(ci);
+        if (lane == 0) sK[wv] = make_double2(tr, ti);
+      } else if (coulomb) {
         const double tr = wave_sum_lane0(cr), ti = wave_sum_lane0(ci);
         if (lane == 0) {
           accJr += tr * tr - ti * ti;
           accJi += 2.0 * tr * ti;
         }
-        cr = 0.0;
-        ci = 0.0;
       }
+      cr = 0.0;
+      ci = 0.0;
       __syncthreads();
+      if (P == 1 && h == 0 && lane == 0) {
+        const double tr = sK[wv].x + sK[wv + 1].x, ti = sK[wv].y + sK[wv + 1].y;
+        accJr += tr * tr - ti * ti;
+        accJi += 2.0 * tr * ti;
+      }
 #pragma unroll
       for (int I = 0; I < NB; ++I) {
         if (I % S == sl) {
