@@ -100,6 +100,67 @@ def measured_traffic(kernel, eps):
         return None
 
 
+KERNEL_SOURCES = {
+    "overlap_kernel": "green_theta.hip", "invert_kernel": "green_theta.hip", "apply_kernel": "green_theta.hip",
+    "lo_pass1_kernel": "energy_lo.hip", "lo_pass1_reg_kernel": "energy_lo.hip", "lo_pass2_kernel": "energy_lo.hip",
+    "reduce_partials_kernel": "energy_full.hip", "energy_full_kernel": "energy_full.hip",
+}
+
+
+def _counter_rows(path):
+    """(kernel base name, grid, counter, value) rows of every rocprofv3
+    counter-collection CSV under `path`."""
+    import csv
+    import glob
+    rows = []
+    for fn in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"].split("(")[0].split("<")[0].split("::")[-1].strip()
+                rows.append((name, int(r["Grid_Size"]), r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def write_traffic_table(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, eps, workload, out_path):
+    """HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch), scaled by what the same counters read
+    for a plain device copy of known size, with the sha256 of each kernel's
+    source so that stale numbers are never used."""
+    import hashlib
+    copy_bytes = None
+
+    def per_kernel(path, counter):
+        acc = {}
+        for name, grid, cname, val in _counter_rows(path):
+            if cname.startswith(counter):
+                acc.setdefault((name, grid), []).append(val * 1024.0)
+        return {k: float(np.mean(v)) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+    cf, _ = per_kernel(copy_fetch_dir, "FETCH_SIZE")
+    cw, _ = per_kernel(copy_write_dir, "WRITE_SIZE")
+    copy_key = max(cf, key=lambda k: cf[k])        # the 1 GiB copy is the largest dispatch
+    copy_bytes = 1024.0 ** 3
+    fetch_scale = copy_bytes / cf[copy_key]
+    write_scale = copy_bytes / cw[max(cw, key=lambda k: cw[k])]
+    fe, nf = per_kernel(fetch_dir, "FETCH_SIZE")
+    wr, _ = per_kernel(write_dir, "WRITE_SIZE")
+    table = {"workload": workload, "epsilon": eps, "fetch_scale": fetch_scale, "write_scale": write_scale,
+             "kernels": {}}
+    for (name, grid), v in sorted(fe.items()):
+        if name not in KERNEL_SOURCES:
+            continue
+        src = os.path.join("paper_2202_00832_amd", "csrc", KERNEL_SOURCES[name])
+        with open(os.path.join(ROOT, src), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        ent = table["kernels"].setdefault(name, {"launches": [], "source": src, "source_sha256": sha})
+        ent["launches"].append({"grid": grid, "dispatches": nf[(name, grid)], "fetch_kib": v / 1024.0,
+                                "write_kib": wr.get((name, grid), 0.0) / 1024.0,
+                                "read_bytes": v * fetch_scale, "write_bytes": wr.get((name, grid), 0.0) * write_scale})
+    with open(out_path, "w") as f:
+        json.dump(table, f, indent=1)
+    return table
+
+
 def roofline_of(name, work, ms_per_launch):
     bound, flops, nbytes = work[name]
     sec = ms_per_launch * 1e-3
@@ -695,7 +756,19 @@ def main():
                     help="skip the half-rotated ERI route (Eq. 17; its pair blocks take 2.3 GB)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run one plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--traffic-table", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="only write profiles/hbm_traffic.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of "
+                         "this bench (one threshold, --eps) and of --calibrate-copy-mib 1024; no GPU needed")
     args = ap.parse_args()
+    if args.traffic_table:
+        eps = float(args.eps) if args.eps else EPS_SWEEP[0]
+        t = write_traffic_table(*args.traffic_table, eps, "chain-M400-n60-w512",
+                                os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+        for k, v in t["kernels"].items():
+            for ln in v["launches"]:
+                print("%-24s grid %9d  read %8.1f MB  write %8.1f MB" % (k, ln["grid"], ln["read_bytes"] / 1e6,
+                                                                          ln["write_bytes"] / 1e6))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the walker batch of this workload is a single GPU's share, "
               "and no multi-GPU path is built (got --gpus %d)" % args.gpus, file=sys.stderr)
