@@ -184,6 +184,28 @@ int lo_factors_info(const lo_factors* f, int64_t* M, int64_t* n_occ, int32_t* ra
  * Synchronous. */
 int lo_factors_export(const lo_factors* f, double* rows, int64_t* row_offset);
 
+/* Kind of a factor set, for lo_factors_import: flags = 0 for factors of the
+ * exact SVD (build_lo_factors), LO_FACTORS_RANDOMIZED for the randomized
+ * set-up (its diagonal-pair Vbar rows are kept apart from Ubar^T). */
+#define LO_FACTORS_RANDOMIZED 1u
+int lo_factors_flags(const lo_factors* f, unsigned* flags);
+
+/* Rebuilds a factor handle from what lo_factors_info, lo_factors_discarded,
+ * lo_factors_export and lo_factors_flags return (a checkpoint of the set-up,
+ * Sec. 2.3.1: the SVDs need not be repeated).
+ *   M, n_occ, n_chol : shapes of the set the factors were built from
+ *   ranks            : host int32 [n_occ][n_occ], symmetric, 0..M
+ *   row_offset       : host int64 [n_occ][n_occ]; the pairs i <= j with K > 0
+ *                      must tile rows 0 .. sum 2 K - 1 (entries i > j ignored)
+ *   first_dropped, discarded : host double [n_occ][n_occ] or NULL (zeros)
+ *   rows             : host double [total_rows][M] as lo_factors_export
+ *   flags            : lo_factors_flags of the exported handle
+ * The handle computes the same energies, bit for bit, as the exported one.
+ * Synchronous; library-owned like build_lo_factors' handles. */
+int lo_factors_import(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const int32_t* ranks,
+                      const int64_t* row_offset, const double* first_dropped, const double* discarded,
+                      const double* rows, unsigned flags, lo_factors** out);
+
 /* -------------------------------------------------------- per-walker calls */
 
 /* Green's-function intermediate Q of Eq. 15 ("theta"):

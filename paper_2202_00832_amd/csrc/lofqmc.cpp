@@ -54,6 +54,7 @@ struct lo_factors {
   double* d_entw = nullptr;            // [n_ent]: pair weight (1 for i = j, 2 for i < j; 0 for padding)
   float* d_orbfeat = nullptr;          // [n][2]: sum_j K_ij, sum_j discarded mass (residual features)
   double* d_grad = nullptr;            // [M][n]: gradient of the dropped energy at the trial (lo_residual_prepare)
+  bool diag_u_only = true;             // exact SVD: the Vbar rows of a diagonal pair equal its Ubar^T rows
 };
 
 struct lo_md {
@@ -368,6 +369,183 @@ namespace {
 // and Tropp 2011, Alg. 4.4) with the caller's test matrix omega [M][L] (row-
 // major, device) and `power_iters` power steps, then the SVD of the L x M
 // projection.
+// Second half of a factor handle: the reduced-precision copies of the rows
+// and the tables of the two energy passes, from M, n, X, ranks, first_dropped,
+// discarded, row_offset, total_rows and the device rows.  diag_u_only: the
+// rows came from the exact SVD, so the Vbar rows of a diagonal pair equal its
+// Ubar^T rows.  On failure frees f and returns the error.
+int finish_factors(lo_ctx* ctx, lo_factors* f, bool diag_u_only) {
+  const int64_t M = f->M, n = f->n, total_rows = f->total_rows;
+  int rc = LO_OK;
+  auto cleanup = [&]() { (void)hipStreamSynchronize(ctx->stream); };
+#define TRY_HIP(call)                                                                           \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      rc = fail(ctx, LO_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));                   \
+      cleanup();                                                                                \
+      free_factors(f);                                                                          \
+      return rc;                                                                                \
+    }                                                                                           \
+  } while (0)
+#define TRY_ALLOC(ptr, bytes)                                                                   \
+  do {                                                                                          \
+    if (hipMalloc(&(ptr), (bytes)) != hipSuccess) {                                             \
+      ptr = nullptr;                                                                            \
+      rc = fail(ctx, LO_ENOMEM, "device allocation of %zu bytes failed", (size_t)(bytes));      \
+      cleanup();                                                                                \
+      free_factors(f);                                                                          \
+      return rc;                                                                                \
+    }                                                                                           \
+  } while (0)
+  f->diag_u_only = diag_u_only;
+  if (total_rows > 0) {
+    // FP32 and split-BF16 copies for the reduced-precision energy
+    const size_t Mp = (size_t)lofqmc::lp_padded_m((int)M);
+    TRY_ALLOC(f->rows32, sizeof(float) * (size_t)total_rows * Mp);
+    TRY_ALLOC(f->rowsbf, sizeof(__bf16) * 2 * (size_t)total_rows * Mp);
+    TRY_HIP(lofqmc::launch_factor_rows_lp(ctx->stream, (int)M, total_rows, f->rows, f->rows32, f->rowsbf));
+  }
+
+  // ---- tables of the two energy passes
+  // A diagonal block Y^[ii] is symmetric positive semidefinite, so every left
+  // singular vector with sigma > 0 equals its right one (Y v = sigma u and
+  // Y v = sigma v): Vbar^[ii] = Ubar^[ii]T and QR_i = QL_i.  With the exact SVD
+  // the pass-1 product of orbital i then takes only the Ubar^T rows of its
+  // diagonal pair; the randomized SVD only approximates the singular vectors,
+  // so its factors keep both.
+  auto out_rows = [&](int o, int k) -> int64_t {
+    const int64_t K = f->ranks[o * n + k];
+    return (o == k && diag_u_only) ? K : 2 * K;
+  };
+  std::vector<int64_t> obase(n + 1, 0);
+  std::vector<int64_t> loc(n * n, 0);  // local output row of pair (o, k) within orbital o
+  for (int o = 0; o < n; ++o) {
+    int64_t R = 0;
+    for (int k = 0; k < n; ++k) {
+      loc[o * n + k] = R;
+      R += out_rows(o, k);
+    }
+    obase[o + 1] = obase[o] + R;
+  }
+  f->n_out_rows = obase[n];
+  if (f->n_out_rows > std::numeric_limits<int>::max()) {
+    rc = fail(ctx, LO_EUNSUPPORTED, "too many factor rows");
+    cleanup();
+    free_factors(f);
+    return rc;
+  }
+  std::vector<int> rowidx(f->n_out_rows);
+  for (int o = 0; o < n; ++o) {
+    for (int k = 0; k < n; ++k) {
+      const int i = std::min(o, k), j = std::max(o, k);
+      const int64_t src = f->row_offset[i * n + j];
+      const int64_t cnt = out_rows(o, k);
+      for (int64_t q = 0; q < cnt; ++q) rowidx[obase[o] + loc[o * n + k] + q] = (int)(src + q);
+    }
+  }
+  // pass-1 tiles: each orbital's rows split into near-equal tiles of at most
+  // `cap` rows, listed by orbital as [orbital][first row][row count], then the
+  // first tile of each block of lo_orbital_block() orbitals
+  auto build_tiles = [&](int64_t cap, int* ntiles, int* nblk, int* tmax) {
+    std::vector<int> t_orb, t_row0, t_nrows;
+    for (int o = 0; o < n; ++o) {
+      const int64_t R = obase[o + 1] - obase[o];
+      const int64_t ntile = (R + cap - 1) / cap;
+      for (int64_t q = 0; q < ntile; ++q) {
+        const int64_t a = obase[o] + R * q / ntile, b = obase[o] + R * (q + 1) / ntile;
+        t_orb.push_back(o);
+        t_row0.push_back((int)a);
+        t_nrows.push_back((int)(b - a));
+      }
+    }
+    *ntiles = (int)t_orb.size();
+    std::vector<int> tiles;
+    tiles.insert(tiles.end(), t_orb.begin(), t_orb.end());
+    tiles.insert(tiles.end(), t_row0.begin(), t_row0.end());
+    tiles.insert(tiles.end(), t_nrows.begin(), t_nrows.end());
+    const int ob = lofqmc::lo_orbital_block();
+    *nblk = (int)((n + ob - 1) / ob);
+    std::vector<int> blk(*nblk + 1, *ntiles);
+    int t = 0;
+    for (int b = 0; b < *nblk; ++b) {
+      while (t < *ntiles && t_orb[t] < b * ob) ++t;
+      blk[b] = t;
+    }
+    *tmax = 0;
+    for (int b = 0; b < *nblk; ++b) *tmax = std::max(*tmax, blk[b + 1] - blk[b]);
+    tiles.insert(tiles.end(), blk.begin(), blk.end());
+    return tiles;
+  };
+  // FP64 pass 1: 384-row tiles (16 waves) when an orbital touches more than
+  // 192 rows and M is a multiple of 16, so each orbital stays one tile
+  int64_t rmax = 0;
+  for (int o = 0; o < n; ++o) rmax = std::max<int64_t>(rmax, obase[o + 1] - obase[o]);
+  f->tile_rows = (rmax > lofqmc::lo_tile_rows() && M % 16 == 0) ? lofqmc::lo_wide_tile_rows()
+                                                                 : lofqmc::lo_tile_rows();
+  const std::vector<int> tiles = build_tiles(f->tile_rows, &f->ntiles, &f->nblk, &f->tmax);
+  const std::vector<int> tiles_lp = build_tiles(lofqmc::lo_lp_tile_rows(), &f->ntiles_lp, &f->nblk_lp, &f->tmax_lp);
+  // pass-2 entries: one per rank row K of every stored pair i <= j, the
+  // output rows of QL_i, QR_j (Coulomb) and QL_j, QR_i (exchange), padded
+  // with weight-0 entries to whole chunks
+  std::vector<int> e_li, e_rj, e_lj, e_ri;
+  std::vector<double> e_w;
+  int nstored = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int j = i; j < n; ++j) {
+      const int K = f->ranks[i * n + j];
+      if (K == 0) continue;
+      ++nstored;
+      const int64_t oi = obase[i] + loc[i * n + j], oj = obase[j] + loc[j * n + i];
+      // the QR rows follow the QL rows, or are the QL rows (diagonal, exact SVD)
+      const int64_t vr = (i == j && diag_u_only) ? 0 : K;
+      for (int k = 0; k < K; ++k) {
+        e_li.push_back((int)(oi + k));
+        e_rj.push_back((int)(oj + vr + k));
+        e_lj.push_back((int)(oj + k));
+        e_ri.push_back((int)(oi + vr + k));
+        e_w.push_back(i == j ? 1.0 : 2.0);
+      }
+    }
+  }
+  f->npairs = nstored;
+  const int ech = lofqmc::lo_pass2_chunk();
+  while (e_w.size() % ech) {
+    e_li.push_back(0);
+    e_rj.push_back(0);
+    e_lj.push_back(0);
+    e_ri.push_back(0);
+    e_w.push_back(0.0);
+  }
+  f->n_ent = (int64_t)e_w.size();
+  std::vector<int> ent(e_li);
+  ent.insert(ent.end(), e_rj.begin(), e_rj.end());
+  ent.insert(ent.end(), e_lj.begin(), e_lj.end());
+  ent.insert(ent.end(), e_ri.begin(), e_ri.end());
+  std::vector<float> orbfeat(2 * n, 0.0f);
+  for (int i = 0; i < n; ++i) {
+    double ks = 0.0, ms = 0.0;
+    for (int j = 0; j < n; ++j) {
+      ks += f->ranks[i * n + j];
+      ms += f->discarded[i * n + j];
+    }
+    orbfeat[2 * i] = (float)ks;
+    orbfeat[2 * i + 1] = (float)ms;
+  }
+  if ((rc = upload(ctx, &f->d_rowidx, rowidx)) || (rc = upload(ctx, &f->d_tiles, tiles)) ||
+      (rc = upload(ctx, &f->d_tiles_lp, tiles_lp)) ||
+      (rc = upload(ctx, &f->d_ent, ent)) || (rc = upload(ctx, &f->d_entw, e_w)) ||
+      (rc = upload(ctx, &f->d_orbfeat, orbfeat))) {
+    cleanup();
+    free_factors(f);
+    return rc;
+  }
+  TRY_HIP(hipStreamSynchronize(ctx->stream));
+  return LO_OK;
+#undef TRY_HIP
+#undef TRY_ALLOC
+}
+
 int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const double* lbar, double epsilon,
                   int64_t L, int power_iters, const double* omega, lo_factors** out) {
   if (!ctx) return LO_EINVAL;
@@ -610,149 +788,10 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
                              hipMemcpyDeviceToDevice, ctx->stream));
       at += chunk_rows[c];
     }
-    // FP32 and split-BF16 copies for the reduced-precision energy
-    const size_t Mp = (size_t)lofqmc::lp_padded_m((int)M);
-    TRY_ALLOC(f->rows32, sizeof(float) * (size_t)total_rows * Mp);
-    TRY_ALLOC(f->rowsbf, sizeof(__bf16) * 2 * (size_t)total_rows * Mp);
-    TRY_HIP(lofqmc::launch_factor_rows_lp(ctx->stream, (int)M, total_rows, f->rows, f->rows32, f->rowsbf));
   }
-
-  // ---- tables of the two energy passes
-  // A diagonal block Y^[ii] is symmetric positive semidefinite, so every left
-  // singular vector with sigma > 0 equals its right one (Y v = sigma u and
-  // Y v = sigma v): Vbar^[ii] = Ubar^[ii]T and QR_i = QL_i.  With the exact SVD
-  // the pass-1 product of orbital i then takes only the Ubar^T rows of its
-  // diagonal pair; the randomized SVD only approximates the singular vectors,
-  // so its factors keep both.
-  const bool diag_u_only = (L == 0);
-  auto out_rows = [&](int o, int k) -> int64_t {
-    const int64_t K = f->ranks[o * n + k];
-    return (o == k && diag_u_only) ? K : 2 * K;
-  };
-  std::vector<int64_t> obase(n + 1, 0);
-  std::vector<int64_t> loc(n * n, 0);  // local output row of pair (o, k) within orbital o
-  for (int o = 0; o < n; ++o) {
-    int64_t R = 0;
-    for (int k = 0; k < n; ++k) {
-      loc[o * n + k] = R;
-      R += out_rows(o, k);
-    }
-    obase[o + 1] = obase[o] + R;
-  }
-  f->n_out_rows = obase[n];
-  if (f->n_out_rows > std::numeric_limits<int>::max()) {
-    rc = fail(ctx, LO_EUNSUPPORTED, "too many factor rows");
-    cleanup();
-    free_factors(f);
-    return rc;
-  }
-  std::vector<int> rowidx(f->n_out_rows);
-  for (int o = 0; o < n; ++o) {
-    for (int k = 0; k < n; ++k) {
-      const int i = std::min(o, k), j = std::max(o, k);
-      const int64_t src = f->row_offset[i * n + j];
-      const int64_t cnt = out_rows(o, k);
-      for (int64_t q = 0; q < cnt; ++q) rowidx[obase[o] + loc[o * n + k] + q] = (int)(src + q);
-    }
-  }
-  // pass-1 tiles: each orbital's rows split into near-equal tiles of at most
-  // `cap` rows, listed by orbital as [orbital][first row][row count], then the
-  // first tile of each block of lo_orbital_block() orbitals
-  auto build_tiles = [&](int64_t cap, int* ntiles, int* nblk, int* tmax) {
-    std::vector<int> t_orb, t_row0, t_nrows;
-    for (int o = 0; o < n; ++o) {
-      const int64_t R = obase[o + 1] - obase[o];
-      const int64_t ntile = (R + cap - 1) / cap;
-      for (int64_t q = 0; q < ntile; ++q) {
-        const int64_t a = obase[o] + R * q / ntile, b = obase[o] + R * (q + 1) / ntile;
-        t_orb.push_back(o);
-        t_row0.push_back((int)a);
-        t_nrows.push_back((int)(b - a));
-      }
-    }
-    *ntiles = (int)t_orb.size();
-    std::vector<int> tiles;
-    tiles.insert(tiles.end(), t_orb.begin(), t_orb.end());
-    tiles.insert(tiles.end(), t_row0.begin(), t_row0.end());
-    tiles.insert(tiles.end(), t_nrows.begin(), t_nrows.end());
-    const int ob = lofqmc::lo_orbital_block();
-    *nblk = (int)((n + ob - 1) / ob);
-    std::vector<int> blk(*nblk + 1, *ntiles);
-    int t = 0;
-    for (int b = 0; b < *nblk; ++b) {
-      while (t < *ntiles && t_orb[t] < b * ob) ++t;
-      blk[b] = t;
-    }
-    *tmax = 0;
-    for (int b = 0; b < *nblk; ++b) *tmax = std::max(*tmax, blk[b + 1] - blk[b]);
-    tiles.insert(tiles.end(), blk.begin(), blk.end());
-    return tiles;
-  };
-  // FP64 pass 1: 384-row tiles (16 waves) when an orbital touches more than
-  // 192 rows and M is a multiple of 16, so each orbital stays one tile
-  int64_t rmax = 0;
-  for (int o = 0; o < n; ++o) rmax = std::max<int64_t>(rmax, obase[o + 1] - obase[o]);
-  f->tile_rows = (rmax > lofqmc::lo_tile_rows() && M % 16 == 0) ? lofqmc::lo_wide_tile_rows()
-                                                                 : lofqmc::lo_tile_rows();
-  const std::vector<int> tiles = build_tiles(f->tile_rows, &f->ntiles, &f->nblk, &f->tmax);
-  const std::vector<int> tiles_lp = build_tiles(lofqmc::lo_lp_tile_rows(), &f->ntiles_lp, &f->nblk_lp, &f->tmax_lp);
-  // pass-2 entries: one per rank row K of every stored pair i <= j, the
-  // output rows of QL_i, QR_j (Coulomb) and QL_j, QR_i (exchange), padded
-  // with weight-0 entries to whole chunks
-  std::vector<int> e_li, e_rj, e_lj, e_ri;
-  std::vector<double> e_w;
-  int nstored = 0;
-  for (int i = 0; i < n; ++i) {
-    for (int j = i; j < n; ++j) {
-      const int K = f->ranks[i * n + j];
-      if (K == 0) continue;
-      ++nstored;
-      const int64_t oi = obase[i] + loc[i * n + j], oj = obase[j] + loc[j * n + i];
-      // the QR rows follow the QL rows, or are the QL rows (diagonal, exact SVD)
-      const int64_t vr = (i == j && diag_u_only) ? 0 : K;
-      for (int k = 0; k < K; ++k) {
-        e_li.push_back((int)(oi + k));
-        e_rj.push_back((int)(oj + vr + k));
-        e_lj.push_back((int)(oj + k));
-        e_ri.push_back((int)(oi + vr + k));
-        e_w.push_back(i == j ? 1.0 : 2.0);
-      }
-    }
-  }
-  f->npairs = nstored;
-  const int ech = lofqmc::lo_pass2_chunk();
-  while (e_w.size() % ech) {
-    e_li.push_back(0);
-    e_rj.push_back(0);
-    e_lj.push_back(0);
-    e_ri.push_back(0);
-    e_w.push_back(0.0);
-  }
-  f->n_ent = (int64_t)e_w.size();
-  std::vector<int> ent(e_li);
-  ent.insert(ent.end(), e_rj.begin(), e_rj.end());
-  ent.insert(ent.end(), e_lj.begin(), e_lj.end());
-  ent.insert(ent.end(), e_ri.begin(), e_ri.end());
-  std::vector<float> orbfeat(2 * n, 0.0f);
-  for (int i = 0; i < n; ++i) {
-    double ks = 0.0, ms = 0.0;
-    for (int j = 0; j < n; ++j) {
-      ks += f->ranks[i * n + j];
-      ms += f->discarded[i * n + j];
-    }
-    orbfeat[2 * i] = (float)ks;
-    orbfeat[2 * i + 1] = (float)ms;
-  }
-  if ((rc = upload(ctx, &f->d_rowidx, rowidx)) || (rc = upload(ctx, &f->d_tiles, tiles)) ||
-      (rc = upload(ctx, &f->d_tiles_lp, tiles_lp)) ||
-      (rc = upload(ctx, &f->d_ent, ent)) || (rc = upload(ctx, &f->d_entw, e_w)) ||
-      (rc = upload(ctx, &f->d_orbfeat, orbfeat))) {
-    cleanup();
-    free_factors(f);
-    return rc;
-  }
-  TRY_HIP(hipStreamSynchronize(ctx->stream));
   cleanup();
+  const int frc = finish_factors(ctx, f, L == 0);
+  if (frc) return frc;
   *out = f;
   return LO_OK;
 #undef TRY_HIP
@@ -913,6 +952,78 @@ int lo_factors_export(const lo_factors* f, double* rows, int64_t* row_offset) {
     if (hipMemcpy(rows, f->rows, sizeof(double) * (size_t)f->total_rows * f->M, hipMemcpyDeviceToHost) != hipSuccess)
       return LO_EHIP;
   }
+  return LO_OK;
+}
+
+int lo_factors_import(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const int32_t* ranks,
+                      const int64_t* row_offset, const double* first_dropped, const double* discarded,
+                      const double* rows, unsigned flags, lo_factors** out) {
+  if (!ctx) return LO_EINVAL;
+  ctx->err.clear();
+  if (!out) return fail(ctx, LO_EINVAL, "null output handle");
+  *out = nullptr;
+  if (M <= 0 || n_occ <= 0 || n_chol <= 0) return fail(ctx, LO_EINVAL, "sizes must be positive");
+  if (n_occ > M) return fail(ctx, LO_EINVAL, "n_occ exceeds M");
+  if (M > 8192 || n_occ > 4096) return fail(ctx, LO_EUNSUPPORTED, "M above 8192 or n_occ above 4096");
+  if (flags & ~(unsigned)LO_FACTORS_RANDOMIZED) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  if (!ranks || !row_offset) return fail(ctx, LO_EINVAL, "null ranks or row_offset");
+  const int64_t n = n_occ;
+  // the stored pairs i <= j must tile [0, total_rows) with 2 K rows each
+  int64_t total = 0;
+  std::vector<std::pair<int64_t, int64_t>> spans;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const int32_t K = ranks[i * n + j];
+      if (K < 0 || K > M || K != ranks[j * n + i]) return fail(ctx, LO_EINVAL, "ranks must be symmetric, 0..M");
+      if (j < i) continue;
+      if (K > 0) {
+        const int64_t off = row_offset[i * n + j];
+        if (off < 0) return fail(ctx, LO_EINVAL, "pair (%d, %d): negative row offset", (int)i, (int)j);
+        spans.emplace_back(off, 2 * (int64_t)K);
+      }
+      total += 2 * (int64_t)K;
+    }
+  std::sort(spans.begin(), spans.end());
+  int64_t at = 0;
+  for (const auto& sp : spans) {
+    if (sp.first != at) return fail(ctx, LO_EINVAL, "row offsets do not tile the rows");
+    at += sp.second;
+  }
+  if (total > 0 && !rows) return fail(ctx, LO_EINVAL, "null rows");
+  lo_factors* f = new (std::nothrow) lo_factors();
+  if (!f) return fail(ctx, LO_ENOMEM, "host allocation failed");
+  f->M = M;
+  f->n = n;
+  f->X = n_chol;
+  f->total_rows = total;
+  f->ranks.assign(ranks, ranks + n * n);
+  f->row_offset.assign(row_offset, row_offset + n * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) f->row_offset[i * n + j] = -1;
+  f->first_dropped.assign(n * n, 0.0);
+  f->discarded.assign(n * n, 0.0);
+  if (first_dropped) f->first_dropped.assign(first_dropped, first_dropped + n * n);
+  if (discarded) f->discarded.assign(discarded, discarded + n * n);
+  if (total > 0) {
+    if (hipMalloc(&f->rows, sizeof(double) * (size_t)total * M) != hipSuccess) {
+      f->rows = nullptr;
+      free_factors(f);
+      return fail(ctx, LO_ENOMEM, "device allocation of the factor rows failed");
+    }
+    if (hipMemcpy(f->rows, rows, sizeof(double) * (size_t)total * M, hipMemcpyHostToDevice) != hipSuccess) {
+      free_factors(f);
+      return fail(ctx, LO_EHIP, "upload of the factor rows failed");
+    }
+  }
+  const int rc = finish_factors(ctx, f, (flags & LO_FACTORS_RANDOMIZED) == 0);
+  if (rc) return rc;
+  *out = f;
+  return LO_OK;
+}
+
+int lo_factors_flags(const lo_factors* f, unsigned* flags) {
+  if (!f || !flags) return LO_EINVAL;
+  *flags = f->diag_u_only ? 0u : (unsigned)LO_FACTORS_RANDOMIZED;
   return LO_OK;
 }
 

@@ -21,6 +21,7 @@ LO_OK, LO_EINVAL, LO_ENOMEM, LO_EHIP, LO_EUNSUPPORTED, LO_ESOLVER = 0, -1, -2, -
 LO_FP64, LO_FP32, LO_BF16X3, LO_BF16 = 0, 1, 2, 3
 LO_THETA_ORBITAL_MAJOR = 1
 LO_EXACT_COULOMB = 2
+LO_FACTORS_RANDOMIZED = 1
 RESIDUAL_NFEAT = 4   # per-orbital features of the learned residual
 _NAMES = {0: "LO_OK", -1: "LO_EINVAL", -2: "LO_ENOMEM", -3: "LO_EHIP", -4: "LO_EUNSUPPORTED", -5: "LO_ESOLVER"}
 
@@ -41,6 +42,9 @@ _SIGS = {
     "lo_factors_destroy": (ctypes.c_int, [_c_p]),
     "lo_factors_info": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "lo_factors_export": (ctypes.c_int, [_c_p, _c_p, _c_p]),
+    "lo_factors_flags": (ctypes.c_int, [_c_p, _c_p]),
+    "lo_factors_import": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p, _c_p, _c_p, ctypes.c_uint,
+                                         ctypes.POINTER(_c_p)]),
     "green_theta": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _c_p, _c_p, _c_p, _c_p, _c_p, ctypes.c_uint]),
     "local_energy_full": (ctypes.c_int, [_c_p, _i64, _i64, _i64, _i64, _c_p, _c_p, _c_p, ctypes.c_int,
                                          ctypes.c_uint, _c_p]),
@@ -192,12 +196,29 @@ class MdTrial:
 class Factors:
     """Owner of a lo_factors handle (device storage held by the library)."""
 
-    def __init__(self, handle: int):
+    def __init__(self, handle: int, n_chol: int = 0):
         self._h = ctypes.c_void_p(handle)
         M = ctypes.c_int64()
         n = ctypes.c_int64()
         load().lo_factors_info(self._h, ctypes.byref(M), ctypes.byref(n), None, None, None, None)
         self.M, self.n_occ = M.value, n.value
+        self.n_chol = n_chol
+
+    def checkpoint(self) -> dict:
+        """Everything lo_factors_import needs, as numpy arrays (np.savez-able)."""
+        inf = self.info()
+        M, n = inf["M"], inf["n_occ"]
+        rows = np.zeros((inf["total_rows"], M), dtype=np.float64)
+        off = np.zeros((n, n), dtype=np.int64)
+        lib = load()
+        rc = lib.lo_factors_export(self._h, rows.ctypes.data if rows.size else None, off.ctypes.data)
+        if rc != LO_OK:
+            raise LoError(rc, "lo_factors_export failed")
+        fl = ctypes.c_uint()
+        lib.lo_factors_flags(self._h, ctypes.byref(fl))
+        return {"M": np.int64(M), "n_occ": np.int64(n), "n_chol": np.int64(self.n_chol), "ranks": inf["ranks"],
+                "row_offset": off, "first_dropped": inf["first_dropped"], "discarded": self.discarded(),
+                "rows": rows, "flags": np.int64(fl.value)}
 
     @property
     def handle(self):
@@ -404,7 +425,23 @@ class Context:
         _check_dev("lbar", lbar, torch.float64, (X, M, n))
         h = ctypes.c_void_p()
         self._check(self._lib.build_lo_factors(self._h, M, n, X, _ptr(lbar), float(epsilon), ctypes.byref(h)))
-        return Factors(h.value)
+        return Factors(h.value, X)
+
+    def import_factors(self, ckpt: dict) -> Factors:
+        """A factor handle from Factors.checkpoint() output (host arrays)."""
+        n = int(ckpt["n_occ"])
+        ranks = np.ascontiguousarray(ckpt["ranks"], dtype=np.int32)
+        off = np.ascontiguousarray(ckpt["row_offset"], dtype=np.int64)
+        fd = np.ascontiguousarray(ckpt["first_dropped"], dtype=np.float64)
+        disc = np.ascontiguousarray(ckpt["discarded"], dtype=np.float64)
+        rows = np.ascontiguousarray(ckpt["rows"], dtype=np.float64)
+        assert ranks.shape == off.shape == fd.shape == disc.shape == (n, n)
+        h = ctypes.c_void_p()
+        self._check(self._lib.lo_factors_import(self._h, int(ckpt["M"]), n, int(ckpt["n_chol"]), ranks.ctypes.data,
+                                                off.ctypes.data, fd.ctypes.data, disc.ctypes.data,
+                                                rows.ctypes.data if rows.size else None, int(ckpt["flags"]),
+                                                ctypes.byref(h)))
+        return Factors(h.value, int(ckpt["n_chol"]))
 
     def build_lo_factors_randomized(self, lbar, epsilon: float, omega, power_iters: int = 2) -> Factors:
         """LO factors from a randomized SVD with the test matrix omega [M][sketch] (float64, device)."""
@@ -415,7 +452,7 @@ class Context:
         h = ctypes.c_void_p()
         self._check(self._lib.build_lo_factors_randomized(self._h, M, n, X, _ptr(lbar), float(epsilon), omega.shape[1],
                                                           int(power_iters), _ptr(omega), ctypes.byref(h)))
-        return Factors(h.value)
+        return Factors(h.value, X)
 
     def build_hr_eri(self, lbar) -> HrEri:
         import torch

@@ -105,6 +105,19 @@ def test_validation_errors_need_no_device(lib):
         assert lib.lo_residual_apply(h, 4, fake, None, math.nan, 0.0, fake) == L.LO_EINVAL
         assert lib.lo_residual_apply(h, 0, None, None, 1.0, 0.0, None) == L.LO_OK
         assert lib.lo_residual_prepare(h, None, 3, fake, fake, None) == L.LO_EINVAL
+        # factor import (checkpoint): shapes, flags and the row tiling are checked first
+        rk = (ctypes.c_int32 * 4)(1, 0, 0, 1)
+        ro = (ctypes.c_int64 * 4)(0, -1, -1, 2)
+        ro_bad = (ctypes.c_int64 * 4)(0, -1, -1, 3)
+        rk_asym = (ctypes.c_int32 * 4)(1, 1, 0, 1)
+        I = lib.lo_factors_import
+        assert I(h, 8, 2, 3, rk, ro, None, None, fake, 0, None) == L.LO_EINVAL               # no output
+        assert I(h, 8, 2, 3, rk, ro_bad, None, None, fake, 0, ctypes.byref(out)) == L.LO_EINVAL   # gap in rows
+        assert I(h, 8, 2, 3, rk_asym, ro, None, None, fake, 0, ctypes.byref(out)) == L.LO_EINVAL  # asymmetric
+        assert I(h, 8, 2, 3, rk, ro, None, None, None, 0, ctypes.byref(out)) == L.LO_EINVAL  # null rows
+        assert I(h, 8, 2, 3, rk, ro, None, None, fake, 4, ctypes.byref(out)) == L.LO_EINVAL  # flags
+        assert I(h, 8, 9, 3, rk, ro, None, None, fake, 0, ctypes.byref(out)) == L.LO_EINVAL  # n > M
+        assert lib.lo_factors_flags(None, None) == L.LO_EINVAL
         # Foster-Boys localization
         assert lib.lo_localize_boys(h, 10, 11, 1, fake, fake, 5, 1e-12, None) == L.LO_EINVAL     # n > M
         assert lib.lo_localize_boys(h, 10, 4, 0, fake, fake, 5, 1e-12, None) == L.LO_EINVAL
