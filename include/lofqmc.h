@@ -51,7 +51,9 @@ enum lo_flags {
   /* local_energy_lo: E_J from the FP64 Cholesky traces Tr(Lbar_g^T theta)
    * (Eq. 16, exact) instead of the LO pair sums; E_K stays LO.  Needs the
    * lbar argument and walker-major theta. */
-  LO_EXACT_COULOMB = 2u
+  LO_EXACT_COULOMB = 2u,
+  /* green_theta: report nearly singular overlaps as info < 0 (see there) */
+  LO_FLAG_SMALL_PIVOT = 4u
 };
 
 /* Arithmetic of the energy contractions.  Reduced precision applies to the
@@ -219,9 +221,14 @@ int lo_factors_import(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, con
  *   log_ovlp : complex [nw] (output; may be NULL)
  *   info     : int32 [nw] (output): 0, or k > 0 if the k-th pivot (1-based)
  *              of O_w is exactly zero; theta_w is then undefined and the
- *              energy calls return NaN for that walker.
- * Always FP64.  Supports n_occ <= 112.
- * "info" reports exact zeros only: a nearly singular O_w is not flagged. */
+ *              energy calls return NaN for that walker.  With flags holding
+ *              LO_FLAG_SMALL_PIVOT also -k < 0 if, with no zero pivot, the
+ *              k-th pivot is the first whose |re| + |im| lies below 2^-40 of
+ *              the largest |re| + |im| of O_w's entries (a nearly singular
+ *              overlap): a warning only, theta_w and the energies are still
+ *              computed (and large).
+ * Always FP64.  Supports n_occ <= 112.  flags: LO_THETA_ORBITAL_MAJOR,
+ * LO_FLAG_SMALL_PIVOT. */
 int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double* trial,
                 const double* phi, double* theta, double* log_ovlp, int32_t* info, unsigned flags);
 
@@ -327,7 +334,7 @@ int lo_hr_info(const lo_hr* h, int64_t* M, int64_t* n_occ, int64_t* bytes);
  *   h      : handle from build_hr_eri (shapes M, n_occ taken from it)
  *   theta  : complex [nw][M][n_occ], or [n_occ][M][nw] with flags
  *            LO_THETA_ORBITAL_MAJOR
- *   info   : int32 [nw] or NULL (walkers with info != 0 get NaN)
+ *   info   : int32 [nw] or NULL (walkers with info > 0 get NaN)
  *   energy : complex [nw][2] (output) = (E_J, E_K)
  * flags may hold LO_THETA_ORBITAL_MAJOR only.  The kernel reads theta columns
  * of 32 walkers, contiguous in the orbital-major layout, which is about twice
@@ -390,7 +397,7 @@ int lo_md_info(const lo_md* md, int64_t* n_occ, int64_t* n_cas, int64_t* n_det, 
  *   theta      : from green_theta with the reference determinant Phi_0
  *                ([M][n_occ] columns 0 .. n_occ-1 of the orbitals), layout
  *                as flags says
- *   info       : from that green_theta call, or NULL; walkers with info != 0
+ *   info       : from that green_theta call, or NULL; walkers with info > 0
  *                get NaN energies
  *   energy     : complex [nw][2], (E_J, E_K) of E2 = sum_d w_d E2^d,
  *                w_d = c_d det(R_d)^2 / sum_d' c_d' det(R_d')^2

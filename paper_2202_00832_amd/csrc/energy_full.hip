@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t nw, int nc
   s2 = wave_sum_lane0(s2);
   s3 = wave_sum_lane0(s3);
   if (lane == 0) {
-    if (info && info[w] != 0) s0 = s1 = s2 = s3 = __builtin_nan("");
+    if (info && info[w] > 0) s0 = s1 = s2 = s3 = __builtin_nan("");   // exact zero pivot
     reinterpret_cast<double4*>(energy)[w] = make_double4(s0, s1, s2, s3);
   }
 }

@@ -159,7 +159,8 @@ __global__ __launch_bounds__(GtCfg<NB>::OT) void overlap_kernel(int M, int n, in
 // ---------------------------------------------------------------------------
 template <int NB>
 __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, double2* __restrict__ O, int* __restrict__ perm,
-                                                          double2* __restrict__ logov, int* __restrict__ info) {
+                                                          double2* __restrict__ logov, int* __restrict__ info,
+                                                          int flag_small) {
   constexpr int NP = 16 * NB;
   constexpr int RPL = (NP + 63) / 64;        // rows per lane
   constexpr int FS = 17;                     // padded row stride of the panel copy (no bank conflicts)
@@ -169,6 +170,8 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
   __shared__ double2 sPivV[NP];
   __shared__ int sZero[2];
   __shared__ int sInvW[NB];                  // per panel: inversions of the pivot order
+  __shared__ int sSmall[NB];                 // per panel: first step with a small pivot (flag_small)
+  __shared__ double sOmax[NB];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const size_t w = w0 + blockIdx.x;
@@ -189,6 +192,29 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
       if (row >= n && row < NP && row == col) e[t][j] = make_double2(1.0, 0.0);
     }
   }
+
+  // with flag_small: the largest |re| + |im| of O's entries, and pivots below
+  // 2^-40 of it mark the overlap as nearly singular (reported as info = -k)
+  double thr = -1.0;
+  if (flag_small) {
+    double m = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int row = lane + 64 * t;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (row < n && 16 * wv + j < n) m = fmax(m, fabs(e[t][j].x) + fabs(e[t][j].y));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if (lane == 0) sOmax[wv] = m;
+    __syncthreads();
+    double om = 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) om = fmax(om, sOmax[q]);
+    thr = om * 0x1p-40;
+  }
+  int small = 0;
 
   int zero = 0;
   for (int b = 0; b < NB; ++b) {
@@ -230,6 +256,7 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
         // columns) from lane pl, read into scalar registers one entry at a time
         const double2 piv = make_double2(readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][c].x : e[0][c].x, pl),
                                          readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][c].y : e[0][c].y, pl));
+        small = (small == 0 && ok && k < n && fabs(piv.x) + fabs(piv.y) < thr) ? k + 1 : small;
         // 1 / |pivot|^2: hardware reciprocal refined by two Newton steps
         const double d = fma(piv.x, piv.x, piv.y * piv.y);
         double r = __builtin_amdgcn_rcp(d);
@@ -289,6 +316,7 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
       if (lane == 0) {
         sZero[buf] = zero;
         sInvW[b] = inversions;
+        sSmall[b] = small;
       }
     }
     __syncthreads();
@@ -380,7 +408,13 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
     la = wave_sum_lane0(la);
     ar = wave_sum_lane0(ar);
     if (lane == 0) {
-      info[w] = zero;
+      // the first small pivot: the panels are swept in order, so the first
+      // panel that recorded one
+      int first_small = 0;
+      if (flag_small && !zero) {
+        for (int b = NB - 1; b >= 0; --b) first_small = sSmall[b] ? sSmall[b] : first_small;
+      }
+      info[w] = zero ? zero : -first_small;
       if (logov) {
         double2 ld;
         if (zero) {
@@ -433,7 +467,7 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, in
   }
   // O_w^{-1} into LDS from R_w in pivot order: O^{-1}[pinv[i]][piv[m]] = R[i][m]
   const double2* Bw = Oinv + w * (size_t)NP * NP;
-  const bool bad = info[w] != 0;
+  const bool bad = info[w] > 0;   // an exact zero pivot (a negative info only warns)
   if (!bad) {
     for (int i = tid; i < NP; i += 512) {
       const int p = perm[w * NP + i];
@@ -536,7 +570,7 @@ size_t green_theta_workspace(int n, int64_t nw) {
 template <int NB>
 static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
                             const double* phi, double* theta, double* logov, int* info, int orbital_major,
-                            double* work, const ProfHook* prof) {
+                            double* work, const ProfHook* prof, int flag_small) {
   double2* O = reinterpret_cast<double2*>(work);
   int* perm = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + gt_perm_offset(n, nw));
   prof_mark(prof, "overlap_kernel");
@@ -546,7 +580,7 @@ static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0,
   if (e != hipSuccess) return e;
   prof_mark(prof, "invert_kernel");
   hipLaunchKernelGGL(invert_kernel<NB>, dim3((unsigned)nwc), dim3(64 * NB), 0, s, n, w0, O, perm, (double2*)logov,
-                     info);
+                     info, flag_small);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t grid = 64 * ((nwc + 63) / 64);
@@ -561,15 +595,15 @@ static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0,
 
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
                               const double* phi, double* theta, double* logov, int* info, int orbital_major,
-                              double* work, const ProfHook* prof) {
+                              double* work, const ProfHook* prof, int flag_small) {
   if (nwc <= 0) return hipSuccess;
-  if (n <= 16) return launch_gt<1>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 32) return launch_gt<2>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 48) return launch_gt<3>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 64) return launch_gt<4>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 80) return launch_gt<5>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
-  if (n <= 96) return launch_gt<6>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
-  return launch_gt<7>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof);
+  if (n <= 16) return launch_gt<1>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
+  if (n <= 32) return launch_gt<2>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
+  if (n <= 48) return launch_gt<3>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
+  if (n <= 64) return launch_gt<4>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
+  if (n <= 80) return launch_gt<5>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
+  if (n <= 96) return launch_gt<6>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
+  return launch_gt<7>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
 }
 
 }  // namespace lofqmc

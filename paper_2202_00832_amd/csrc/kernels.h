@@ -24,9 +24,10 @@ inline void prof_mark(const ProfHook* h, const char* name) {
 // arrays (and by the workspace), so disjoint walker ranges can run on
 // different streams.
 size_t green_theta_workspace(int n, int64_t nw);
+// flag_small: info = -k for the first pivot k below 2^-40 of the largest |re| + |im| of O
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
                               const double* phi, double* theta, double* logov, int* info, int orbital_major,
-                              double* work, const ProfHook* prof);
+                              double* work, const ProfHook* prof, int flag_small);
 
 int full_num_chunks(int64_t X, int64_t nw);
 // passes of the FP64 full route at n orbitals (partial rows = passes x chunks)

@@ -1432,7 +1432,8 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   if (n_occ > kMaxOccTheta) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d", kMaxOccTheta);
   if (M > (1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "M above 2^24");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
-  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(unsigned)(LO_THETA_ORBITAL_MAJOR | LO_FLAG_SMALL_PIVOT))
+    return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   if (nw == 0) return LO_OK;
   if (!trial || !phi || !theta || !info) return fail(ctx, LO_EINVAL, "null array");
   int rc = ensure_ws(ctx, align256(lofqmc::green_theta_workspace((int)n_occ, nw)));
@@ -1440,7 +1441,7 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   ProfScope prof(ctx);
   HIP_OR_FAIL(ctx, lofqmc::launch_green_theta(ctx->stream, (int)M, (int)n_occ, nw, 0, nw, trial, phi, theta, log_ovlp,
                                               info, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0, (double*)ctx->ws,
-                                              prof.get()));
+                                              prof.get(), (flags & LO_FLAG_SMALL_PIVOT) ? 1 : 0));
   return LO_OK;
 }
 
@@ -1558,7 +1559,7 @@ hipError_t batch_enqueue(lo_batch* b, hipStream_t st) {
     const lo_system& s = b->sys[k];
     if (!s.phi) continue;
     e = lofqmc::launch_green_theta(st, (int)s.M, (int)s.n_occ, s.nw, 0, s.nw, s.trial, s.phi, s.theta, nullptr,
-                                   s.info, 0, b->gws[k], nullptr);
+                                   s.info, 0, b->gws[k], nullptr, 0);
     if (e != hipSuccess) return e;
   }
   for (int k = 0; k < b->nsys; ++k) {

@@ -22,6 +22,7 @@ LO_FP64, LO_FP32, LO_BF16X3, LO_BF16 = 0, 1, 2, 3
 LO_THETA_ORBITAL_MAJOR = 1
 LO_EXACT_COULOMB = 2
 LO_FACTORS_RANDOMIZED = 1
+LO_FLAG_SMALL_PIVOT = 4
 RESIDUAL_NFEAT = 4   # per-orbital features of the learned residual
 _NAMES = {0: "LO_OK", -1: "LO_EINVAL", -2: "LO_ENOMEM", -3: "LO_EHIP", -4: "LO_EUNSUPPORTED", -5: "LO_ESOLVER"}
 
@@ -463,8 +464,10 @@ class Context:
         return HrEri(h.value)
 
     # -- per walker ---------------------------------------------------------------
-    def green_theta(self, trial, phi, theta=None, log_ovlp=None, info=None, orbital_major=False):
-        """theta is [nw][M][n] (walker-major) or [n][M][nw] when orbital_major."""
+    def green_theta(self, trial, phi, theta=None, log_ovlp=None, info=None, orbital_major=False,
+                    flag_small_pivots=False):
+        """theta is [nw][M][n] (walker-major) or [n][M][nw] when orbital_major.
+        flag_small_pivots: nearly singular overlaps get info < 0 (a warning)."""
         import torch
         nw, M, n = phi.shape
         _check_dev("trial", trial, torch.float64, (M, n))
@@ -480,7 +483,7 @@ class Context:
         _check_dev("theta", theta, torch.complex128, tshape)
         _check_dev("log_ovlp", log_ovlp, torch.complex128, (nw,))
         _check_dev("info", info, torch.int32, (nw,))
-        flags = LO_THETA_ORBITAL_MAJOR if orbital_major else 0
+        flags = (LO_THETA_ORBITAL_MAJOR if orbital_major else 0) | (LO_FLAG_SMALL_PIVOT if flag_small_pivots else 0)
         self._check(self._lib.green_theta(self._h, M, n, nw, _ptr(trial), _ptr(phi), _ptr(theta), _ptr(log_ovlp),
                                           _ptr(info), flags))
         return theta, log_ovlp, info

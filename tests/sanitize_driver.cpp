@@ -27,7 +27,7 @@ int main() {
   lo_factors* out = nullptr;
   EXPECT(green_theta(h, 0, 2, 1, fake, fake, fake, nullptr, ifake, 0), LO_EINVAL);
   EXPECT(green_theta(h, 200, 113, 1, fake, fake, fake, nullptr, ifake, 0), LO_EUNSUPPORTED);
-  EXPECT(green_theta(h, 8, 2, 3, fake, fake, fake, nullptr, ifake, 6), LO_EINVAL);
+  EXPECT(green_theta(h, 8, 2, 3, fake, fake, fake, nullptr, ifake, 2), LO_EINVAL);
   EXPECT(local_energy_full(h, 200, 113, 3, 4, fake, fake, nullptr, LO_FP64, 0, fake), LO_EUNSUPPORTED);
   EXPECT(local_energy_full(h, 8, 2, 3, 4, fake, fake, nullptr, 7, 0, fake), LO_EINVAL);
   EXPECT(local_energy_lo(h, nullptr, 4, fake, nullptr, LO_FP64, 0, nullptr, fake), LO_EINVAL);

@@ -48,7 +48,7 @@ def test_validation_errors_need_no_device(lib):
         assert lib.green_theta(h, 8, 2, 3, None, fake, fake, None, fake, 0) == L.LO_EINVAL
         assert b"null" in lib.lo_last_error(h)
         assert lib.green_theta(h, 8, 2, 0, None, None, None, None, None, 0) == L.LO_OK   # empty batch
-        assert lib.green_theta(h, 8, 2, 3, fake, fake, fake, None, fake, 6) == L.LO_EINVAL  # unknown flag
+        assert lib.green_theta(h, 8, 2, 3, fake, fake, fake, None, fake, 2) == L.LO_EINVAL  # unknown flag
         assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, 4, None, fake) == L.LO_EINVAL
         # LO_EXACT_COULOMB needs lbar and walker-major theta
         assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, L.LO_EXACT_COULOMB, None, fake) == L.LO_EINVAL

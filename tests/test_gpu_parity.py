@@ -155,6 +155,34 @@ def test_green_theta_zero_pivot_and_nan_energy(ctx):
     assert np.isnan(e_lo[1]).all() and np.isfinite(e_lo[[0, 2]]).all()
 
 
+def test_green_theta_flags_nearly_singular_overlaps(ctx):
+    """LO_FLAG_SMALL_PIVOT: an overlap column scaled to 1e-14 (below 2^-40 of
+    the largest entry) is reported as info = -2 with theta and energies still
+    computed; 1e-10 is not flagged; an exact zero stays info = +2 (NaN
+    energies); without the flag the nearly singular walker reports 0, and the
+    other walkers' theta is the same bit for bit either way."""
+    M, n, X = 20, 3, 4
+    rng = np.random.default_rng(13)
+    chol = synth.random_symmetric_cholesky(M, X, rng)
+    trial = np.eye(M)[:, :n].copy()
+    walkers = synth.noisy_walkers(trial, 5, 0.3, rng)
+    walkers[1, :n, 1] *= 1e-14
+    walkers[2, :n, 1] *= 1e-10
+    walkers[3, :n, 1] = 0.0
+    th_f, _, info_f = ctx.green_theta(dev(trial), dev(walkers), flag_small_pivots=True)
+    th_p, _, info_p = ctx.green_theta(dev(trial), dev(walkers))
+    assert list(host(info_f)) == [0, -2, 0, 2, 0]
+    assert list(host(info_p)) == [0, 0, 0, 2, 0]
+    a, b = host(th_f), host(th_p)
+    for w in (0, 1, 2, 4):
+        assert np.array_equal(a[w].view(np.float64), b[w].view(np.float64))
+    lbar = ctx.build_half_rotated_chol(dev(chol), dev(trial))
+    e = host(ctx.local_energy_full(lbar, th_f, info_f))
+    assert np.isfinite(e[[0, 1, 2, 4]]).all() and np.isnan(e[3]).all()
+    ref = E.e2_cholesky(E.half_rotate(chol, trial), E.green_theta(trial, walkers[1])[0])
+    assert abs(e[1, 0] - ref[0]) <= 1e-9 * max(1.0, abs(ref[0]))    # large but computed
+
+
 # ---------------------------------------------------------------------------
 # local_energy_full
 # ---------------------------------------------------------------------------
