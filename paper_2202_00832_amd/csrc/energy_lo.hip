@@ -11,6 +11,8 @@
 //   J_ij = QL_i . QR_j,   X_ij = QL_j . QR_i   (complex, bilinear),
 // with weight 1 for i = j and 2 for i < j (Y^[ji] = (Y^[ij])^T), and sums
 // E_J = 2 sum J, E_K = -sum X in a fixed order per chunk of rank rows.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -176,24 +178,56 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_reg_kernel(int M, int64_t nw,
 // by 2 (r & 3): the 4 rows x 2 column pairs of one MFMA operand read fall in 8
 // distinct 16-byte bank groups.  Rows past the tile and walkers past nw load
 // a valid address and their outputs are discarded.
-// NWV = 8 waves (192-row tiles, two workgroups per CU) or 16 waves (384-row
-// tiles for orbitals that touch more than 192 rows, one workgroup per CU:
-// each orbital's rows, and its theta column, are then gathered once per
-// walker tile instead of twice).
-template <int NWV>
-__global__ __launch_bounds__(64 * NWV, NWV == 8 ? 2 : 1) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
-                                                             const int* __restrict__ rowidx,
-                                                             const int* __restrict__ tile_orb,
-                                                             const int* __restrict__ tile_row0,
-                                                             const int* __restrict__ tile_nrows,
-                                                             const int* __restrict__ blk, int nblk, int tmax,
-                                                             const double2* __restrict__ theta, int64_t so,
-                                                             int64_t sr, int64_t sw, double2* __restrict__ qbar,
-                                                             int64_t orow, int64_t ow, int nwt) {
+// Eight waves, 192-row tiles, two workgroups per CU (an orbital touching more
+// rows is cut into near-equal tiles, each gathering its theta column again;
+// with the operand reads pipelined as below this measured faster than one
+// 384-row tile in a sixteen-wave workgroup, whose slab barriers no second
+// workgroup on the CU covers).
+// The tile's 4-row groups are dealt to the waves in turn (group g to wave
+// g % 8), so a tile that is not full leaves every SIMD (waves v and v + 4)
+// the same number of groups to within one, instead of idling the SIMDs whose
+// waves hold the end of the tile.
+// BUF: the slab loads go through buffer descriptors (buffer_load_dwordx4 ...
+// lds, 32-bit byte offsets from the factor rows and from the tile's theta
+// slice).  The global-address form (global_load_lds) is a FLAT-encoded
+// instruction that writes LDS; while one is in flight the compiler orders
+// every LDS read by lgkmcnt(0), so the operand reads of the next K-step could
+// not overlap the products of the current one.  The buffer form is counted by
+// vmcnt alone and keeps the graded waits; the global form is kept for byte
+// offsets beyond 2^31 (factor rows or one orbital's theta slice).
+// s_waitcnt vmcnt(0) through the builtin (not inline asm), so the compiler's
+// own wait insertion sees it.  gfx9 encoding: vmcnt in bits 3:0 and 15:14,
+// expcnt 6:4, lgkmcnt 11:8 (expcnt and lgkmcnt at their maximum: no wait)
+__device__ __forceinline__ void wait_vmcnt0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// calls f(integral_constant<q>) for the wave-uniform group count q in 1 .. N
+template <int N, typename F>
+__device__ __forceinline__ void with_group_count(int q, F&& f) {
+  if constexpr (N > 0) {
+    if (q == N)
+      f(std::integral_constant<int, N>{});
+    else
+      with_group_count<N - 1>(q, f);
+  }
+}
+
+template <bool BUF>
+__global__ __launch_bounds__(512) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
+                                                       const int* __restrict__ rowidx,
+                                                       const int* __restrict__ tile_orb,
+                                                       const int* __restrict__ tile_row0,
+                                                       const int* __restrict__ tile_nrows,
+                                                       const int* __restrict__ blk, int nblk, int tmax,
+                                                       const double2* __restrict__ theta, int64_t so,
+                                                       int64_t sr, int64_t sw, double2* __restrict__ qbar,
+                                                       int64_t orow, int64_t ow, int nwt, uint32_t rows_bytes,
+                                                       uint32_t theta_bytes) {
   // two buffers as distinct objects (and the slab loop unrolled by two), so
   // the compiler sees that the reads of one buffer and the loads in flight
   // into the other cannot alias and does not wait for the loads before reading
-  constexpr int TILE = LO_WROWS * NWV;
+  constexpr int NWV = 8;
+  constexpr int QG = LO_QG;
+  constexpr int TILE = LO_TILE_ROWS;
   constexpr int NT = 64 * NWV;
   __shared__ __attribute__((aligned(16))) double sA0[TILE * 16];   // swizzled [row][r]
   __shared__ __attribute__((aligned(16))) double sA1[TILE * 16];
@@ -217,14 +251,16 @@ __global__ __launch_bounds__(64 * NWV, NWV == 8 ? 2 : 1) void lo_pass1_kernel(in
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int rw = LO_WROWS * wv;                // first row of this wave
-  const bool active = rw < nrows;
+  // this wave's groups: rows 4 (wv + NWV q) .. + 3 for q < qv
+  const int ngroups = (nrows + 3) / 4;
+  const int qv = ngroups > wv ? min(QG, (ngroups - wv + NWV - 1) / NWV) : 0;
   const double2* tho = theta + o * so;
 
   // A: TILE rows x 8 column pairs of 16-byte slots, three per thread: slot
   // S = NT k + tid holds row S / 8, column pair (S % 8) ^ (2 (row & 3))
   constexpr int A_LD = TILE * 8 / NT;   // 3
   const double* asrc[A_LD];
+  uint32_t aoffs[A_LD];
 #pragma unroll
   for (int k = 0; k < A_LD; ++k) {
     const int S = NT * k + tid;
@@ -232,89 +268,108 @@ __global__ __launch_bounds__(64 * NWV, NWV == 8 ? 2 : 1) void lo_pass1_kernel(in
     const int cp = (S & 7) ^ (2 * (row & 3));
     const int ar = rowidx[row0 + (row < nrows ? row : 0)];
     asrc[k] = rows + (size_t)ar * M + 2 * cp;
+    aoffs[k] = (uint32_t)(((size_t)ar * M + 2 * cp) * sizeof(double));
   }
-  // B: 16 x 32 slots, slot tid (tid < 512, the first eight waves) holds
-  // r = tid / 32, walker tid % 32 (clamped to a valid walker)
+  // B: 16 x 32 slots, slot tid holds r = tid / 32, walker tid % 32 (clamped
+  // to a valid walker)
   const int64_t bw = w0 + (tid % LO_WT) < nw ? w0 + (tid % LO_WT) : nw - 1;
-  const double2* bsrc = tho + ((tid & 511) / LO_WT) * sr + bw * sw;
+  const double2* bsrc = tho + (tid / LO_WT) * sr + bw * sw;
+  const uint32_t boff = (uint32_t)(((tid / LO_WT) * sr + bw * sw) * sizeof(double2));
+  // raw descriptors (stride 0, byte ranges rows_bytes and theta_bytes; the
+  // third word is the gfx9 default data format); only used when BUF
+  const __amdgpu_buffer_rsrc_t ares = __builtin_amdgcn_make_buffer_rsrc((void*)rows, 0, (int)rows_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t bres = __builtin_amdgcn_make_buffer_rsrc((void*)tho, 0, (int)theta_bytes, 0x00020000);
   auto issue = [&](int c, double* sa, double2* sb) __attribute__((always_inline)) {
 #pragma unroll
-    for (int k = 0; k < A_LD; ++k)
-      __builtin_amdgcn_global_load_lds((const void*)(asrc[k] + 16 * c),
-                                       (__attribute__((address_space(3))) void*)(sa + (NT * k + 64 * wv) * 2), 16, 0,
-                                       0);
-    if (NWV == 8 || wv < 8)
-      __builtin_amdgcn_global_load_lds((const void*)(bsrc + 16 * c * sr),
-                                       (__attribute__((address_space(3))) void*)(sb + 64 * wv), 16, 0, 0);
+    for (int k = 0; k < A_LD; ++k) {
+      auto* dst = (__attribute__((address_space(3))) void*)(sa + (NT * k + 64 * wv) * 2);
+      if constexpr (BUF)
+        // the slab offset goes in soffset (the instruction offset would also
+        // move the LDS destination)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ares, dst, 16, (int)aoffs[k], 16 * c * (int)sizeof(double), 0, 0);
+      else
+        __builtin_amdgcn_global_load_lds((const void*)(asrc[k] + 16 * c), dst, 16, 0, 0);
+    }
+    auto* dst = (__attribute__((address_space(3))) void*)(sb + 64 * wv);
+    if constexpr (BUF)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(bres, dst, 16, (int)boff, (int)(16 * c * sr * (int64_t)sizeof(double2)), 0,
+                                               0);
+    else
+      __builtin_amdgcn_global_load_lds((const void*)(bsrc + 16 * c * sr), dst, 16, 0, 0);
   };
 
-  // acc[q][c]: rows rw + 4q + lk, walker column c (block h = c / 2, part = c % 2)
-  double acc[LO_QG][4];
+  // acc[q][c]: rows 4 (wv + NWV q) + lk, walker column c (block h = c / 2, part = c % 2)
+  double acc[QG][4];
 #pragma unroll
-  for (int q = 0; q < LO_QG; ++q)
+  for (int q = 0; q < QG; ++q)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[q][c] = 0.0;
-  // A operand of this lane: row rw + 4q + (lane & 3) (so row & 3 = lane & 3),
-  // column 4 s4 + lk, i.e. column pair 2 s4 + (lk >> 1), element lk & 1
+  // A operand of this lane: row 4 (wv + NWV q) + (lane & 3) (so row & 3 =
+  // lane & 3), column 4 s4 + lk, i.e. column pair 2 s4 + (lk >> 1), element lk & 1
   const int e2 = 2 * (lane & 3);
-  const int abase = (rw + (lane & 3)) * 16 + (lk & 1);
+  const int abase = (4 * wv + (lane & 3)) * 16 + (lk & 1);
   const int nchunk = M / 16;
-  // 4-row groups of this wave that hold rows of the tile (wave-uniform): the
-  // last busy wave of a tile skips the products of the groups past its end
-  const int qv = active ? min(LO_QG, (nrows - rw + 3) / 4) : 0;
-  auto compute = [&](const double* sa, const double2* sb, int nq) __attribute__((always_inline)) {
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
+  // NQ = qv, the wave-uniform group count, as a constant: one straight run
+  // of MFMAs per count, no tests inside the slab.  The operands of K-step
+  // s4 + 1 are read from LDS into a second register set before the products
+  // of K-step s4 (scheduling barriers keep that order), so a product waits
+  // only for reads issued a whole K-step earlier.
+  auto compute = [&](const double* sa, const double2* sb, auto nqc) __attribute__((always_inline)) {
+    constexpr int NQ = decltype(nqc)::value;
+    double a[2][NQ];
+    double2 b0[2], b1[2];
+    auto read = [&](int s4, int slot) __attribute__((always_inline)) {
       const int rr = 4 * s4 + lk;
-      const double2 b0 = sb[rr * LO_WT + lr];
-      const double2 b1 = sb[rr * LO_WT + 16 + lr];
+      b0[slot] = sb[rr * LO_WT + lr];
+      b1[slot] = sb[rr * LO_WT + 16 + lr];
       const int aoff = abase + 2 * (((2 * s4) ^ e2) | (lk >> 1));
 #pragma unroll
-      for (int q = 0; q < LO_QG; ++q) {
-        if (q < nq) {
-          const double a = sa[aoff + 64 * q];
-          acc[q][0] = mfma4(a, b0.x, acc[q][0]);
-          acc[q][1] = mfma4(a, b0.y, acc[q][1]);
-          acc[q][2] = mfma4(a, b1.x, acc[q][2]);
-          acc[q][3] = mfma4(a, b1.y, acc[q][3]);
-        }
+      for (int q = 0; q < NQ; ++q) a[slot][q] = sa[aoff + 64 * NWV * q];
+    };
+    read(0, 0);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int u = s4 & 1;
+      if (s4 < 3) read(s4 + 1, u ^ 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        acc[q][0] = mfma4(a[u][q], b0[u].x, acc[q][0]);
+        acc[q][1] = mfma4(a[u][q], b0[u].y, acc[q][1]);
+        acc[q][2] = mfma4(a[u][q], b1[u].x, acc[q][2]);
+        acc[q][3] = mfma4(a[u][q], b1[u].y, acc[q][3]);
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
   };
-  // the common case (every group busy) is compiled without the row tests
   auto compute_wave = [&](const double* sa, const double2* sb) __attribute__((always_inline)) {
-    if (qv == LO_QG)
-      compute(sa, sb, LO_QG);
-    else if (qv > 0)
-      compute(sa, sb, qv);
+    with_group_count<QG>(qv, [&](auto nqc) __attribute__((always_inline)) { compute(sa, sb, nqc); });
   };
   issue(0, sA0, sB0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  wait_vmcnt0();
   __syncthreads();
   for (int c = 0; c < nchunk; c += 2) {
     if (c + 1 < nchunk) issue(c + 1, sA1, sB1);
     compute_wave(sA0, sB0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    wait_vmcnt0();
     __syncthreads();
     if (c + 1 < nchunk) {
       if (c + 2 < nchunk) issue(c + 2, sA0, sB0);
       compute_wave(sA1, sB1);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      wait_vmcnt0();
       __syncthreads();
     }
   }
-  // lane holds rows rw + 4q + lk, walker 16h + lr
-  if (active) {
+  // lane holds rows 4 (wv + NWV q) + lk, walker 16h + lr
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t w = w0 + 16 * h + lr;
-      if (w < nw) {
+  for (int h = 0; h < 2; ++h) {
+    const int64_t w = w0 + 16 * h + lr;
+    if (w < nw) {
 #pragma unroll
-        for (int q = 0; q < LO_QG; ++q) {
-          const int lrow = rw + 4 * q + lk;
-          if (lrow < nrows)
-            qbar[(size_t)(row0 + lrow) * orow + w * ow] = make_double2(acc[q][2 * h], acc[q][2 * h + 1]);
-        }
+      for (int q = 0; q < QG; ++q) {
+        const int lrow = 4 * (wv + NWV * q) + lk;
+        if (q < qv && lrow < nrows)
+          qbar[(size_t)(row0 + lrow) * orow + w * ow] = make_double2(acc[q][2 * h], acc[q][2 * h + 1]);
       }
     }
   }
@@ -324,12 +379,11 @@ const char* lo_pass1_name(int M) { return M % 16 == 0 ? "lo_pass1_kernel" : "lo_
 int lo_tile_rows() { return LO_TILE_ROWS; }
 int lo_orbital_block() { return LO_OBLK; }
 
-int lo_wide_tile_rows() { return 2 * LO_TILE_ROWS; }
 
 hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
-                           const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
-                           const double* theta, int orbital_major, double* qbar, int64_t out_walker_stride,
-                           int tile_rows) {
+                           int64_t rows_count, const int* rowidx, const int* tiles, const int* blk, int nblk,
+                           int tmax, const double* theta, int orbital_major, double* qbar,
+                           int64_t out_walker_stride) {
   if (nw <= 0 || ntiles <= 0) return hipSuccess;
   const int nwt = (int)((nw + LO_WT - 1) / LO_WT);
   const int64_t units = (int64_t)nblk * nwt;
@@ -337,14 +391,24 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
   const int64_t so = orbital_major ? (int64_t)M * nw : 1;
   const int64_t sr = orbital_major ? nw : n;
   const int64_t sw = orbital_major ? 1 : (int64_t)M * n;
-  const bool wide = tile_rows == 2 * LO_TILE_ROWS;
-  if (wide && M % 16 != 0) return hipErrorInvalidValue;   // the wide tile has no register-staged form
-  auto kern = wide ? lo_pass1_kernel<16> : (M % 16 == 0 ? lo_pass1_kernel<8> : lo_pass1_reg_kernel);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(wide ? 1024 : 512), 0, s, M,
-                     nw, rows, rowidx, tiles,
-                     tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax, (const double2*)theta, so, sr, sw,
-                     (double2*)qbar, out_walker_stride ? (int64_t)1 : nw,
-                     out_walker_stride ? out_walker_stride : (int64_t)1, nwt);
+  const int64_t orow_ = out_walker_stride ? (int64_t)1 : nw;
+  const int64_t ow_ = out_walker_stride ? out_walker_stride : (int64_t)1;
+  if (M % 16 != 0) {
+    hipLaunchKernelGGL(lo_pass1_reg_kernel, dim3((unsigned)grid), dim3(512), 0, s, M, nw, rows, rowidx, tiles,
+                       tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax, (const double2*)theta, so, sr, sw,
+                       (double2*)qbar, orow_, ow_, nwt);
+    return hipGetLastError();
+  }
+  // byte ranges the buffer form addresses: all factor rows, and one orbital's
+  // theta elements from its first (r = 0, w = 0) to its last
+  const int64_t abytes = rows_count * M * (int64_t)sizeof(double);
+  const int64_t bbytes = ((int64_t)(M - 1) * sr + (nw - 1) * sw + 1) * (int64_t)sizeof(double2);
+  const int64_t lim = INT32_MAX;   // descriptor range and offsets are 32-bit (kept signed)
+  const bool buf = abytes <= lim && bbytes <= lim;
+  hipLaunchKernelGGL(buf ? lo_pass1_kernel<true> : lo_pass1_kernel<false>, dim3((unsigned)grid), dim3(512), 0, s, M,
+                     nw, rows, rowidx, tiles, tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax,
+                     (const double2*)theta, so, sr, sw, (double2*)qbar, orow_, ow_, nwt, (uint32_t)(buf ? abytes : 0),
+                     (uint32_t)(buf ? bbytes : 0));
   return hipGetLastError();
 }
 // Pass 2: one thread per walker; the four waves of a workgroup take four

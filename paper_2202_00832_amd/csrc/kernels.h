@@ -49,13 +49,12 @@ hipError_t launch_reduce_partials(hipStream_t s, int64_t nw, int nchunk, const d
 // lo_orbital_block() orbitals; tmax: most tiles in one block.
 // qbar: output row r of walker w at r * nw + w (walkers fastest), or, with a
 // nonzero out_walker_stride, at w * out_walker_stride + r (rows fastest)
-// tile_rows: lo_tile_rows(), or lo_wide_tile_rows() (M a multiple of 16) for
-// the 16-wave form; the tiles must have been cut at that size
-int lo_wide_tile_rows();
+// tiles of at most lo_tile_rows() rows; rows_count: rows in `rows` (every
+// rowidx entry is below it)
 hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
-                           const int* rowidx, const int* tiles, const int* blk, int nblk, int tmax,
-                           const double* theta, int orbital_major, double* qbar, int64_t out_walker_stride,
-                           int tile_rows);
+                           int64_t rows_count, const int* rowidx, const int* tiles, const int* blk, int nblk,
+                           int tmax, const double* theta, int orbital_major, double* qbar,
+                           int64_t out_walker_stride);
 // name of the pass-1 kernel launch_lo_pass1 runs for this M (direct-to-LDS
 // staging when M is a multiple of 16, register staging otherwise)
 const char* lo_pass1_name(int M);

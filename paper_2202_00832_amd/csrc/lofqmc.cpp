@@ -43,7 +43,6 @@ struct lo_factors {
   std::vector<double> discarded;       // [n][n], sum of the discarded singular values
   std::vector<int64_t> row_offset;     // [n][n], -1 for i > j
   int ntiles = 0, npairs = 0, nblk = 0, tmax = 0;
-  int tile_rows = 0;                   // pass-1 tile size the FP64 tiles were cut at
   int ntiles_lp = 0, nblk_lp = 0, tmax_lp = 0;
   int* d_rowidx = nullptr;             // [n_out_rows]
   int* d_tiles = nullptr;              // [3][ntiles]: orbital, first output row, row count;
@@ -477,13 +476,7 @@ int finish_factors(lo_ctx* ctx, lo_factors* f, bool diag_u_only) {
     tiles.insert(tiles.end(), blk.begin(), blk.end());
     return tiles;
   };
-  // FP64 pass 1: 384-row tiles (16 waves) when an orbital touches more than
-  // 192 rows and M is a multiple of 16, so each orbital stays one tile
-  int64_t rmax = 0;
-  for (int o = 0; o < n; ++o) rmax = std::max<int64_t>(rmax, obase[o + 1] - obase[o]);
-  f->tile_rows = (rmax > lofqmc::lo_tile_rows() && M % 16 == 0) ? lofqmc::lo_wide_tile_rows()
-                                                                 : lofqmc::lo_tile_rows();
-  const std::vector<int> tiles = build_tiles(f->tile_rows, &f->ntiles, &f->nblk, &f->tmax);
+  const std::vector<int> tiles = build_tiles(lofqmc::lo_tile_rows(), &f->ntiles, &f->nblk, &f->tmax);
   const std::vector<int> tiles_lp = build_tiles(lofqmc::lo_lp_tile_rows(), &f->ntiles_lp, &f->nblk_lp, &f->tmax_lp);
   // pass-2 entries: one per rank row K of every stored pair i <= j, the
   // output rows of QL_i, QR_j (Coulomb) and QL_j, QR_i (exchange), padded
@@ -853,9 +846,10 @@ int lo_energy_enqueue(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double
   double* partial = (double*)(base + qbytes);
   if (precision == LO_FP64) {
     prof.mark(lofqmc::lo_pass1_name((int)M));
-    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->d_rowidx,
+    HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->total_rows,
+                                             f->d_rowidx,
                                              f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
-                                             orbital_major ? 1 : 0, qbar, 0, f->tile_rows));
+                                             orbital_major ? 1 : 0, qbar, 0));
   } else if (f->ntiles > 0) {
     void* tlp = base + qbytes + pbytes;
     prof.mark("lp_convert_kernel");
@@ -1408,9 +1402,8 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   ProfScope prof(ctx);
   prof.mark(lofqmc::lo_pass1_name((int)md->M));
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)md->M, (int)md->n, nw, md->ntiles, md->rows,
-                                           md->d_rowidx, md->d_tiles, md->d_tiles + 3 * md->ntiles, md->nblk,
-                                           md->tmax, theta, om ? 1 : 0, qbar, md->n_out_rows,
-                                           lofqmc::lo_tile_rows()));
+                                           md->total_rows + md->nav, md->d_rowidx, md->d_tiles, md->d_tiles + 3 * md->ntiles, md->nblk,
+                                           md->tmax, theta, om ? 1 : 0, qbar, md->n_out_rows));
   prof.mark("md_prep_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_md_prep(ctx->stream, g, mwork, ovlp_ratio));
   prof.mark("md_energy_kernel");

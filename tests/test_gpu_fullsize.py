@@ -41,7 +41,7 @@ def run():
     theta_om, _, info_om = ctx.green_theta(trial, phi, orbital_major=True)
     e_lo = ctx.local_energy_lo(fac, theta_om, info_om, orbital_major=True)
     # the headline threshold: orbitals touch more than 192 factor rows, so
-    # pass 1 runs its 384-row tiles; walker-major theta as in the bench
+    # pass 1 cuts each into two tiles; walker-major theta as in the bench
     fac7 = ctx.build_lo_factors(lbar, EPS_TIGHT)
     e_lo7 = ctx.local_energy_lo(fac7, theta, info)
     torch.cuda.synchronize()
@@ -110,7 +110,8 @@ def _check_lo(run_ranks, run_e, ref_f, ref, eps):
 
 def test_lo_energy_at_the_headline_threshold(run, ref, ref_svd):
     """eps = 1e-7 (the largest threshold whose per-walker error stays within
-    1 mHa on this workload), 384-row pass-1 tiles."""
+    1 mHa on this workload): orbitals touch more than 192 rows, so pass 1 runs
+    two tiles per orbital."""
     assert 2 * run["ranks7"].sum() - np.trace(run["ranks7"]) > 192 * run["ranks7"].shape[0]
     _check_lo(run["ranks7"], run["e_lo7"], E.lo_truncate(ref_svd, EPS_TIGHT), ref, EPS_TIGHT)
 

@@ -303,6 +303,35 @@ def test_lo_exact_coulomb(ctx, M, n, X, nw, eps, chain):
         ctx.local_energy_lo(f, theta_om, orbital_major=True, lbar=lbar)
 
 
+def test_lo_pass1_global_address_fallback(ctx):
+    """Pass 1 loads through 32-bit buffer offsets unless the factor rows or one
+    orbital's theta slice span more than 2^31 bytes.  Walker-major theta of
+    2^19 walkers of the 48-site chain puts 3.2 GB between an orbital's first and
+    last element, so that call takes the global-address loads; orbital-major
+    theta (slice 48 x 2^19 x 16 bytes) takes the buffer loads.  Same arithmetic
+    in the same order: the energies agree bit for bit, and sampled walkers
+    match the CPU reference.  4096 distinct walkers, repeated 128 times."""
+    s = synth.make_system(synth.CHAIN_SMALL, nw=4096)
+    nw = 1 << 19
+    print("lo pass-1 fallback nw=%d" % nw, flush=True)
+    lbar = ctx.build_half_rotated_chol(dev(s.chol), dev(s.trial))
+    f = ctx.build_lo_factors(lbar, 1e-4)
+    trial = dev(s.trial)
+    phi = dev(s.walkers).repeat(nw // 4096, 1, 1)
+    theta_wm, _, info_wm = ctx.green_theta(trial, phi)
+    e_wm = ctx.local_energy_lo(f, theta_wm, info_wm)
+    del theta_wm
+    theta_om, _, info_om = ctx.green_theta(trial, phi, orbital_major=True)
+    e_om = ctx.local_energy_lo(f, theta_om, info_om, orbital_major=True)
+    del theta_om, phi
+    a, b = host(e_wm), host(e_om)
+    assert np.array_equal(a.view(np.float64), b.view(np.float64))
+    pick = [0, 4095, 77 * 4096 + 13, nw - 1]
+    thetas, _ = oracle_thetas(s.trial, s.walkers[[w % 4096 for w in pick]])
+    ref = E.e2_lo_batch(E.lo_compress(E.half_rotate(s.chol, s.trial), 1e-4, pairs="upper"), thetas)
+    assert_energy_close(a[pick], ref)
+
+
 def test_lo_threshold_above_every_singular_value_gives_zero(ctx):
     s = synth.make_system(synth.CHAIN_SMALL, nw=3)
     lbar = ctx.build_half_rotated_chol(dev(s.chol), dev(s.trial))
