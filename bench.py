@@ -248,6 +248,18 @@ def hr_study(torch, ctx, lbar, trial_d, phi_d, info, energy, e_full_h, work, M, 
     return out
 
 
+def release_cached(torch, what):
+    """Hands torch's cached device blocks back to the driver before a study
+    that allocates outside torch's allocator (library workspaces, hipBLAS
+    work arrays) and logs the free device memory."""
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    log("%s: %.1f of %.1f GiB free on the device" % (what, free / 2 ** 30, total / 2 ** 30))
+
+
 def event_ms(torch, fn, reps=50, warm=5):
     """Mean ms per call of fn() over reps calls between two events, after warm calls."""
     for _ in range(warm):
@@ -456,12 +468,15 @@ def batch_study(torch, lofqmc, synth, evaluations=50):
 
 def _orthonormalize(torch, a):
     """Orthonormal columns spanning those of each a[w] (Cholesky QR,
-    a = Q L^H with L L^H = a^H a).  Q differs from a Householder QR's only by
-    column phases, which the circular walk noise does not see."""
+    a = Q L^H with L L^H = a^H a, Q = a L^{-H}).  Q differs from a Householder
+    QR's only by column phases, which the circular walk noise does not see.
+    L is inverted through torch.linalg.inv (LU) and applied by a batched
+    product: hipBLAS's batched complex triangular solve failed here with an
+    allocation error whatever the batch size."""
     ah = a.conj().transpose(-1, -2).contiguous()
     L = torch.linalg.cholesky(ah @ a)
-    return torch.linalg.solve_triangular(L.conj().transpose(-1, -2).contiguous(), a, upper=True,
-                                         left=False).contiguous()
+    linv_h = torch.linalg.inv(L).conj().transpose(-1, -2).contiguous()
+    return a @ linv_h
 
 
 def residual_study(torch, lofqmc, synth, n_train=20480, n_test=2048, steps=2000, step_sigmas=(0.005, 0.02),
@@ -921,15 +936,19 @@ def main():
 
     prec = None
     if not args.no_precision:
+        release_cached(torch, "precision study")
         prec = precision_study(torch, lofqmc, synth, max(2, min(args.steps, 5)))
     batch = None
     if not args.no_batch:
+        release_cached(torch, "batching study")
         batch = batch_study(torch, lofqmc, synth)
     mdet = None
     if not args.no_md:
+        release_cached(torch, "multi-determinant study")
         mdet = md_study(torch, lofqmc, synth, max(5, min(args.steps, 50)), min(args.warmup, 20))
     resid = None
     if not args.no_residual:
+        release_cached(torch, "residual study")
         resid = residual_study(torch, lofqmc, synth)
 
     log("CPU reference baseline (%d walkers)" % args.cpu_sample)

@@ -32,8 +32,14 @@
 // NA x NA, so every determinant runs the same branch-free code), the
 // unnormalised moments summed over determinants in a fixed order, then scaled
 // by 1 / sum_d c_d det(R_d)^2.
+// It also contracts Omega with each orbital's tau once per walker:
+//   Y_o[a][b][q] = sum_p Omega[a,p,b,q] tau_o[p].
 // md_energy_kernel: one workgroup per (walker, chunk of pairs), a thread per
-// pair; Omega, tau and mu of the walker in LDS.
+// pair; tau and mu of the walker in LDS.  Omega is symmetric under
+// (a,p) <-> (b,q) (a sum of w_d B_d[a,p] B_d[b,q]), so with
+// M[a][b] = sum_q Y_i[a][b][q] tau_j[q] the two determinant-averaged terms are
+//   tau_i^T H tau_j = sum_ab G_ab M[a][b],   tau_j^T H tau_i = sum_ab G_ab M[b][a]:
+// NA^3 + 2 NA^2 complex products per pair instead of the NA^4 of forming H.
 #include "common.h"
 #include "kernels.h"
 
@@ -57,8 +63,10 @@ __global__ __launch_bounds__(256) void md_prep_kernel(int n, int nao, int nav, i
                                                       const int* __restrict__ holes, const int* __restrict__ parts,
                                                       const double* __restrict__ coef, double2* __restrict__ tau,
                                                       double2* __restrict__ bbar, double2* __restrict__ omega,
+                                                      double2* __restrict__ ycon, int ncas,
                                                       double2* __restrict__ ovr) {
   constexpr int NA2 = NA * NA;
+  constexpr int NA3 = NA2 * NA;
   constexpr int NA4 = NA2 * NA2;
   constexpr int NE = (NA4 + 255) / 256;        // Omega entries per thread
   constexpr int CH = NA <= 5 ? 128 : 64;       // determinants per round (LDS: CH x NA^2 complex)
@@ -200,12 +208,37 @@ __global__ __launch_bounds__(256) void md_prep_kernel(int n, int nao, int nav, i
   const double nrm = S.x * S.x + S.y * S.y;
   const double2 rs = make_double2(S.x / nrm, -S.y / nrm);   // NaN moments when S = 0
   if (tid < NA2) bbar[w * NA2 + tid] = cmul(bacc, rs);
+  // Omega in LDS (over the determinant blocks, no longer needed) for Y
+  double2* sOmg = &sB[0][0];
+  static_assert(CH * NA2 >= NA4, "Omega fits the determinant blocks");
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
     const int e = tid + 256 * k;
-    if (e < NA4) omega[w * NA4 + e] = cmul(oacc[k], rs);
+    if (e < NA4) {
+      const double2 v = cmul(oacc[k], rs);
+      omega[w * NA4 + e] = v;
+      sOmg[e] = v;
+    }
   }
   if (tid == 0 && ovr) ovr[w] = S;
+  __syncthreads();
+  // Y_o[a][b][q] = sum_p Omega[a,p,b,q] tau_o[p]: tau_o = T[:, o] for an
+  // occupied o, -e_{o-n} for an active virtual one (Omega[a,p,b,q] at
+  // (a NA + p) NA^2 + b NA + q)
+  double2* yw = ycon + (size_t)w * ncas * NA3;
+  for (int e = tid; e < ncas * NA3; e += 256) {
+    const int o = e / NA3, r = e % NA3;
+    const int a = r / NA2, b = (r / NA) % NA, q = r % NA;
+    double2 y = make_double2(0.0, 0.0);
+    if (o < n) {
+#pragma unroll
+      for (int pp = 0; pp < NA; ++pp) y = cfma(sOmg[(a * NA + pp) * NA2 + b * NA + q], sT[pp][o], y);
+    } else if (o - n < NA) {
+      const double2 v = sOmg[(a * NA + (o - n)) * NA2 + b * NA + q];
+      y = make_double2(-v.x, -v.y);
+    }
+    yw[e] = y;
+  }
 }
 
 template <int NA>
@@ -219,11 +252,10 @@ __global__ __launch_bounds__(256) void md_energy_kernel(int n, int ncas, int nao
                                                         const double2* __restrict__ qbar,
                                                         const double2* __restrict__ tau,
                                                         const double2* __restrict__ bbar,
-                                                        const double2* __restrict__ omega,
+                                                        const double2* __restrict__ ycon,
                                                         double* __restrict__ partial) {
   constexpr int NA2 = NA * NA;
-  constexpr int NA4 = NA2 * NA2;
-  __shared__ double2 sOm[NA4];
+  constexpr int NA3 = NA2 * NA;
   __shared__ double2 sTau[MD_MAXN][NA];
   __shared__ double2 sBb[NA2];
   __shared__ double2 sMu[MD_MAXN][NA];     // mu_o = Bbar tau_o
@@ -236,7 +268,6 @@ __global__ __launch_bounds__(256) void md_energy_kernel(int n, int ncas, int nao
   if (w >= nw) return;
   const int chunk = blockIdx.y;
   const int tid = threadIdx.x;
-  for (int e = tid; e < NA4; e += 256) sOm[e] = omega[w * NA4 + e];
   if (tid < NA2) sBb[tid] = bbar[w * NA2 + tid];
   for (int e = tid; e < ncas * NA; e += 256) {
     const int o = e / NA, p = e % NA;
@@ -315,29 +346,29 @@ __global__ __launch_bounds__(256) void md_energy_kernel(int n, int ncas, int nao
 #pragma unroll
         for (int b = 0; b < NA; ++b) G[a][b] = cfma(la[a], ra[b], G[a][b]);
     }
-    // determinant-averaged covariance: H[p,q] = sum_ab G_ab Omega[a,p,b,q]
-    // (p, q loops kept rolled, tau read from LDS: unrolled, the NA^4 LDS
-    // reads of Omega would all be live at once)
-#pragma unroll 1
-    for (int pp = 0; pp < NA; ++pp) {
-      double2 hj = make_double2(0.0, 0.0), hx = make_double2(0.0, 0.0);
-#pragma unroll 1
-      for (int qq = 0; qq < NA; ++qq) {
-        double2 h = make_double2(0.0, 0.0);
-        const double2* om = sOm + pp * NA2 + qq;
+    // determinant-averaged terms through Y_i of this pair's orbital i:
+    // M[a][b] = sum_q Y_i[a][b][q] tau_j[q], J += sum G_ab M[a][b],
+    // X += sum G_ab M[b][a] (Y_i read through the cache: the pairs of a wave
+    // mostly share i, so their loads share addresses)
+    {
+      const double2* yi = ycon + ((size_t)w * ncas + i) * NA3;
+      double2 tj[NA];
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          double2 o[NA];
+      for (int q = 0; q < NA; ++q) tj[q] = sTau[j][q];
 #pragma unroll
-          for (int b = 0; b < NA; ++b) o[b] = om[a * NA * NA2 + b * NA];
+      for (int a = 0; a < NA; ++a) {
 #pragma unroll
-          for (int b = 0; b < NA; ++b) h = cfma(G[a][b], o[b], h);
+        for (int b = 0; b < NA; ++b) {
+          double2 yv[NA];
+#pragma unroll
+          for (int q = 0; q < NA; ++q) yv[q] = yi[(a * NA + b) * NA + q];
+          double2 m = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int q = 0; q < NA; ++q) m = cfma(yv[q], tj[q], m);
+          J = cfma(G[a][b], m, J);
+          X = cfma(G[b][a], m, X);
         }
-        hj = cfma(h, sTau[j][qq], hj);
-        hx = cfma(h, sTau[i][qq], hx);
       }
-      J = cfma(sTau[i][pp], hj, J);
-      X = cfma(sTau[j][pp], hx, X);
     }
     accJ = make_double2(accJ.x + wt * J.x, accJ.y + wt * J.y);
     accX = make_double2(accX.x + wt * X.x, accX.y + wt * X.y);
@@ -362,9 +393,9 @@ __global__ __launch_bounds__(256) void md_energy_kernel(int n, int ncas, int nao
 int md_max_orbitals() { return MD_MAXN; }
 int md_max_active() { return 6; }
 
-size_t md_walker_bytes(int na, int n) {
+size_t md_walker_bytes(int na, int n, int ncas) {
   const size_t na2 = (size_t)na * na;
-  return sizeof(double2) * ((size_t)na * n + na2 + na2 * na2);
+  return sizeof(double2) * ((size_t)na * n + na2 + na2 * na2 + (size_t)ncas * na2 * na);
 }
 
 int md_pair_chunks(int npairs) {
@@ -375,7 +406,7 @@ int md_pair_chunks(int npairs) {
 }
 
 struct MdWork {
-  double2 *tau, *bbar, *omega;
+  double2 *tau, *bbar, *omega, *ycon;
 };
 static MdWork md_work(const MdArgs& g, void* work) {
   const int na = g.nao > g.nav ? g.nao : g.nav;
@@ -384,6 +415,7 @@ static MdWork md_work(const MdArgs& g, void* work) {
   m.tau = (double2*)work;
   m.bbar = m.tau + (size_t)g.nw * na * g.n;
   m.omega = m.bbar + (size_t)g.nw * na2;
+  m.ycon = m.omega + (size_t)g.nw * na2 * na2;
   return m;
 }
 
@@ -391,7 +423,7 @@ template <int NA>
 static hipError_t launch_prep_na(hipStream_t s, const MdArgs& g, const MdWork& m, double2* ovr) {
   hipLaunchKernelGGL((md_prep_kernel<NA>), dim3((unsigned)g.nw), dim3(256), 0, s, g.n, g.nao, g.nav, g.ndet,
                      g.hstride, g.tpos, (const double2*)g.qbar, g.n_out, g.exc, g.holes, g.parts, g.coef, m.tau,
-                     m.bbar, m.omega, ovr);
+                     m.bbar, m.omega, m.ycon, g.ncas, ovr);
   return hipGetLastError();
 }
 
@@ -401,7 +433,7 @@ static hipError_t launch_pairs_na(hipStream_t s, const MdArgs& g, const MdWork& 
   const int64_t nw8 = (g.nw + 7) / 8;
   hipLaunchKernelGGL((md_energy_kernel<NA>), dim3((unsigned)(8 * nw8), nchunk), dim3(256), 0, s, g.n, g.ncas, g.nao,
                      g.nw, g.npairs, per, g.pi, g.pj, g.pK, g.offI, g.offJ, g.offA, g.act_stride, g.n_out,
-                     (const double2*)g.qbar, m.tau, m.bbar, m.omega, partial);
+                     (const double2*)g.qbar, m.tau, m.bbar, m.ycon, partial);
   return hipGetLastError();
 }
 

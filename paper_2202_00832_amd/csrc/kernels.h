@@ -167,8 +167,9 @@ struct MdArgs {
 };
 int md_max_orbitals();
 int md_max_active();
-// per-walker device bytes of the moments and T (work of launch_md_energy is nw times this)
-size_t md_walker_bytes(int na, int n);
+// per-walker device bytes of T, the moments and the contractions Y_o (work of
+// launch_md_prep / launch_md_pairs is nw times this)
+size_t md_walker_bytes(int na, int n, int ncas);
 int md_pair_chunks(int npairs);
 // prep: T, the determinant moments (into work) and ovr, device complex [nw]
 // (sum_d c_d det(R_d)^2) or null; pairs: the weighted pair sums into partial

@@ -1367,7 +1367,7 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   const bool om = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
   const int nchunk = lofqmc::md_pair_chunks(md->npairs);
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)md->n_out_rows * nw);
-  const size_t mbytes = align256(lofqmc::md_walker_bytes(md->na, (int)md->n) * (size_t)nw);
+  const size_t mbytes = align256(lofqmc::md_walker_bytes(md->na, (int)md->n, (int)md->ncas) * (size_t)nw);
   const size_t pbytes = align256(sizeof(double) * 4 * (size_t)nchunk * nw);
   int rc = ensure_ws(ctx, qbytes + mbytes + pbytes);
   if (rc) return rc;
