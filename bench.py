@@ -681,9 +681,10 @@ def md_study(torch, lofqmc, synth, steps, warmup, baseline_steps=2):
     own = [k for k in kern if k.startswith("md_") or k == "lo_pass1_kernel" or k == "reduce_partials_kernel"]
     # algorithmic work per launch (unpadded sizes): pass 1 as in the single-
     # determinant route; md_prep: T = C_av^T theta, a Gauss-Jordan inverse of
-    # every eps_d x eps_d R_d and its eps_d^4 moment products; md_energy: per
-    # pair and rank row the own products, the four mean projections and the
-    # outer product G, then the NA^4 contraction with Omega and two NA^2 forms
+    # every eps_d x eps_d R_d and its eps_d^4 moment products, then Y_o =
+    # Omega tau_o for every orbital (n_cas nao^2 nav^2 products); md_energy:
+    # per pair and rank row the own products, the four mean projections and
+    # the outer product G, then M = Y_i tau_j (nao^2 nav) and two nao^2 forms
     nao, nav = cfg.n_act_occ, cfg.n_act_virt
     finfo = f.info()
     ranks = finfo["ranks"]
@@ -693,10 +694,11 @@ def md_study(torch, lofqmc, synth, steps, warmup, baseline_steps=2):
     mdwork = {
         "lo_pass1_kernel": ("mfma", 4.0 * M * md.out_rows * nw,
                             8.0 * M * finfo["total_rows"] + 16.0 * nw * (M * n + md.out_rows)),
-        "md_prep_kernel": ("alu", nw * (4.0 * M * nav * n + np.sum(8.0 * eps_d ** 3 + 16.0 * eps_d ** 4)),
-                           16.0 * nw * (M * n + nao * nav * (1 + nao * nav))),
+        "md_prep_kernel": ("alu", nw * (4.0 * M * nav * n + np.sum(8.0 * eps_d ** 3 + 16.0 * eps_d ** 4)
+                                        + 8.0 * ncas * nao * nao * nav * nav),
+                           16.0 * nw * (M * n + nao * nav * (1 + nao * nav) + ncas * nao * nao * nav)),
         "md_energy_kernel": ("alu", nw * 8.0 * float(np.sum(Ks * (2 + 4 * nao + nao * nao)
-                                                           + (nao * nav) ** 2 + 2 * nav * nav)),
+                                                           + nao * nao * nav + 2 * nao * nao)),
                              16.0 * nw * md.out_rows),
     }
     md_roof = {k: roofline_of(k, mdwork, kern[k][1] / kern[k][0]) for k in mdwork if k in kern}
