@@ -18,6 +18,8 @@
 //      walker-major [w][r][j] or, with the orbital-major flag, as [j][r][w];
 //      walkers 8g .. 8g+7 then run on the same XCD so that their interleaved
 //      16-byte stores meet in one L2.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -146,16 +148,20 @@ __global__ __launch_bounds__(GtCfg<NB>::OT) void overlap_kernel(int M, int n, in
 //    log det O_w and the zero-pivot index.  Wave q owns the 16 columns
 //    16q .. 16q+15 of every row (lane l holds rows l and l + 64).
 //
-//    Blocked by panels of 16 columns.  Panel b (the columns of wave b) is
+//    Blocked by half-panels of 8 columns: half h of wave b's columns is
 //    swept by wave b alone: for each of its columns k, the pivot row p (the
 //    largest |re|+|im| among rows not yet used, compared on its exponent and
-//    leading 14 mantissa bits, lowest row on ties), then A[i][j] -= m_i A[p][j] on the panel's columns with
+//    leading 14 mantissa bits, lowest row on ties), then A[i][j] -= m_i A[p][j] on the half's columns with
 //    m_i = (A[i][k] + [i == p]) / A[p][k], and column k set to A[i][k] / A[p][k]
-//    (1 / A[p][k] on row p).  The sixteen sweeps act on any other column as
-//    one rank-16 update: with P the panel's pivot rows, Z = A[P, J] taken
-//    before the panel and F the swept panel columns,
+//    (1 / A[p][k] on row p).  The eight sweeps act on any other column as
+//    one rank-8 update: with P the half's pivot rows, Z = A[P, J] taken
+//    before the half and F the swept columns,
 //        A[:, J] <- (rows not in P ? A[:, J] : 0) - F Z,
-//    which every other wave applies to its own columns after one barrier.
+//    which every other wave applies to its own columns after one barrier and
+//    wave b to its other half straight from its registers, so it sweeps its
+//    second half without waiting for the others.  (Sixteen-column panels
+//    broadcast sixteen pivot-row entries per step through v_readlane, which
+//    made the serial sweep issue-bound.)
 // ---------------------------------------------------------------------------
 template <int NB>
 __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, double2* __restrict__ O, int* __restrict__ perm,
@@ -163,14 +169,14 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
                                                           int flag_small) {
   constexpr int NP = 16 * NB;
   constexpr int RPL = (NP + 63) / 64;        // rows per lane
-  constexpr int FS = 17;                     // padded row stride of the panel copy (no bank conflicts)
-  __shared__ double2 sF[2][NP * FS];         // swept panel columns, by panel parity
-  __shared__ double2 sZ[NB][16][16];         // per wave: its columns of the panel's pivot rows
+  constexpr int FS = 9;                      // padded row stride of the half-panel copy
+  __shared__ double2 sF[2][NP * FS];         // swept half-panel columns, by half
+  __shared__ double2 sZ[NB][8][16];          // per wave: its columns of the half-panel's pivot rows
   __shared__ int sPiv[NP];
   __shared__ double2 sPivV[NP];
   __shared__ int sZero[2];
-  __shared__ int sInvW[NB];                  // per panel: inversions of the pivot order
-  __shared__ int sSmall[NB];                 // per panel: first step with a small pivot (flag_small)
+  __shared__ int sInvW[2 * NB];              // per half-panel: inversions of the pivot order
+  __shared__ int sSmall[2 * NB];             // per half-panel: first step with a small pivot (flag_small)
   __shared__ double sOmax[NB];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -217,165 +223,211 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
   int small = 0;
 
   int zero = 0;
-  for (int b = 0; b < NB; ++b) {
-    const int buf = b & 1;
-    if (wv == b) {
-      // inversions of k -> p_k: the rows still unused at step k are the later
-      // pivots, so the step adds the number of unused rows below p_k.  Lane c
-      // keeps the pivot row and value of step c (no branches inside the sweep,
-      // so its sixteen steps form one block the scheduler can overlap).
-      int inversions = 0;
-      int myp = 0;
-      double mypr = 1.0, mypi = 0.0;
-      // sweep the panel, wave-local and branch-free (no join points, so the
-      // rows are updated in place)
+  // sweep of half H of wave b's columns (8 H .. 8 H + 7), then its publication
+  auto sweep_half = [&](auto hc, int b) __attribute__((always_inline)) {
+    constexpr int H = decltype(hc)::value;
+    // inversions of k -> p_k: the rows still unused at step k are the later
+    // pivots, so the step adds the number of unused rows below p_k.  Lane c
+    // keeps the pivot row and value of step c (no branches inside the sweep,
+    // so its eight steps form one block the scheduler can overlap).
+    int inversions = 0;
+    int myp = 0;
+    double mypr = 1.0, mypi = 0.0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const int k = 16 * b + c;
-        // key: exponent and leading 14 mantissa bits of |re|+|im| above the
-        // complement of the row index (largest magnitude, lowest row on ties)
-        unsigned key = 0u;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int row = lane + 64 * t;
-          const double2 v = e[t][c];
-          const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fabs(v.x) + fabs(v.y)) >> 32);
-          const unsigned kt = used[t] ? 0u : (((hi >> 6) << 7) | (unsigned)(127 - row));
-          key = kt > key ? kt : key;
-        }
-        key = wave_max_u32(key);
-        // no pivot left (singular): record the first such step; the sweeps go
-        // on with zero multipliers and the result is discarded
-        const bool ok = (key >> 7) != 0u && zero == 0;
-        zero = (zero == 0 && !ok) ? k + 1 : zero;
-        const int p = 127 - (int)(key & 127u);
-        const int pl = p & 63, pt = p >> 6;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) inversions += __popcll(__ballot(!used[t] && lane + 64 * t < p));
-        // pivot value and, inside the update, the pivot row (the panel's 16
-        // columns) from lane pl, read into scalar registers one entry at a time
-        const double2 piv = make_double2(readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][c].x : e[0][c].x, pl),
-                                         readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][c].y : e[0][c].y, pl));
-        small = (small == 0 && ok && k < n && fabs(piv.x) + fabs(piv.y) < thr) ? k + 1 : small;
-        // 1 / |pivot|^2: hardware reciprocal refined by two Newton steps
-        const double d = fma(piv.x, piv.x, piv.y * piv.y);
-        double r = __builtin_amdgcn_rcp(d);
-        r = fma(r, fma(-d, r, 1.0), r);
-        r = fma(r, fma(-d, r, 1.0), r);
-        const double rn = ok ? r : 0.0;
-        const double2 inv = make_double2(piv.x * rn, -piv.y * rn);
-        // (selects on scalars: a select of two double2 values goes through scratch)
-        myp = lane == c ? p : myp;
-        mypr = lane == c ? piv.x : mypr;
-        mypi = lane == c ? piv.y : mypi;
-        double2 mi[RPL], cc[RPL];
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int row = lane + 64 * t;
-          double2 ci = e[t][c];
-          cc[t].x = row == p ? 1.0 : ci.x;
-          cc[t].y = row == p ? 0.0 : ci.y;
-          ci.x += row == p ? 1.0 : 0.0;
-          const double2 m = cmul(ci, inv);
-          mi[t].x = ok ? m.x : 0.0;
-          mi[t].y = ok ? m.y : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const double2 src = (RPL > 1 && pt == 1) ? e[RPL - 1][j] : e[0][j];
-          const double2 a = make_double2(readlane_f64(src.x, pl), readlane_f64(src.y, pl));
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            double2 v = e[t][j];
-            v.x = fma(-mi[t].x, a.x, fma(mi[t].y, a.y, v.x));
-            v.y = fma(-mi[t].x, a.y, fma(-mi[t].y, a.x, v.y));
-            e[t][j] = v;
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const double2 v = cmul(cc[t], inv);
-          e[t][c].x = ok ? v.x : e[t][c].x;
-          e[t][c].y = ok ? v.y : e[t][c].y;
-          if (lane + 64 * t == p) used[t] = true;
-        }
-      }
-      // publish the swept panel (every row) and the outcome
+    for (int c = 0; c < 8; ++c) {
+      const int jc = 8 * H + c;               // this wave's column
+      const int k = 16 * b + jc;
+      // key: exponent and leading 14 mantissa bits of |re|+|im| above the
+      // complement of the row index (largest magnitude, lowest row on ties)
+      unsigned key = 0u;
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int row = lane + 64 * t;
-        if (row < NP) {
+        const double2 v = e[t][jc];
+        const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fabs(v.x) + fabs(v.y)) >> 32);
+        const unsigned kt = used[t] ? 0u : (((hi >> 6) << 7) | (unsigned)(127 - row));
+        key = kt > key ? kt : key;
+      }
+      key = wave_max_u32(key);
+      // no pivot left (singular): record the first such step; the sweeps go
+      // on with zero multipliers and the result is discarded
+      const bool ok = (key >> 7) != 0u && zero == 0;
+      zero = (zero == 0 && !ok) ? k + 1 : zero;
+      const int p = 127 - (int)(key & 127u);
+      const int pl = p & 63, pt = p >> 6;
 #pragma unroll
-          for (int j = 0; j < 16; ++j) sF[buf][row * FS + j] = e[t][j];
+      for (int t = 0; t < RPL; ++t) inversions += __popcll(__ballot(!used[t] && lane + 64 * t < p));
+      // pivot value and, inside the update, the pivot row (the half's 8
+      // columns) from lane pl, read into scalar registers one entry at a time
+      const double2 piv = make_double2(readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][jc].x : e[0][jc].x, pl),
+                                       readlane_f64(RPL > 1 && pt == 1 ? e[RPL - 1][jc].y : e[0][jc].y, pl));
+      small = (small == 0 && ok && k < n && fabs(piv.x) + fabs(piv.y) < thr) ? k + 1 : small;
+      // 1 / |pivot|^2: hardware reciprocal refined by two Newton steps
+      const double d = fma(piv.x, piv.x, piv.y * piv.y);
+      double r = __builtin_amdgcn_rcp(d);
+      r = fma(r, fma(-d, r, 1.0), r);
+      r = fma(r, fma(-d, r, 1.0), r);
+      const double rn = ok ? r : 0.0;
+      const double2 inv = make_double2(piv.x * rn, -piv.y * rn);
+      // (selects on scalars: a select of two double2 values goes through scratch)
+      myp = lane == c ? p : myp;
+      mypr = lane == c ? piv.x : mypr;
+      mypi = lane == c ? piv.y : mypi;
+      double2 mi[RPL], cc[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = lane + 64 * t;
+        double2 ci = e[t][jc];
+        cc[t].x = row == p ? 1.0 : ci.x;
+        cc[t].y = row == p ? 0.0 : ci.y;
+        ci.x += row == p ? 1.0 : 0.0;
+        const double2 m = cmul(ci, inv);
+        mi[t].x = ok ? m.x : 0.0;
+        mi[t].y = ok ? m.y : 0.0;
+      }
+#pragma unroll
+      for (int j = 8 * H; j < 8 * H + 8; ++j) {
+        const double2 src = (RPL > 1 && pt == 1) ? e[RPL - 1][j] : e[0][j];
+        const double2 a = make_double2(readlane_f64(src.x, pl), readlane_f64(src.y, pl));
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          double2 v = e[t][j];
+          v.x = fma(-mi[t].x, a.x, fma(mi[t].y, a.y, v.x));
+          v.y = fma(-mi[t].x, a.y, fma(-mi[t].y, a.x, v.y));
+          e[t][j] = v;
         }
       }
-      if (lane < 16) {
-        sPiv[16 * b + lane] = myp;
-        sPivV[16 * b + lane] = make_double2(mypr, mypi);
-      }
-      if (lane == 0) {
-        sZero[buf] = zero;
-        sInvW[b] = inversions;
-        sSmall[b] = small;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const double2 v = cmul(cc[t], inv);
+        e[t][jc].x = ok ? v.x : e[t][jc].x;
+        e[t][jc].y = ok ? v.y : e[t][jc].y;
+        if (lane + 64 * t == p) used[t] = true;
       }
     }
-    __syncthreads();
-    zero = sZero[buf];
-    if (zero) break;
-    if (wv != b) {
-      const int k0 = 16 * b;
-      // position of each of this lane's rows among the panel's pivot rows
-      int pos[RPL];
+    // publish the swept columns (every row) and the outcome
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) pos[t] = -1;
+    for (int t = 0; t < RPL; ++t) {
+      const int row = lane + 64 * t;
+      if (row < NP) {
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const int pc = sPiv[k0 + c];
-#pragma unroll
-        for (int t = 0; t < RPL; ++t)
-          if (lane + 64 * t == pc) pos[t] = c;
+        for (int j = 0; j < 8; ++j) sF[H][row * FS + j] = e[t][8 * H + j];
       }
-      // Z = this wave's columns of the pivot rows, through wave-local LDS; a
-      // wavefront-scope release/acquire pair around a wave barrier orders the
-      // writes before the reads of the other lanes
+    }
+    if (lane < 8) {
+      sPiv[16 * b + 8 * H + lane] = myp;
+      sPivV[16 * b + 8 * H + lane] = make_double2(mypr, mypi);
+    }
+    if (lane == 0) {
+      sZero[H] = zero;
+      sInvW[2 * b + H] = inversions;
+      sSmall[2 * b + H] = small;
+    }
+  };
+  // Z = this wave's columns J0 .. J0 + NJ - 1 at the pivot rows of half-panel
+  // hp (first column k0 = 8 hp), through wave-local LDS (a wavefront-scope
+  // release/acquire pair around a wave barrier orders the writes before the
+  // reads of the other lanes); then the pivot rows of those columns zeroed
+  auto take_z = [&](auto j0c, auto njc, int hp, bool (&inp)[RPL]) __attribute__((always_inline)) {
+    constexpr int J0 = decltype(j0c)::value, NJ = decltype(njc)::value;
+    int pos[RPL];
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        if (pos[t] >= 0) {
-          used[t] = true;
+    for (int t = 0; t < RPL; ++t) pos[t] = -1;
 #pragma unroll
-          for (int j = 0; j < 16; ++j) sZ[wv][pos[t]][j] = e[t][j];
-        }
+    for (int c = 0; c < 8; ++c) {
+      const int pc = sPiv[8 * hp + c];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t)
+        if (lane + 64 * t == pc) pos[t] = c;
+    }
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      inp[t] = pos[t] >= 0;
+      if (pos[t] >= 0) {
+        used[t] = true;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) sZ[wv][pos[t]][j] = e[t][J0 + j];
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int row = lane + 64 * t;
-        if (row < NP) {
-          if (pos[t] >= 0) {
+    for (int t = 0; t < RPL; ++t) {
+      if (inp[t]) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) e[t][j] = make_double2(0.0, 0.0);
-          }
-          // per panel column: the Z row's loads are all issued before the
-          // products (a scheduling barrier keeps them apart), so each product
-          // waits only for its own operand; c is not unrolled (only j must be static)
+        for (int j = 0; j < NJ; ++j) e[t][J0 + j] = make_double2(0.0, 0.0);
+      }
+    }
+  };
+  // rank-8 update of all sixteen columns of a wave that did not sweep
+  // half-panel hp, with F from LDS (buffer H)
+  auto update_other = [&](int hp, int H) __attribute__((always_inline)) {
+    bool inp[RPL];
+    take_z(std::integral_constant<int, 0>{}, std::integral_constant<int, 16>{}, hp, inp);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int row = lane + 64 * t;
+      if (row < NP) {
+        // per swept column: the Z row's loads are all issued before the
+        // products (a scheduling barrier keeps them apart), so each product
+        // waits only for its own operand; c is not unrolled (only j must be static)
 #pragma unroll 1
-          for (int c = 0; c < 16; ++c) {
-            double2 z[16];
-            const double2 f = sF[buf][row * FS + c];
+        for (int c = 0; c < 8; ++c) {
+          double2 z[16];
+          const double2 f = sF[H][row * FS + c];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) z[j] = sZ[wv][c][j];
-            __builtin_amdgcn_sched_barrier(0);
+          for (int j = 0; j < 16; ++j) z[j] = sZ[wv][c][j];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-              e[t][j].x = fma(-f.x, z[j].x, fma(f.y, z[j].y, e[t][j].x));
-              e[t][j].y = fma(-f.x, z[j].y, fma(-f.y, z[j].x, e[t][j].y));
-            }
+          for (int j = 0; j < 16; ++j) {
+            e[t][j].x = fma(-f.x, z[j].x, fma(f.y, z[j].y, e[t][j].x));
+            e[t][j].y = fma(-f.x, z[j].y, fma(-f.y, z[j].x, e[t][j].y));
           }
         }
       }
     }
+  };
+  // rank-8 update of the sweeping wave's other half by its half H, with F
+  // from its own registers
+  auto update_self = [&](auto hc, int hp) __attribute__((always_inline)) {
+    constexpr int H = decltype(hc)::value;
+    constexpr int JO = 8 * (1 - H), FO = 8 * H;
+    bool inp[RPL];
+    take_z(std::integral_constant<int, JO>{}, std::integral_constant<int, 8>{}, hp, inp);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      double2 z[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) z[j] = sZ[wv][c][j];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const double2 f = e[t][FO + c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          e[t][JO + j].x = fma(-f.x, z[j].x, fma(f.y, z[j].y, e[t][JO + j].x));
+          e[t][JO + j].y = fma(-f.x, z[j].y, fma(-f.y, z[j].x, e[t][JO + j].y));
+        }
+      }
+    }
+  };
+  for (int b = 0; b < NB; ++b) {
+    if (wv == b) sweep_half(std::integral_constant<int, 0>{}, b);
+    __syncthreads();
+    zero = sZero[0];
+    if (zero) break;
+    if (wv == b)
+      update_self(std::integral_constant<int, 0>{}, 2 * b);
+    else
+      update_other(2 * b, 0);
+    if (wv == b) sweep_half(std::integral_constant<int, 1>{}, b);
+    __syncthreads();
+    zero = sZero[1];
+    if (zero) break;
+    if (wv == b)
+      update_self(std::integral_constant<int, 1>{}, 2 * b + 1);
+    else
+      update_other(2 * b + 1, 1);
   }
   __syncthreads();
 
@@ -403,7 +455,7 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
         ar += atan2(pv.y, pv.x);
       }
 #pragma unroll
-      for (int b = 0; b < NB; ++b) inv_count += sInvW[b];
+      for (int b = 0; b < 2 * NB; ++b) inv_count += sInvW[b];
     }
     la = wave_sum_lane0(la);
     ar = wave_sum_lane0(ar);
@@ -412,7 +464,7 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
       // panel that recorded one
       int first_small = 0;
       if (flag_small && !zero) {
-        for (int b = NB - 1; b >= 0; --b) first_small = sSmall[b] ? sSmall[b] : first_small;
+        for (int b = 2 * NB - 1; b >= 0; --b) first_small = sSmall[b] ? sSmall[b] : first_small;
       }
       info[w] = zero ? zero : -first_small;
       if (logov) {
