@@ -6,10 +6,10 @@
 //      16-row slabs of phi_w and Psi_T are staged in LDS with coalesced loads,
 //      prefetched two slabs ahead.  One workgroup per walker.
 //   2. invert_kernel: exchange (Gauss-Jordan) elimination with partial
-//      pivoting, blocked by 16-column panels: each panel is swept inside one
-//      wave (no workgroup barrier per step), the other waves then apply the
-//      panel's rank-16 update to their columns.  Gives O^{-1} in pivot order
-//      with the pivot rows, log det O and the zero-pivot index.
+//      pivoting, blocked by 8-column half-panels: each is swept inside one
+//      wave (no workgroup barrier per step), the other waves then apply its
+//      rank-8 update to their columns.  Gives O^{-1} in pivot order with the
+//      pivot rows, log det O and the zero-pivot index.
 //   3. apply_kernel: theta = phi O^{-1} on MFMA with three real products per
 //      complex block (re = P1 - P2, im = P3 - P1 - P2 with P1 = a_re b_re,
 //      P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im)); one workgroup per
