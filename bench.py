@@ -280,13 +280,13 @@ def few_walker_study(torch, ctx, lbar, trial_d, phi_d, factors, nw=16):
     walkers, LO at each threshold against the HR-ERI code): energy calls only,
     on the first 16 walkers of the workload."""
     phi = phi_d[:nw].contiguous()
-    th, _, inf = ctx.green_theta(trial_d, phi)
+    th, _, inf = ctx.green_theta(trial_d, phi, transposed=True)
     th_om, _, inf_om = ctx.green_theta(trial_d, phi, orbital_major=True)
     hr = ctx.build_hr_eri(lbar)
     hr_ms = event_ms(torch, lambda: ctx.local_energy_hr(hr, th_om, inf_om, orbital_major=True))
     out = {"walkers": nw, "local_energy_hr_ms": round(hr_ms, 4), "lo": {}}
     for eps, f in factors.items():
-        lo_ms = event_ms(torch, lambda f=f: ctx.local_energy_lo(f, th, inf))
+        lo_ms = event_ms(torch, lambda f=f: ctx.local_energy_lo(f, th, inf, transposed=True))
         out["lo"]["%g" % eps] = {"local_energy_lo_ms": round(lo_ms, 4), "speedup_vs_hr": round(hr_ms / lo_ms, 1)}
     hr.close()
     log("16 walkers: HR-ERI %.3f ms, LO %s" % (hr_ms, ", ".join("%s %.3f ms (%.0fx)" % (k, v["local_energy_lo_ms"],
@@ -616,7 +616,7 @@ def md_study(torch, lofqmc, synth, steps, warmup, baseline_steps=2):
     md = ctx.build_md_trial(f, n, cfg.n_act_occ, C, s.holes, s.particles, s.coeffs)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    theta = torch.empty((nw, M, n), dtype=torch.complex128, device="cuda")
+    theta = torch.empty((nw, n, M), dtype=torch.complex128, device="cuda")   # transposed, as the LO step
     logov = torch.empty(nw, dtype=torch.complex128, device="cuda")
     info = torch.empty(nw, dtype=torch.int32, device="cuda")
     energy = torch.empty((nw, 2), dtype=torch.complex128, device="cuda")
@@ -625,10 +625,10 @@ def md_study(torch, lofqmc, synth, steps, warmup, baseline_steps=2):
     def step(ev):
         if ev is not None:
             ev["a"].record()
-        ctx.green_theta(ref, phi, theta, logov, info)
+        ctx.green_theta(ref, phi, theta, logov, info, transposed=True)
         if ev is not None:
             ev["b"].record()
-        ctx.local_energy_md(md, theta, info, energy, ovr)
+        ctx.local_energy_md(md, theta, info, energy, ovr, transposed=True)
         if ev is not None:
             ev["c"].record()
 
@@ -719,7 +719,7 @@ def md_study(torch, lofqmc, synth, steps, warmup, baseline_steps=2):
     for k in (1, 20, 100, 251):
         h, p_, c = synth.cas_expansion(n, cfg.n_act_occ, cfg.n_act_virt, k, cfg.max_exc, np.random.default_rng(k))
         mk = ctx.build_md_trial(f, n, cfg.n_act_occ, C, h, p_, c)
-        ms_k = event_ms(torch, lambda mk=mk: ctx.local_energy_md(mk, theta, info, energy))
+        ms_k = event_ms(torch, lambda mk=mk: ctx.local_energy_md(mk, theta, info, energy, transposed=True))
         scaling.append({"n_det": k, "local_energy_md_ms": round(ms_k, 4)})
         mk.close()
     out["n_det_scaling"] = scaling
@@ -871,15 +871,19 @@ def main():
     eps_h = head["epsilon"]
 
     energy = torch.empty((nw, 2), dtype=torch.complex128, device="cuda")
+    # the LO step hands theta over transposed ([w][j][r]), the layout whose
+    # orbital columns pass 1 loads in whole cache lines (same energies bit
+    # for bit as walker-major theta)
+    theta_tr = torch.empty((nw, n, M), dtype=torch.complex128, device="cuda")
 
     def lo_step_for(f):
         def step(ev):
             if ev is not None:
                 ev["a"].record()
-            ctx.green_theta(trial_d, phi_d, theta, logov, info)
+            ctx.green_theta(trial_d, phi_d, theta_tr, logov, info, transposed=True)
             if ev is not None:
                 ev["b"].record()
-            ctx.local_energy_lo(f, theta, info, energy)
+            ctx.local_energy_lo(f, theta_tr, info, energy, transposed=True)
             if ev is not None:
                 ev["c"].record()
         return step

@@ -45,7 +45,10 @@ enum lo_status {
 /* Layout of theta (the Q matrices) produced by green_theta and read by the
  * energy calls.  Default: walker-major complex [nw][M][n_occ].  With
  * LO_THETA_ORBITAL_MAJOR: orbital-major complex [n_occ][M][nw] (walkers
- * contiguous), the layout the LO energy multiplies directly. */
+ * contiguous).  With LO_THETA_TRANSPOSED: each walker's theta transposed,
+ * complex [nw][n_occ][M] (the basis index contiguous), the layout whose
+ * orbital columns the LO energy's pass 1 loads in whole cache lines.  At
+ * most one of the two layout flags. */
 enum lo_flags {
   LO_THETA_ORBITAL_MAJOR = 1u,
   /* local_energy_lo: E_J from the FP64 Cholesky traces Tr(Lbar_g^T theta)
@@ -53,7 +56,8 @@ enum lo_flags {
    * lbar argument and walker-major theta. */
   LO_EXACT_COULOMB = 2u,
   /* green_theta: report nearly singular overlaps as info < 0 (see there) */
-  LO_FLAG_SMALL_PIVOT = 4u
+  LO_FLAG_SMALL_PIVOT = 4u,
+  LO_THETA_TRANSPOSED = 8u
 };
 
 /* Arithmetic of the energy contractions.  Reduced precision applies to the
@@ -217,7 +221,8 @@ int lo_factors_import(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, con
  *   trial    : [M][n_occ] double (real)
  *   phi      : complex [nw][M][n_occ] walker determinants
  *   theta    : complex [nw][M][n_occ] (output), or [n_occ][M][nw] when flags
- *              holds LO_THETA_ORBITAL_MAJOR
+ *              holds LO_THETA_ORBITAL_MAJOR, or [nw][n_occ][M] with
+ *              LO_THETA_TRANSPOSED (the same values in each layout)
  *   log_ovlp : complex [nw] (output; may be NULL)
  *   info     : int32 [nw] (output): 0, or k > 0 if the k-th pivot (1-based)
  *              of O_w is exactly zero; theta_w is then undefined and the
@@ -227,8 +232,8 @@ int lo_factors_import(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, con
  *              the largest |re| + |im| of O_w's entries (a nearly singular
  *              overlap): a warning only, theta_w and the energies are still
  *              computed (and large).
- * Always FP64.  Supports n_occ <= 112.  flags: LO_THETA_ORBITAL_MAJOR,
- * LO_FLAG_SMALL_PIVOT. */
+ * Always FP64.  Supports n_occ <= 112.  flags: LO_THETA_ORBITAL_MAJOR or
+ * LO_THETA_TRANSPOSED, LO_FLAG_SMALL_PIVOT. */
 int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double* trial,
                 const double* phi, double* theta, double* log_ovlp, int32_t* info, unsigned flags);
 
@@ -256,17 +261,19 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
  *   E_J = 2 sum_ij QL_i . QR_j,   E_K = -sum_ij QL_j . QR_i.
  *   factors : handle from build_lo_factors (shapes M, n_occ taken from it)
  *   theta   : complex [nw][M][n_occ], or [n_occ][M][nw] with flags
- *             LO_THETA_ORBITAL_MAJOR (both are read in place)
+ *             LO_THETA_ORBITAL_MAJOR, or [nw][n_occ][M] with
+ *             LO_THETA_TRANSPOSED (all are read in place; the transposed one
+ *             is the fastest to read at M a multiple of 16)
  *   info    : int32 [nw] or NULL
  *   lbar    : NULL, or with LO_EXACT_COULOMB the [n_chol][M][n_occ] vectors
  *             the factors were built from (E_J then comes from their traces)
  *   energy  : complex [nw][2] (output) = (E_J, E_K)
  * precision: LO_FP64, LO_FP32 or LO_BF16X3 (enum lo_precision); the reduced
- * ones need walker-major theta (LO_EUNSUPPORTED otherwise), nw <= 65535 and
+ * ones need [nw][M][n_occ] theta (LO_EUNSUPPORTED otherwise), nw <= 65535 and
  * n_occ <= 96 (LO_FP32) or <= 64 (LO_BF16X3),
  * and rewrite theta into a padded FP32 or split-BF16 copy in the context
- * workspace first.  flags may hold LO_THETA_ORBITAL_MAJOR or LO_EXACT_COULOMB
- * (not both). */
+ * workspace first.  flags may hold one of LO_THETA_ORBITAL_MAJOR,
+ * LO_THETA_TRANSPOSED and LO_EXACT_COULOMB. */
 int local_energy_lo(lo_ctx* ctx, const lo_factors* factors, int64_t nw, const double* theta,
                     const int32_t* info, int precision, unsigned flags, const double* lbar, double* energy);
 

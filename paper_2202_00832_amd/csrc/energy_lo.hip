@@ -33,7 +33,8 @@ namespace lofqmc {
 // per CU) and zero-fills a partial last slab.
 //
 // theta element (o, r, w) is read at theta[o * so + r * sr + w * sw], which
-// serves both layouts: walker-major [w][r][o] and orbital-major [o][r][w].
+// serves the three layouts: walker-major [w][r][o], orbital-major [o][r][w]
+// and transposed walker-major [w][o][r].
 // Work units (block of LO_OBLK orbitals, walker tile) go round-robin over the
 // 8 XCDs (workgroups are dispatched round-robin over XCDs) and the tiles of
 // one unit run side by side on one XCD: with walker-major theta the orbitals
@@ -195,6 +196,11 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_reg_kernel(int M, int64_t nw,
 // not overlap the products of the current one.  The buffer form is counted by
 // vmcnt alone and keeps the graded waits; the global form is kept for byte
 // offsets beyond 2^31 (factor rows or one orbital's theta slice).
+// TR (theta as [w][o][r], r contiguous): the 16 x 32 theta slab is loaded as
+// 32 runs of 16 consecutive r (256 bytes, two cache lines per walker) instead
+// of 512 elements from as many lines; it sits in LDS as [walker][r] with r
+// XOR-swizzled by the walker's low four bits, so the operand reads (16
+// walkers x 4 r per read) spread over all bank groups.
 // s_waitcnt vmcnt(0) through the builtin (not inline asm), so the compiler's
 // own wait insertion sees it.  gfx9 encoding: vmcnt in bits 3:0 and 15:14,
 // expcnt 6:4, lgkmcnt 11:8 (expcnt and lgkmcnt at their maximum: no wait)
@@ -211,7 +217,7 @@ __device__ __forceinline__ void with_group_count(int q, F&& f) {
   }
 }
 
-template <bool BUF>
+template <bool BUF, bool TR>
 __global__ __launch_bounds__(512) void lo_pass1_kernel(int M, int64_t nw, const double* __restrict__ rows,
                                                        const int* __restrict__ rowidx,
                                                        const int* __restrict__ tile_orb,
@@ -270,11 +276,14 @@ __global__ __launch_bounds__(512) void lo_pass1_kernel(int M, int64_t nw, const 
     asrc[k] = rows + (size_t)ar * M + 2 * cp;
     aoffs[k] = (uint32_t)(((size_t)ar * M + 2 * cp) * sizeof(double));
   }
-  // B: 16 x 32 slots, slot tid holds r = tid / 32, walker tid % 32 (clamped
-  // to a valid walker)
-  const int64_t bw = w0 + (tid % LO_WT) < nw ? w0 + (tid % LO_WT) : nw - 1;
-  const double2* bsrc = tho + (tid / LO_WT) * sr + bw * sw;
-  const uint32_t boff = (uint32_t)(((tid / LO_WT) * sr + bw * sw) * sizeof(double2));
+  // B: 16 x 32 slots, slot tid holds r = tid / 32, walker tid % 32, or with
+  // TR walker tid / 16, r = (tid % 16) ^ (walker % 16) (walkers clamped to a
+  // valid one)
+  const int bwl = TR ? tid / 16 : tid % LO_WT;
+  const int brl = TR ? (tid % 16) ^ (bwl & 15) : tid / LO_WT;
+  const int64_t bw = w0 + bwl < nw ? w0 + bwl : nw - 1;
+  const double2* bsrc = tho + brl * sr + bw * sw;
+  const uint32_t boff = (uint32_t)((brl * sr + bw * sw) * sizeof(double2));
   // raw descriptors (stride 0, byte ranges rows_bytes and theta_bytes; the
   // third word is the gfx9 default data format); only used when BUF
   const __amdgpu_buffer_rsrc_t ares = __builtin_amdgcn_make_buffer_rsrc((void*)rows, 0, (int)rows_bytes, 0x00020000);
@@ -320,8 +329,13 @@ __global__ __launch_bounds__(512) void lo_pass1_kernel(int M, int64_t nw, const 
     double2 b0[2], b1[2];
     auto read = [&](int s4, int slot) __attribute__((always_inline)) {
       const int rr = 4 * s4 + lk;
-      b0[slot] = sb[rr * LO_WT + lr];
-      b1[slot] = sb[rr * LO_WT + 16 + lr];
+      if constexpr (TR) {
+        b0[slot] = sb[lr * 16 + (rr ^ lr)];
+        b1[slot] = sb[(16 + lr) * 16 + (rr ^ lr)];
+      } else {
+        b0[slot] = sb[rr * LO_WT + lr];
+        b1[slot] = sb[rr * LO_WT + 16 + lr];
+      }
       const int aoff = abase + 2 * (((2 * s4) ^ e2) | (lk >> 1));
 #pragma unroll
       for (int q = 0; q < NQ; ++q) a[slot][q] = sa[aoff + 64 * NWV * q];
@@ -382,15 +396,16 @@ int lo_orbital_block() { return LO_OBLK; }
 
 hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
                            int64_t rows_count, const int* rowidx, const int* tiles, const int* blk, int nblk,
-                           int tmax, const double* theta, int orbital_major, double* qbar,
+                           int tmax, const double* theta, int theta_layout, double* qbar,
                            int64_t out_walker_stride) {
   if (nw <= 0 || ntiles <= 0) return hipSuccess;
   const int nwt = (int)((nw + LO_WT - 1) / LO_WT);
   const int64_t units = (int64_t)nblk * nwt;
   const int64_t grid = (int64_t)8 * ((units + 7) / 8) * tmax;
-  const int64_t so = orbital_major ? (int64_t)M * nw : 1;
-  const int64_t sr = orbital_major ? nw : n;
-  const int64_t sw = orbital_major ? 1 : (int64_t)M * n;
+  const bool om = theta_layout == THETA_ORBITAL, tr = theta_layout == THETA_TRANSPOSED;
+  const int64_t so = om ? (int64_t)M * nw : tr ? (int64_t)M : 1;
+  const int64_t sr = om ? nw : tr ? 1 : n;
+  const int64_t sw = om ? 1 : (int64_t)M * n;
   const int64_t orow_ = out_walker_stride ? (int64_t)1 : nw;
   const int64_t ow_ = out_walker_stride ? out_walker_stride : (int64_t)1;
   if (M % 16 != 0) {
@@ -405,8 +420,9 @@ hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, 
   const int64_t bbytes = ((int64_t)(M - 1) * sr + (nw - 1) * sw + 1) * (int64_t)sizeof(double2);
   const int64_t lim = INT32_MAX;   // descriptor range and offsets are 32-bit (kept signed)
   const bool buf = abytes <= lim && bbytes <= lim;
-  hipLaunchKernelGGL(buf ? lo_pass1_kernel<true> : lo_pass1_kernel<false>, dim3((unsigned)grid), dim3(512), 0, s, M,
-                     nw, rows, rowidx, tiles, tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax,
+  auto kern = tr ? (buf ? lo_pass1_kernel<true, true> : lo_pass1_kernel<false, true>)
+                 : (buf ? lo_pass1_kernel<true, false> : lo_pass1_kernel<false, false>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(512), 0, s, M, nw, rows, rowidx, tiles, tiles + ntiles, tiles + 2 * ntiles, blk, nblk, tmax,
                      (const double2*)theta, so, sr, sw, (double2*)qbar, orow_, ow_, nwt, (uint32_t)(buf ? abytes : 0),
                      (uint32_t)(buf ? bbytes : 0));
   return hipGetLastError();

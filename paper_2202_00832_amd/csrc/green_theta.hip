@@ -15,9 +15,10 @@
 //      P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im)); one workgroup per
 //      walker with O^{-1} in LDS (put back in natural order while it is staged),
 //      one wave per 16-row block.  theta is written
-//      walker-major [w][r][j] or, with the orbital-major flag, as [j][r][w];
-//      walkers 8g .. 8g+7 then run on the same XCD so that their interleaved
-//      16-byte stores meet in one L2.
+//      walker-major [w][r][j], as [w][j][r] (theta_w^T, with the MFMA operands
+//      swapped so that the stores stay 256-byte runs), or orbital-major as
+//      [j][r][w]; walkers 8g .. 8g+7 then run on the same XCD so that their
+//      interleaved 16-byte stores meet in one L2.
 #include <type_traits>
 
 #include "common.h"
@@ -488,9 +489,13 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
 //    CB column blocks (all NB of them up to 96 orbitals; beyond that the
 //    columns of O_w^{-1} no longer fit the LDS and blockIdx.y picks the part),
 //    the part of O_w^{-1} staged once in LDS, wave (q, h) takes the 16-row
-//    blocks q, q+4, ... against half h of the part's column blocks
+//    blocks q, q+4, ... against half h of the part's column blocks.
+//    TRANS (theta written as theta_w^T, [nw][n][M]): the two MFMA operands
+//    swap places, so the products give the blocks of theta_w^T = O_w^{-T}
+//    phi_w^T from the same fragments (same loads, same sums) and each lane's
+//    outputs run along r, the contiguous index of that layout.
 // ---------------------------------------------------------------------------
-template <int NB, int CB>
+template <int NB, int CB, bool TRANS>
 __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, int64_t w0, int64_t nwc,
                                                     const double2* __restrict__ phi,
                                                     const double2* __restrict__ Oinv, const int* __restrict__ perm,
@@ -580,24 +585,34 @@ __global__ __launch_bounds__(512) void apply_kernel(int M, int n, int64_t nw, in
           const int JJ = hf * JH + J;   // block within the part
           if (JJ < CB && c0 + 16 * JJ < NP) {
             const double2 bv = kk < NP ? sB[kk * CW + 16 * JJ + lr] : make_double2(0.0, 0.0);
-            P1[J] = mfma16(av[u].x, bv.x, P1[J]);
-            P2[J] = mfma16(av[u].y, bv.y, P2[J]);
-            P3[J] = mfma16(as, bv.x + bv.y, P3[J]);
+            if constexpr (TRANS) {
+              P1[J] = mfma16(bv.x, av[u].x, P1[J]);
+              P2[J] = mfma16(bv.y, av[u].y, P2[J]);
+              P3[J] = mfma16(bv.x + bv.y, as, P3[J]);
+            } else {
+              P1[J] = mfma16(av[u].x, bv.x, P1[J]);
+              P2[J] = mfma16(av[u].y, bv.y, P2[J]);
+              P3[J] = mfma16(as, bv.x + bv.y, P3[J]);
+            }
           }
         }
       }
     }
 #pragma unroll
     for (int J = 0; J < JH; ++J) {
-      const int j = c0 + 16 * (hf * JH + J) + lr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * rb + 4 * v + lk;
+        // element v of the accumulator: (row 4 v + lk, column lr) of the
+        // 16 x 16 block, (r, j) or, with TRANS, (j, r)
+        const int j = c0 + 16 * (hf * JH + J) + (TRANS ? 4 * v + lk : lr);
+        const int row = 16 * rb + (TRANS ? lr : 4 * v + lk);
         if (hf * JH + J < CB && row < M && j < n) {
           const double re = P1[J][v] - P2[J][v];
           const double im = P3[J][v] - P1[J][v] - P2[J][v];
           const double2 val = bad ? make_double2(nan, nan) : make_double2(re, im);
-          if (orbital_major)
+          if (TRANS)
+            theta[(w * (size_t)n + j) * M + row] = val;
+          else if (orbital_major)
             theta[((size_t)j * M + row) * nw + w] = val;
           else
             theta[(w * (size_t)M + row) * n + j] = val;
@@ -621,7 +636,7 @@ size_t green_theta_workspace(int n, int64_t nw) {
 
 template <int NB>
 static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
-                            const double* phi, double* theta, double* logov, int* info, int orbital_major,
+                            const double* phi, double* theta, double* logov, int* info, int theta_layout,
                             double* work, const ProfHook* prof, int flag_small) {
   double2* O = reinterpret_cast<double2*>(work);
   int* perm = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + gt_perm_offset(n, nw));
@@ -640,22 +655,27 @@ static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0,
   constexpr int CB = NB <= 6 ? NB : (NB + 1) / 2;
   constexpr int parts = (NB + CB - 1) / CB;
   prof_mark(prof, "apply_kernel");
-  hipLaunchKernelGGL((apply_kernel<NB, CB>), dim3((unsigned)grid, parts), dim3(512), 0, s, M, n, nw, w0, nwc,
-                     (const double2*)phi, (const double2*)O, perm, info, (double2*)theta, orbital_major);
+  if (theta_layout == THETA_TRANSPOSED)
+    hipLaunchKernelGGL((apply_kernel<NB, CB, true>), dim3((unsigned)grid, parts), dim3(512), 0, s, M, n, nw, w0, nwc,
+                       (const double2*)phi, (const double2*)O, perm, info, (double2*)theta, 0);
+  else
+    hipLaunchKernelGGL((apply_kernel<NB, CB, false>), dim3((unsigned)grid, parts), dim3(512), 0, s, M, n, nw, w0,
+                       nwc, (const double2*)phi, (const double2*)O, perm, info, (double2*)theta,
+                       theta_layout == THETA_ORBITAL ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
-                              const double* phi, double* theta, double* logov, int* info, int orbital_major,
+                              const double* phi, double* theta, double* logov, int* info, int theta_layout,
                               double* work, const ProfHook* prof, int flag_small) {
   if (nwc <= 0) return hipSuccess;
-  if (n <= 16) return launch_gt<1>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
-  if (n <= 32) return launch_gt<2>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
-  if (n <= 48) return launch_gt<3>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
-  if (n <= 64) return launch_gt<4>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
-  if (n <= 80) return launch_gt<5>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
-  if (n <= 96) return launch_gt<6>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
-  return launch_gt<7>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, orbital_major, work, prof, flag_small);
+  if (n <= 16) return launch_gt<1>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, theta_layout, work, prof, flag_small);
+  if (n <= 32) return launch_gt<2>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, theta_layout, work, prof, flag_small);
+  if (n <= 48) return launch_gt<3>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, theta_layout, work, prof, flag_small);
+  if (n <= 64) return launch_gt<4>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, theta_layout, work, prof, flag_small);
+  if (n <= 80) return launch_gt<5>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, theta_layout, work, prof, flag_small);
+  if (n <= 96) return launch_gt<6>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, theta_layout, work, prof, flag_small);
+  return launch_gt<7>(s, M, n, nw, w0, nwc, trial, phi, theta, logov, info, theta_layout, work, prof, flag_small);
 }
 
 }  // namespace lofqmc

@@ -24,9 +24,15 @@ inline void prof_mark(const ProfHook* h, const char* name) {
 // arrays (and by the workspace), so disjoint walker ranges can run on
 // different streams.
 size_t green_theta_workspace(int n, int64_t nw);
+// Layouts of theta (complex, element (w, r, o): walker, basis index, orbital)
+enum ThetaLayout {
+  THETA_WALKER = 0,       // [nw][M][n]: theta_w row-major
+  THETA_ORBITAL = 1,      // [n][M][nw]: walkers contiguous
+  THETA_TRANSPOSED = 2    // [nw][n][M]: theta_w^T, the basis index contiguous
+};
 // flag_small: info = -k for the first pivot k below 2^-40 of the largest |re| + |im| of O
 hipError_t launch_green_theta(hipStream_t s, int M, int n, int64_t nw, int64_t w0, int64_t nwc, const double* trial,
-                              const double* phi, double* theta, double* logov, int* info, int orbital_major,
+                              const double* phi, double* theta, double* logov, int* info, int theta_layout,
                               double* work, const ProfHook* prof, int flag_small);
 
 int full_num_chunks(int64_t X, int64_t nw);
@@ -53,7 +59,7 @@ hipError_t launch_reduce_partials(hipStream_t s, int64_t nw, int nchunk, const d
 // rowidx entry is below it)
 hipError_t launch_lo_pass1(hipStream_t s, int M, int n, int64_t nw, int ntiles, const double* rows,
                            int64_t rows_count, const int* rowidx, const int* tiles, const int* blk, int nblk,
-                           int tmax, const double* theta, int orbital_major, double* qbar,
+                           int tmax, const double* theta, int theta_layout, double* qbar,
                            int64_t out_walker_stride);
 // name of the pass-1 kernel launch_lo_pass1 runs for this M (direct-to-LDS
 // staging when M is a multiple of 16, register staging otherwise)

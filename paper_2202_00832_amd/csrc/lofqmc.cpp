@@ -791,6 +791,16 @@ int build_factors(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, const d
 #undef TRY_ALLOC
 }
 
+// theta layout named by the layout flags (at most one may be set)
+static int theta_layout_of(unsigned flags) {
+  return (flags & LO_THETA_TRANSPOSED) ? lofqmc::THETA_TRANSPOSED
+         : (flags & LO_THETA_ORBITAL_MAJOR) ? lofqmc::THETA_ORBITAL
+                                            : lofqmc::THETA_WALKER;
+}
+static bool two_layouts(unsigned flags) {
+  return (flags & LO_THETA_ORBITAL_MAJOR) && (flags & LO_THETA_TRANSPOSED);
+}
+
 // Argument checks of the LO energy call and the scratch bytes it needs
 // (Q-bar intermediates, pass-2 partial sums, reduced-precision theta copy).
 int lo_energy_check(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const double* lbar,
@@ -801,13 +811,14 @@ int lo_energy_check(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
   if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
   if (precision != LO_FP64 && precision != LO_FP32 && precision != LO_BF16X3)
     return fail(ctx, LO_EINVAL, "unknown precision %d", precision);
-  if (flags & ~(unsigned)(LO_THETA_ORBITAL_MAJOR | LO_EXACT_COULOMB))
+  if (flags & ~(unsigned)(LO_THETA_ORBITAL_MAJOR | LO_THETA_TRANSPOSED | LO_EXACT_COULOMB))
     return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
-  const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
+  if (two_layouts(flags)) return fail(ctx, LO_EINVAL, "two theta layouts in flags");
+  const bool other_layout = theta_layout_of(flags) != lofqmc::THETA_WALKER;
   const bool exact_j = (flags & LO_EXACT_COULOMB) != 0;
-  if (precision != LO_FP64 && orbital_major)
+  if (precision != LO_FP64 && other_layout)
     return fail(ctx, LO_EUNSUPPORTED, "reduced precision reads walker-major theta only");
-  if (exact_j && orbital_major) return fail(ctx, LO_EUNSUPPORTED, "LO_EXACT_COULOMB reads walker-major theta only");
+  if (exact_j && other_layout) return fail(ctx, LO_EUNSUPPORTED, "LO_EXACT_COULOMB reads walker-major theta only");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
   if (precision != LO_FP64 && nw > 65535) return fail(ctx, LO_EUNSUPPORTED, "reduced precision: nw above 65535");
   if (precision != LO_FP64 && f->n > (precision == LO_FP32 ? kMaxOccWide : kMaxOcc))
@@ -833,7 +844,6 @@ int lo_energy_check(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* 
 int lo_energy_enqueue(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double* theta, const int32_t* info,
                       int precision, unsigned flags, const double* lbar, double* energy, char* base,
                       const ProfScope& prof) {
-  const bool orbital_major = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
   const bool exact_j = (flags & LO_EXACT_COULOMB) != 0;
   const int64_t M = f->M, n = f->n;
   const int nchunk = (int)(f->n_ent / lofqmc::lo_pass2_chunk());
@@ -849,7 +859,7 @@ int lo_energy_enqueue(lo_ctx* ctx, const lo_factors* f, int64_t nw, const double
     HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)M, (int)n, nw, f->ntiles, f->rows, f->total_rows,
                                              f->d_rowidx,
                                              f->d_tiles, f->d_tiles + 3 * f->ntiles, f->nblk, f->tmax, theta,
-                                             orbital_major ? 1 : 0, qbar, 0));
+                                             theta_layout_of(flags), qbar, 0));
   } else if (f->ntiles > 0) {
     void* tlp = base + qbytes + pbytes;
     prof.mark("lp_convert_kernel");
@@ -1114,6 +1124,7 @@ int local_energy_hr(lo_ctx* ctx, const lo_hr* h, int64_t nw, const double* theta
   ctx->err.clear();
   if (!h) return fail(ctx, LO_EINVAL, "null pair blocks");
   if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
+  if (flags & LO_THETA_TRANSPOSED) return fail(ctx, LO_EUNSUPPORTED, "the ERI route reads [nw][M][n] or [n][M][nw] theta");
   if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
   if (nw == 0) return LO_OK;
@@ -1361,10 +1372,11 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   if (nw < 0) return fail(ctx, LO_EINVAL, "nw < 0");
   // one 256-thread workgroup per walker: the grid's work-item count must fit 32 bits
   if (nw > ((int64_t)1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^24");
-  if (flags & ~(unsigned)LO_THETA_ORBITAL_MAJOR) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(unsigned)(LO_THETA_ORBITAL_MAJOR | LO_THETA_TRANSPOSED))
+    return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  if (two_layouts(flags)) return fail(ctx, LO_EINVAL, "two theta layouts in flags");
   if (nw == 0) return LO_OK;
   if (!theta || !energy) return fail(ctx, LO_EINVAL, "null array");
-  const bool om = (flags & LO_THETA_ORBITAL_MAJOR) != 0;
   const int nchunk = lofqmc::md_pair_chunks(md->npairs);
   const size_t qbytes = align256(sizeof(double) * 2 * (size_t)md->n_out_rows * nw);
   const size_t mbytes = align256(lofqmc::md_walker_bytes(md->na, (int)md->n, (int)md->ncas) * (size_t)nw);
@@ -1403,7 +1415,7 @@ int local_energy_md(lo_ctx* ctx, const lo_md* md, int64_t nw, const double* thet
   prof.mark(lofqmc::lo_pass1_name((int)md->M));
   HIP_OR_FAIL(ctx, lofqmc::launch_lo_pass1(ctx->stream, (int)md->M, (int)md->n, nw, md->ntiles, md->rows,
                                            md->total_rows + md->nav, md->d_rowidx, md->d_tiles, md->d_tiles + 3 * md->ntiles, md->nblk,
-                                           md->tmax, theta, om ? 1 : 0, qbar, md->n_out_rows));
+                                           md->tmax, theta, theta_layout_of(flags), qbar, md->n_out_rows));
   prof.mark("md_prep_kernel");
   HIP_OR_FAIL(ctx, lofqmc::launch_md_prep(ctx->stream, g, mwork, ovlp_ratio));
   prof.mark("md_energy_kernel");
@@ -1425,15 +1437,16 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
   if (n_occ > kMaxOccTheta) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d", kMaxOccTheta);
   if (M > (1 << 24)) return fail(ctx, LO_EUNSUPPORTED, "M above 2^24");
   if (nw > ((int64_t)1 << 31) - 1) return fail(ctx, LO_EUNSUPPORTED, "nw above 2^31-1");
-  if (flags & ~(unsigned)(LO_THETA_ORBITAL_MAJOR | LO_FLAG_SMALL_PIVOT))
+  if (flags & ~(unsigned)(LO_THETA_ORBITAL_MAJOR | LO_THETA_TRANSPOSED | LO_FLAG_SMALL_PIVOT))
     return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
+  if (two_layouts(flags)) return fail(ctx, LO_EINVAL, "two theta layouts in flags");
   if (nw == 0) return LO_OK;
   if (!trial || !phi || !theta || !info) return fail(ctx, LO_EINVAL, "null array");
   int rc = ensure_ws(ctx, align256(lofqmc::green_theta_workspace((int)n_occ, nw)));
   if (rc) return rc;
   ProfScope prof(ctx);
   HIP_OR_FAIL(ctx, lofqmc::launch_green_theta(ctx->stream, (int)M, (int)n_occ, nw, 0, nw, trial, phi, theta, log_ovlp,
-                                              info, (flags & LO_THETA_ORBITAL_MAJOR) ? 1 : 0, (double*)ctx->ws,
+                                              info, theta_layout_of(flags), (double*)ctx->ws,
                                               prof.get(), (flags & LO_FLAG_SMALL_PIVOT) ? 1 : 0));
   return LO_OK;
 }
@@ -1552,7 +1565,7 @@ hipError_t batch_enqueue(lo_batch* b, hipStream_t st) {
     const lo_system& s = b->sys[k];
     if (!s.phi) continue;
     e = lofqmc::launch_green_theta(st, (int)s.M, (int)s.n_occ, s.nw, 0, s.nw, s.trial, s.phi, s.theta, nullptr,
-                                   s.info, 0, b->gws[k], nullptr, 0);
+                                   s.info, lofqmc::THETA_WALKER, b->gws[k], nullptr, 0);
     if (e != hipSuccess) return e;
   }
   for (int k = 0; k < b->nsys; ++k) {

@@ -23,6 +23,7 @@ LO_THETA_ORBITAL_MAJOR = 1
 LO_EXACT_COULOMB = 2
 LO_FACTORS_RANDOMIZED = 1
 LO_FLAG_SMALL_PIVOT = 4
+LO_THETA_TRANSPOSED = 8
 RESIDUAL_NFEAT = 4   # per-orbital features of the learned residual
 _NAMES = {0: "LO_OK", -1: "LO_EINVAL", -2: "LO_ENOMEM", -3: "LO_EHIP", -4: "LO_EUNSUPPORTED", -5: "LO_ESOLVER"}
 
@@ -353,6 +354,20 @@ class Batch:
             pass
 
 
+
+def _theta_layout(theta, M, n, orbital_major, transposed):
+    """(nw, layout flag, expected shape) of a theta tensor: [nw][M][n],
+    [n][M][nw] (orbital_major) or [nw][n][M] (transposed)."""
+    if orbital_major and transposed:
+        raise ValueError("theta cannot be orbital-major and transposed")
+    if orbital_major:
+        nw = theta.shape[2]
+        return nw, LO_THETA_ORBITAL_MAJOR, (n, M, nw)
+    nw = theta.shape[0]
+    if transposed:
+        return nw, LO_THETA_TRANSPOSED, (nw, n, M)
+    return nw, 0, (nw, M, n)
+
 class Context:
     """A library context bound to a HIP stream (default: torch's current stream)."""
 
@@ -465,15 +480,18 @@ class Context:
 
     # -- per walker ---------------------------------------------------------------
     def green_theta(self, trial, phi, theta=None, log_ovlp=None, info=None, orbital_major=False,
-                    flag_small_pivots=False):
-        """theta is [nw][M][n] (walker-major) or [n][M][nw] when orbital_major.
+                    flag_small_pivots=False, transposed=False):
+        """theta is [nw][M][n] (walker-major), [n][M][nw] when orbital_major or
+        [nw][n][M] when transposed.
         flag_small_pivots: nearly singular overlaps get info < 0 (a warning)."""
         import torch
         nw, M, n = phi.shape
         _check_dev("trial", trial, torch.float64, (M, n))
         _check_dev("phi", phi, torch.complex128, (nw, M, n))
         dev = phi.device
-        tshape = (n, M, nw) if orbital_major else (nw, M, n)
+        if orbital_major and transposed:
+            raise ValueError("theta cannot be orbital-major and transposed")
+        tshape = (n, M, nw) if orbital_major else (nw, n, M) if transposed else (nw, M, n)
         if theta is None:
             theta = torch.empty(tshape, dtype=torch.complex128, device=dev)
         if log_ovlp is None:
@@ -483,7 +501,8 @@ class Context:
         _check_dev("theta", theta, torch.complex128, tshape)
         _check_dev("log_ovlp", log_ovlp, torch.complex128, (nw,))
         _check_dev("info", info, torch.int32, (nw,))
-        flags = (LO_THETA_ORBITAL_MAJOR if orbital_major else 0) | (LO_FLAG_SMALL_PIVOT if flag_small_pivots else 0)
+        flags = ((LO_THETA_ORBITAL_MAJOR if orbital_major else 0) | (LO_THETA_TRANSPOSED if transposed else 0)
+                 | (LO_FLAG_SMALL_PIVOT if flag_small_pivots else 0))
         self._check(self._lib.green_theta(self._h, M, n, nw, _ptr(trial), _ptr(phi), _ptr(theta), _ptr(log_ovlp),
                                           _ptr(info), flags))
         return theta, log_ovlp, info
@@ -504,8 +523,9 @@ class Context:
         return energy
 
     def local_energy_lo(self, factors: Factors, theta, info=None, energy=None, precision=LO_FP64, flags=0,
-                        orbital_major=False, noalloc=False, lbar=None):
-        """theta is [nw][M][n], or [n][M][nw] when orbital_major.  noalloc=True
+                        orbital_major=False, noalloc=False, lbar=None, transposed=False):
+        """theta is [nw][M][n], [n][M][nw] when orbital_major, or [nw][n][M]
+        when transposed.  noalloc=True
         calls local_energy_lo_noalloc (fixed scratch, no device allocation in
         the library; `energy` should then be passed in by the caller).  With
         lbar ([X][M][n], the vectors the factors were built from) E_J comes
@@ -514,13 +534,9 @@ class Context:
         if lbar is not None:
             _check_dev("lbar", lbar, torch.float64, (lbar.shape[0], factors.M, factors.n_occ))
             flags = flags | LO_EXACT_COULOMB
-        if orbital_major:
-            nw = theta.shape[2]
-            _check_dev("theta", theta, torch.complex128, (factors.n_occ, factors.M, nw))
-            flags = flags | LO_THETA_ORBITAL_MAJOR
-        else:
-            nw = theta.shape[0]
-            _check_dev("theta", theta, torch.complex128, (nw, factors.M, factors.n_occ))
+        nw, lflag, tshape = _theta_layout(theta, factors.M, factors.n_occ, orbital_major, transposed)
+        _check_dev("theta", theta, torch.complex128, tshape)
+        flags = flags | lflag
         if info is not None:
             _check_dev("info", info, torch.int32, (nw,))
         if energy is None:
@@ -582,18 +598,14 @@ class Context:
             c.ctypes.data, ctypes.byref(h)))
         return MdTrial(h.value, factors)
 
-    def local_energy_md(self, md: MdTrial, theta, info=None, energy=None, ovlp_ratio=None, orbital_major=False):
+    def local_energy_md(self, md: MdTrial, theta, info=None, energy=None, ovlp_ratio=None, orbital_major=False,
+                        transposed=False):
         """Multi-determinant LO energy; theta from green_theta with the reference
-        determinant, [nw][M][n_occ] or [n_occ][M][nw] when orbital_major."""
+        determinant, [nw][M][n_occ], [n_occ][M][nw] when orbital_major or
+        [nw][n_occ][M] when transposed."""
         import torch
-        flags = 0
-        if orbital_major:
-            nw = theta.shape[2]
-            _check_dev("theta", theta, torch.complex128, (md.n_occ, md.M, nw))
-            flags = LO_THETA_ORBITAL_MAJOR
-        else:
-            nw = theta.shape[0]
-            _check_dev("theta", theta, torch.complex128, (nw, md.M, md.n_occ))
+        nw, flags, tshape = _theta_layout(theta, md.M, md.n_occ, orbital_major, transposed)
+        _check_dev("theta", theta, torch.complex128, tshape)
         if info is not None:
             _check_dev("info", info, torch.int32, (nw,))
         if energy is None:

@@ -56,6 +56,17 @@ def test_validation_errors_need_no_device(lib):
         assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, 3, fake, fake) == L.LO_EUNSUPPORTED
         assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, 7, 0, fake) == L.LO_EINVAL   # precision
         assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP32, 1, None, fake) == L.LO_EUNSUPPORTED
+        # transposed theta ([nw][n][M]): one layout flag at a time, FP64 LO without exact Coulomb
+        T = L.LO_THETA_TRANSPOSED
+        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, T | 1, None, fake) == L.LO_EINVAL
+        assert b"two theta layouts" in lib.lo_last_error(h)
+        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP32, T, None, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_lo(h, fake, 4, fake, None, L.LO_FP64, T | L.LO_EXACT_COULOMB, fake,
+                                   fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_lo_noalloc(h, fake, 4, fake, None, L.LO_FP64, T | 1, None, fake) == L.LO_EINVAL
+        assert lib.green_theta(h, 8, 2, 3, fake, fake, fake, None, fake, T | 1) == L.LO_EINVAL
+        assert lib.green_theta(h, 8, 2, 0, None, None, None, None, None, T) == L.LO_OK   # empty batch
+        assert lib.local_energy_hr(h, fake, 4, fake, None, T, fake) == L.LO_EUNSUPPORTED
         assert lib.local_energy_lo(h, fake, 4, fake, None, 9, 0, None, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP64, 7, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, -3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
@@ -145,6 +156,8 @@ def test_multideterminant_validation_needs_no_device(lib):
         assert lib.build_md_trial(h, fake, 4, 1, fake, 1, 0, one, None, None, c, None) == L.LO_EINVAL
         assert lib.local_energy_md(h, None, 4, fake, None, 0, fake, None) == L.LO_EINVAL
         assert lib.local_energy_md(None, fake, 4, fake, None, 0, fake, None) == L.LO_EINVAL
+        assert lib.local_energy_md(h, fake, 4, fake, None, L.LO_THETA_TRANSPOSED | 1, fake, None) == L.LO_EINVAL
+        assert lib.local_energy_md(h, fake, 4, fake, None, L.LO_EXACT_COULOMB, fake, None) == L.LO_EINVAL
         assert lib.lo_md_destroy(None) == L.LO_OK
         assert lib.lo_md_info(None, None, None, None, None, None) == L.LO_EINVAL
     finally:

@@ -2,7 +2,8 @@
 
 400-site chain, 60 orbitals per spin, 799 Cholesky vectors, 512 walkers: the
 whole batch is evaluated on the GPU exactly as bench.py does (walker-major theta
-for the full route, orbital-major theta for the LO route); the CPU reference
+for the full route, transposed theta [w][j][r] for the LO route at the headline
+threshold; orbital-major at eps = 1e-5); the CPU reference
 recomputes a sample of walkers one by one from the same inputs (its own
 half-rotation, overlap inverse and SVD factors).  Properties that hold at any
 size are checked on every walker.
@@ -41,13 +42,16 @@ def run():
     theta_om, _, info_om = ctx.green_theta(trial, phi, orbital_major=True)
     e_lo = ctx.local_energy_lo(fac, theta_om, info_om, orbital_major=True)
     # the headline threshold: orbitals touch more than 192 factor rows, so
-    # pass 1 cuts each into two tiles; walker-major theta as in the bench
+    # pass 1 cuts each into two tiles; transposed theta as in the bench
     fac7 = ctx.build_lo_factors(lbar, EPS_TIGHT)
-    e_lo7 = ctx.local_energy_lo(fac7, theta, info)
+    theta_tr, _, info_tr = ctx.green_theta(trial, phi, transposed=True)
+    e_lo7 = ctx.local_energy_lo(fac7, theta_tr, info_tr, transposed=True)
+    e_lo7_wm = ctx.local_energy_lo(fac7, theta, info)
     torch.cuda.synchronize()
     out = dict(system=s, theta=theta.cpu().numpy(), logov=logov.cpu().numpy(), info=info.cpu().numpy(),
                e_full=e_full.cpu().numpy(), e_lo=e_lo.cpu().numpy(), ranks=fac.info()["ranks"],
-               theta_om=theta_om.cpu().numpy(), e_lo7=e_lo7.cpu().numpy(), ranks7=fac7.info()["ranks"])
+               theta_om=theta_om.cpu().numpy(), e_lo7=e_lo7.cpu().numpy(), ranks7=fac7.info()["ranks"],
+               theta_tr=theta_tr.cpu().numpy(), info_tr=info_tr.cpu().numpy(), e_lo7_wm=e_lo7_wm.cpu().numpy())
     fac.close()
     fac7.close()
     ctx.close()
@@ -68,12 +72,13 @@ def ref(run):
 
 
 def test_theta_sampled_walkers(run, ref):
-    assert (run["info"] == 0).all()
+    assert (run["info"] == 0).all() and (run["info_tr"] == 0).all()
     for k, w in enumerate(SAMPLE):
         t = ref["thetas"][k]
         scale = np.abs(t).max()
         assert np.abs(run["theta"][w] - t).max() <= 1e-12 * scale
         assert np.abs(run["theta_om"][:, :, w].T - t).max() <= 1e-12 * scale
+        assert np.abs(run["theta_tr"][w].T - t).max() <= 1e-12 * scale
         assert abs(run["logov"][w].real - ref["logdets"][k].real) <= 1e-10
         assert abs(np.angle(np.exp(1j * (run["logov"][w].imag - ref["logdets"][k].imag)))) <= 1e-10
 
@@ -114,6 +119,8 @@ def test_lo_energy_at_the_headline_threshold(run, ref, ref_svd):
     two tiles per orbital."""
     assert 2 * run["ranks7"].sum() - np.trace(run["ranks7"]) > 192 * run["ranks7"].shape[0]
     _check_lo(run["ranks7"], run["e_lo7"], E.lo_truncate(ref_svd, EPS_TIGHT), ref, EPS_TIGHT)
+    # every walker: the transposed layout gives the walker-major energies bit for bit
+    assert np.array_equal(run["e_lo7"].view(np.float64), run["e_lo7_wm"].view(np.float64))
 
 
 def test_lo_energy_sampled_walkers_and_ranks(run, ref, ref_lo):

@@ -46,14 +46,17 @@ def host(t):
     return t.cpu().numpy()
 
 
-def gpu_md(ctx, chol, C, n, nao, holes, parts, coeffs, walkers, eps, orbital_major=False):
+def gpu_md(ctx, chol, C, n, nao, holes, parts, coeffs, walkers, eps, layout="walker"):
+    """layout of theta: "walker" [nw][M][n], "orbital" [n][M][nw] or
+    "transposed" [nw][n][M]."""
     lbar = ctx.build_half_rotated_chol(dev(chol), dev(C))
     f = ctx.build_lo_factors(lbar, eps)
     md = ctx.build_md_trial(f, n, nao, dev(C), holes, parts, coeffs)
-    theta, _, info = ctx.green_theta(dev(C[:, :n]), dev(walkers), orbital_major=orbital_major)
+    kw = dict(orbital_major=layout == "orbital", transposed=layout == "transposed")
+    theta, _, info = ctx.green_theta(dev(C[:, :n]), dev(walkers), **kw)
     ovr = torch.empty(len(walkers), dtype=torch.complex128, device="cuda")
-    e = ctx.local_energy_md(md, theta, info, ovlp_ratio=ovr, orbital_major=orbital_major)
-    again = ctx.local_energy_md(md, theta, info, orbital_major=orbital_major)
+    e = ctx.local_energy_md(md, theta, info, ovlp_ratio=ovr, **kw)
+    again = ctx.local_energy_md(md, theta, info, **kw)
     out = dict(e=host(e), ovr=host(ovr), again=host(again), info=host(info), ranks=f.info()["ranks"])
     md.close()
     f.close()
@@ -97,24 +100,24 @@ def test_cas_chain_exact_threshold_equals_cholesky_route(ctx):
         assert abs(g["e"][w, 0] - ej) <= TOL_E and abs(g["e"][w, 1] - ek) <= TOL_E
 
 
-@pytest.mark.parametrize("M,n,nao,nav,ndet,maxe,nw,om", [
-    (24, 4, 1, 1, 2, 1, 3, False),      # NA = 1
-    (30, 6, 2, 1, 3, 1, 9, True),       # NA = 2
-    (36, 7, 3, 2, 10, 2, 17, False),    # NA = 3
-    (40, 9, 4, 3, 30, 3, 33, True),     # NA = 4
-    (44, 10, 5, 4, 90, 4, 70, False),   # NA = 5, four determinant chunks of 32
-    (48, 12, 6, 6, 150, 6, 65, True),   # NA = 6, sextuples
-    (30, 8, 3, 0, 1, 0, 10, False),     # no active virtual orbitals: the reference alone
+@pytest.mark.parametrize("M,n,nao,nav,ndet,maxe,nw,layout", [
+    (24, 4, 1, 1, 2, 1, 3, "walker"),         # NA = 1
+    (30, 6, 2, 1, 3, 1, 9, "orbital"),        # NA = 2
+    (36, 7, 3, 2, 10, 2, 17, "transposed"),   # NA = 3
+    (40, 9, 4, 3, 30, 3, 33, "orbital"),      # NA = 4
+    (44, 10, 5, 4, 90, 4, 70, "walker"),      # NA = 5, four determinant chunks of 32
+    (48, 12, 6, 6, 150, 6, 65, "transposed"), # NA = 6, sextuples
+    (30, 8, 3, 0, 1, 0, 10, "walker"),        # no active virtual orbitals: the reference alone
 ])
-def test_active_space_shapes(ctx, M, n, nao, nav, ndet, maxe, nw, om):
-    print("md shape M=%d n=%d %dx%d ndet=%d nw=%d om=%d" % (M, n, nao, nav, ndet, nw, om), flush=True)
+def test_active_space_shapes(ctx, M, n, nao, nav, ndet, maxe, nw, layout):
+    print("md shape M=%d n=%d %dx%d ndet=%d nw=%d %s" % (M, n, nao, nav, ndet, nw, layout), flush=True)
     rng = np.random.default_rng(M * 100 + n)
     chol = synth.random_symmetric_cholesky(M, 12, rng)
     C = np.linalg.qr(rng.standard_normal((M, n + nav)))[0]
     holes, parts, coeffs = synth.cas_expansion(n, nao, nav, ndet, maxe, rng)
     walkers = synth.noisy_walkers(C[:, :n], nw, 0.3, rng)
     eps = 1e-4
-    g = gpu_md(ctx, chol, C, n, nao, holes, parts, coeffs, walkers, eps, orbital_major=om)
+    g = gpu_md(ctx, chol, C, n, nao, holes, parts, coeffs, walkers, eps, layout=layout)
     sample = sorted(set([0, nw // 2, nw - 1]))
     ref, den, ranks = reference(chol, C, n, nao, holes, parts, coeffs, walkers[sample], eps)
     assert np.array_equal(g["ranks"], ranks)

@@ -38,9 +38,10 @@ def run():
     lbar = ctx.build_half_rotated_chol(d(s.chol), C)
     f = ctx.build_lo_factors(lbar, cfg.epsilon)
     md = ctx.build_md_trial(f, cfg.n, cfg.n_act_occ, C, s.holes, s.particles, s.coeffs)
-    theta, _, info = ctx.green_theta(d(s.reference), d(s.walkers))
+    # transposed theta, as the benchmark's multi-determinant step runs it
+    theta, _, info = ctx.green_theta(d(s.reference), d(s.walkers), transposed=True)
     ovr = torch.empty(cfg.nw, dtype=torch.complex128, device="cuda")
-    e = ctx.local_energy_md(md, theta, info, ovlp_ratio=ovr)
+    e = ctx.local_energy_md(md, theta, info, ovlp_ratio=ovr, transposed=True)
     torch.cuda.synchronize()
     out = dict(system=s, e=e.cpu().numpy(), ovr=ovr.cpu().numpy(), info=info.cpu().numpy(),
                ranks=f.info()["ranks"])

@@ -102,6 +102,12 @@ def test_green_theta(ctx, M, n, nw):
     assert (host(info_om) == 0).all()
     assert np.abs(theta_om.transpose(2, 1, 0) - ref).max() <= 1e-12 * scale
     assert np.array_equal(host(logov_om), logov)
+    # transposed output [w][j][r] (the apply kernel's operands swapped)
+    theta_tr, logov_tr, info_tr = ctx.green_theta(dev(trial), dev(walkers), transposed=True)
+    theta_tr = host(theta_tr)
+    assert (host(info_tr) == 0).all()
+    assert np.abs(theta_tr.transpose(0, 2, 1) - ref).max() <= 1e-12 * scale
+    assert np.array_equal(host(logov_tr), logov)
     # log det: real part exactly comparable, imaginary part modulo 2 pi
     assert np.abs(logov.real - ref_ld.real).max() <= 1e-11
     dphi = np.angle(np.exp(1j * (logov.imag - ref_ld.imag)))
@@ -119,8 +125,13 @@ def test_green_theta_many_walkers_with_singular_ones(ctx):
     walkers[250, :, 16] = 0.0                  # which stay zero through the elimination
     theta, logov, info = ctx.green_theta(dev(trial), dev(walkers))
     theta_om, logov_om, info_om = ctx.green_theta(dev(trial), dev(walkers), orbital_major=True)
-    theta, logov, info, theta_om = host(theta), host(logov), host(info), host(theta_om)
+    theta_tr, _, info_tr = ctx.green_theta(dev(trial), dev(walkers), transposed=True)
+    theta, logov, info, theta_om, theta_tr = host(theta), host(logov), host(info), host(theta_om), host(theta_tr)
     assert np.array_equal(host(info_om), info)
+    assert np.array_equal(host(info_tr), info)
+    # walkers with a zero pivot get NaN theta in every layout
+    for t in (theta[[5, 250]], theta_om.transpose(2, 1, 0)[[5, 250]], theta_tr[[5, 250]]):
+        assert np.isnan(t.real).all() and np.isnan(t.imag).all()
     assert (info[5], info[250]) == (4, 17)
     assert (E.green_theta(trial, walkers[5])[2], E.green_theta(trial, walkers[250])[2]) == (4, 17)
     ok = np.ones(nw, bool)
@@ -131,6 +142,7 @@ def test_green_theta_many_walkers_with_singular_ones(ctx):
     scale = np.abs(ref).max()
     assert np.abs(theta[ok] - ref).max() <= 1e-12 * scale
     assert np.abs(theta_om.transpose(2, 1, 0)[ok] - ref).max() <= 1e-12 * scale
+    assert np.abs(theta_tr.transpose(0, 2, 1)[ok] - ref).max() <= 1e-12 * scale
     assert np.abs(logov[ok].real - ref_ld.real).max() <= 1e-11
     assert np.abs(np.angle(np.exp(1j * (logov[ok].imag - ref_ld.imag)))).max() <= 1e-11
     assert np.array_equal(host(logov_om)[ok], logov[ok])
@@ -237,6 +249,10 @@ def _lo_case(ctx, chol, trial, walkers, eps):
     theta_om, _, info_om = ctx.green_theta(dev(trial), dev(walkers), orbital_major=True)
     got_om = host(ctx.local_energy_lo(f, theta_om, info_om, orbital_major=True))
     assert np.array_equal(got.view(np.float64), got_om.view(np.float64))
+    # transposed theta: the same products in the same order from other loads
+    theta_tr, _, info_tr = ctx.green_theta(dev(trial), dev(walkers), transposed=True)
+    got_tr = host(ctx.local_energy_lo(f, theta_tr, info_tr, transposed=True))
+    assert np.array_equal(got.view(np.float64), got_tr.view(np.float64))
     ref_f = E.lo_compress(lbar_ref, eps, pairs="upper")
     thetas, _ = oracle_thetas(trial, walkers)
     ref = E.e2_lo_batch(ref_f, thetas)
@@ -323,9 +339,15 @@ def test_lo_pass1_global_address_fallback(ctx):
     del theta_wm
     theta_om, _, info_om = ctx.green_theta(trial, phi, orbital_major=True)
     e_om = ctx.local_energy_lo(f, theta_om, info_om, orbital_major=True)
-    del theta_om, phi
-    a, b = host(e_wm), host(e_om)
+    del theta_om
+    # transposed theta: the slice of one orbital spans the whole array (3.2 GB),
+    # so the transposed staging also runs with global-address loads
+    theta_tr, _, info_tr = ctx.green_theta(trial, phi, transposed=True)
+    e_tr = ctx.local_energy_lo(f, theta_tr, info_tr, transposed=True)
+    del theta_tr, phi
+    a, b, c = host(e_wm), host(e_om), host(e_tr)
     assert np.array_equal(a.view(np.float64), b.view(np.float64))
+    assert np.array_equal(a.view(np.float64), c.view(np.float64))
     pick = [0, 4095, 77 * 4096 + 13, nw - 1]
     thetas, _ = oracle_thetas(s.trial, s.walkers[[w % 4096 for w in pick]])
     ref = E.e2_lo_batch(E.lo_compress(E.half_rotate(s.chol, s.trial), 1e-4, pairs="upper"), thetas)

@@ -74,6 +74,7 @@ def test_noalloc_chain_many_walkers():
         lbar = ctx.build_half_rotated_chol(dev(s.chol), dev(s.trial))
         fac = ctx.build_lo_factors(lbar, 1e-5)
         theta, _, info = ctx.green_theta(dev(s.trial), dev(s.walkers))
+        theta_tr, _, _ = ctx.green_theta(dev(s.trial), dev(s.walkers), transposed=True)
         for count in (600, 33):
             th, inf = theta[:count].contiguous(), info[:count].contiguous()
             out = torch.empty((count, 2), dtype=torch.complex128, device="cuda")
@@ -81,6 +82,12 @@ def test_noalloc_chain_many_walkers():
             e_ws = ctx.local_energy_lo(fac, th, inf)
             torch.cuda.synchronize()
             assert torch.equal(e_na, e_ws)
+            # transposed theta ([nw][n][M]) through the same entry point
+            out_tr = torch.empty((count, 2), dtype=torch.complex128, device="cuda")
+            e_tr = ctx.local_energy_lo(fac, theta_tr[:count].contiguous(), inf, energy=out_tr, noalloc=True,
+                                       transposed=True)
+            torch.cuda.synchronize()
+            assert torch.equal(e_tr, e_ws)
         fac.close()
     finally:
         ctx.close()
