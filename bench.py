@@ -58,6 +58,7 @@ def kernel_work(M, n, nw, X=0, n_out=0, total_rows=0, pair_rows=0):
     return {
         # O = Psi^T phi: real x complex, M n^2 MACs
         "overlap_kernel": ("mfma", 4.0 * M * n * n * nw, nw * c16 * (M * n + n * n) + r8 * M * n),
+        "overlap4_kernel": ("mfma", 4.0 * M * n * n * nw, nw * c16 * (M * n + n * n) + r8 * M * n),
         # Gauss-Jordan inverse: n^3 complex MACs, O in and O^-1 out
         "invert_kernel": ("alu", 8.0 * n ** 3 * nw, nw * 2 * c16 * n * n),
         # theta = phi O^-1: M n^2 complex MACs; phi in, theta out, O^-1 in
@@ -101,7 +102,8 @@ def measured_traffic(kernel, eps):
 
 
 KERNEL_SOURCES = {
-    "overlap_kernel": "green_theta.hip", "invert_kernel": "green_theta.hip", "apply_kernel": "green_theta.hip",
+    "overlap_kernel": "green_theta.hip", "overlap4_kernel": "green_theta.hip", "invert_kernel": "green_theta.hip",
+    "apply_kernel": "green_theta.hip",
     "lo_pass1_kernel": "energy_lo.hip", "lo_pass1_reg_kernel": "energy_lo.hip", "lo_pass2_kernel": "energy_lo.hip",
     "reduce_partials_kernel": "energy_full.hip", "energy_full_kernel": "energy_full.hip",
 }

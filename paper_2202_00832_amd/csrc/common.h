@@ -29,6 +29,13 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
+// s_waitcnt vmcnt(0) through the builtin (not inline asm), so the compiler's
+// own wait insertion sees it: the loads straight into LDS (buffer or global
+// form) of the issuing lane are complete after it.  gfx9 encoding: vmcnt in
+// bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8 (expcnt and lgkmcnt at their
+// maximum: no wait)
+__device__ __forceinline__ void wait_vmcnt0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Complex product on double2 (x = re, y = im).
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

@@ -201,10 +201,6 @@ __global__ __launch_bounds__(512, 2) void lo_pass1_reg_kernel(int M, int64_t nw,
 // of 512 elements from as many lines; it sits in LDS as [walker][r] with r
 // XOR-swizzled by the walker's low four bits, so the operand reads (16
 // walkers x 4 r per read) spread over all bank groups.
-// s_waitcnt vmcnt(0) through the builtin (not inline asm), so the compiler's
-// own wait insertion sees it.  gfx9 encoding: vmcnt in bits 3:0 and 15:14,
-// expcnt 6:4, lgkmcnt 11:8 (expcnt and lgkmcnt at their maximum: no wait)
-__device__ __forceinline__ void wait_vmcnt0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // calls f(integral_constant<q>) for the wave-uniform group count q in 1 .. N
 template <int N, typename F>

@@ -144,6 +144,149 @@ __global__ __launch_bounds__(GtCfg<NB>::OT) void overlap_kernel(int M, int n, in
 }
 
 // ---------------------------------------------------------------------------
+// 1'. The same product on the FP64 4x4x4 MFMA form, for NB <= 4, M a multiple
+//    of 16 and n even (so that every 16-byte chunk of a trial or walker row
+//    is whole and aligned).  CS workgroups of four waves per walker, each
+//    taking NP / CS columns of O (so a CU holds four workgroups and their
+//    slab barriers overlap); wave v owns the 4-row groups g = v + 4q (rows
+//    i = 4g .. 4g + 3) against the workgroup's columns.
+//    The trial fragment (4 rows x 4 r) is the operand the four blocks of an
+//    MFMA share; each block takes 4 walker columns, so one MFMA gives a
+//    4 x 16 tile, and per K-step a wave issues 2 NB^2 / CS MFMAs (real and
+//    imaginary part) from NB + NB / CS LDS reads.  16-row slabs of Psi_T and phi_w
+//    are loaded straight into LDS through buffer descriptors one slab ahead
+//    (as in LO pass 1).  Psi_T sits in LDS as [r][i] with the 16-byte column
+//    pairs of row r XOR-swizzled by 2 (r & 3), so a fragment read (4 rows r x
+//    4 consecutive i) falls in 8 distinct bank groups; phi_w as [r][j].
+//    Columns i, j >= n load a valid neighbour and their outputs are written
+//    as the zeros of the padded block.
+// ---------------------------------------------------------------------------
+template <int NB, int CS>
+__global__ __launch_bounds__(256) void overlap4_kernel(int M, int n, int64_t w0, const double* __restrict__ trial,
+                                                       const double2* __restrict__ phi, double2* __restrict__ O) {
+  static_assert(NB % CS == 0, "column parts of whole blocks");
+  constexpr int NP = 16 * NB;
+  constexpr int NJ = NP / CS;               // columns of this workgroup
+  constexpr int CB = NB / CS;               // their 16-column blocks
+  constexpr int NWV = 4;
+  constexpr int A_CH = 8 * NP;              // 16-byte chunks of a trial slab (16 rows x NP doubles)
+  constexpr int B_CH = 16 * NJ;             // of a walker slab (16 rows x NJ complex)
+  constexpr int A_LD = (A_CH + 255) / 256;  // wave-instructions per thread for A (ceil)
+  constexpr int B_LD = B_CH / 256;          // for B (exactly CB)
+  __shared__ __attribute__((aligned(16))) double sA0[16 * NP];
+  __shared__ __attribute__((aligned(16))) double sA1[16 * NP];
+  __shared__ __attribute__((aligned(16))) double2 sB0[16 * NJ];
+  __shared__ __attribute__((aligned(16))) double2 sB1[16 * NJ];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t w = w0 + blockIdx.x / CS;
+  const int j0 = NJ * (int)(blockIdx.x % CS);
+
+  // chunk offsets (bytes from the slab's first row) of this thread's loads
+  uint32_t aoff[A_LD], boff[B_LD];
+#pragma unroll
+  for (int k = 0; k < A_LD; ++k) {
+    const int S = 256 * k + tid;                      // chunk slot in LDS
+    const int r = (S / (NP / 2)) & 15;
+    const int cp = (S % (NP / 2)) ^ (2 * (r & 3));    // logical column pair
+    const int i = min(2 * cp, n - 2);
+    aoff[k] = (uint32_t)(((size_t)r * n + i) * sizeof(double));
+  }
+#pragma unroll
+  for (int k = 0; k < B_LD; ++k) {
+    const int S = 256 * k + tid;
+    const int r = S / NJ, j = min(j0 + S % NJ, n - 1);
+    boff[k] = (uint32_t)(((size_t)r * n + j) * sizeof(double2));
+  }
+  const __amdgpu_buffer_rsrc_t ares =
+      __builtin_amdgcn_make_buffer_rsrc((void*)trial, 0, (int)((size_t)M * n * sizeof(double)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t bres = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(phi + w * (size_t)M * n), 0, (int)((size_t)M * n * sizeof(double2)), 0x00020000);
+  auto issue = [&](int c, double* sa, double2* sb) __attribute__((always_inline)) {
+    const int srow = 16 * c * n;   // first element of the slab's rows
+#pragma unroll
+    for (int k = 0; k < A_LD; ++k) {
+      if (A_CH % 256 == 0 || 256 * k + 64 * wv < A_CH) {
+        auto* dst = (__attribute__((address_space(3))) void*)(sa + 2 * (256 * k + 64 * wv));
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ares, dst, 16, (int)aoff[k], srow * (int)sizeof(double), 0, 0);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < B_LD; ++k) {
+      auto* dst = (__attribute__((address_space(3))) void*)(sb + 256 * k + 64 * wv);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(bres, dst, 16, (int)boff[k], srow * (int)sizeof(double2), 0, 0);
+    }
+  };
+
+  // acc[q][c][p]: rows 4 (wv + 4 q) + lk, columns j0 + 16 c + lr, part p (re, im)
+  double acc[NB][CB][2];
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[q][c][0] = acc[q][c][1] = 0.0;
+  // A operand of this lane: row i = 4 (wv + 4 q) + (lane & 3), r = 4 s4 + lk:
+  // column pair 2 (wv + 4 q) + ((lane & 3) >> 1) of row r, element lane & 1
+  const int e2 = 2 * (lk & 3);   // swizzle of row r = 4 s4 + lk (r & 3 = lk)
+  auto compute = [&](const double* sa, const double2* sb) __attribute__((always_inline)) {
+    double a[2][NB];
+    double2 b[2][CB];
+    auto read = [&](int s4, int slot) __attribute__((always_inline)) {
+      const int r = 4 * s4 + lk;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int cp = (2 * (wv + NWV * q) + ((lane & 3) >> 1)) ^ e2;
+        a[slot][q] = sa[r * NP + 2 * cp + (lane & 1)];
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c) b[slot][c] = sb[r * NJ + 16 * c + lr];
+    };
+    read(0, 0);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int u = s4 & 1;
+      if (s4 < 3) read(s4 + 1, u ^ 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          acc[q][c][0] = mfma4(a[u][q], b[u][c].x, acc[q][c][0]);
+          acc[q][c][1] = mfma4(a[u][q], b[u][c].y, acc[q][c][1]);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  const int nslab = M / 16;
+  issue(0, sA0, sB0);
+  wait_vmcnt0();
+  __syncthreads();
+  for (int c = 0; c < nslab; c += 2) {
+    if (c + 1 < nslab) issue(c + 1, sA1, sB1);
+    compute(sA0, sB0);
+    wait_vmcnt0();
+    __syncthreads();
+    if (c + 1 < nslab) {
+      if (c + 2 < nslab) issue(c + 2, sA0, sB0);
+      compute(sA1, sB1);
+      wait_vmcnt0();
+      __syncthreads();
+    }
+  }
+  double2* Ow = O + w * (size_t)NP * NP;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int i = 4 * (wv + NWV * q) + lk;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int j = j0 + 16 * c + lr;
+      const bool in = i < n && j < n;
+      Ow[(size_t)i * NP + j] = in ? make_double2(acc[q][c][0], acc[q][c][1]) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 2. O_w -> R_w, the exchange (Gauss-Jordan) inverse in pivot order:
 //    O_w^{-1}[k][p_m] = R_w[p_k][m], with the pivot rows p_k written to perm;
 //    log det O_w and the zero-pivot index.  Wave q owns the 16 columns
@@ -640,9 +783,23 @@ static hipError_t launch_gt(hipStream_t s, int M, int n, int64_t nw, int64_t w0,
                             double* work, const ProfHook* prof, int flag_small) {
   double2* O = reinterpret_cast<double2*>(work);
   int* perm = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + gt_perm_offset(n, nw));
-  prof_mark(prof, "overlap_kernel");
-  hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nwc), dim3(GtCfg<NB>::OT), 0, s, M, n, w0, trial,
-                     (const double2*)phi, O);
+  // the 4x4x4 form where its loads are whole 16-byte chunks of full slabs
+  // and the buffer offsets of one walker fit 32 bits
+  bool four = false;
+  if constexpr (NB <= 4) four = M % 16 == 0 && n % 2 == 0 && (int64_t)M * n * 16 <= (int64_t)INT32_MAX;
+  if (four) {
+    prof_mark(prof, "overlap4_kernel");
+    // one workgroup per walker (two column parts measured slower at 60 orbitals)
+    if constexpr (NB <= 4) {
+      constexpr int CS = 1;
+      hipLaunchKernelGGL((overlap4_kernel<NB, CS>), dim3((unsigned)(nwc * CS)), dim3(256), 0, s, M, n, w0, trial,
+                         (const double2*)phi, O);
+    }
+  } else {
+    prof_mark(prof, "overlap_kernel");
+    hipLaunchKernelGGL(overlap_kernel<NB>, dim3((unsigned)nwc), dim3(GtCfg<NB>::OT), 0, s, M, n, w0, trial,
+                       (const double2*)phi, O);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   prof_mark(prof, "invert_kernel");

@@ -81,8 +81,12 @@ def test_half_rotation(ctx, M, n, X):
 # green_theta
 # ---------------------------------------------------------------------------
 
+# M a multiple of 16 with n even and at most 64 runs the overlap on the 4x4x4
+# form (one to four column blocks, ragged last block), any other shape the
+# 16x16x4 form
 @pytest.mark.parametrize("M,n,nw", [(48, 8, 16), (37, 1, 3), (50, 17, 5), (70, 33, 4), (100, 60, 3),
-                                    (64, 64, 2), (131, 47, 5), (5, 5, 2), (140, 100, 3), (120, 112, 2)])
+                                    (64, 64, 2), (131, 47, 5), (5, 5, 2), (140, 100, 3), (120, 112, 2),
+                                    (32, 2, 5), (96, 46, 4), (160, 64, 7), (48, 16, 3), (400, 60, 9)])
 def test_green_theta(ctx, M, n, nw):
     print("green_theta M=%d n=%d nw=%d" % (M, n, nw), flush=True)
     if (M, n) == (48, 8):
@@ -114,11 +118,12 @@ def test_green_theta(ctx, M, n, nw):
     assert np.abs(dphi).max() <= 1e-11
 
 
-def test_green_theta_many_walkers_with_singular_ones(ctx):
+@pytest.mark.parametrize("M,n", [(50, 17), (64, 18)])
+def test_green_theta_many_walkers_with_singular_ones(ctx, M, n):
     """300 walkers (several XCD groups of the apply kernel and a ragged last
-    group): every walker, both layouts, and two singular walkers whose zero
-    pivots come at different steps."""
-    M, n, nw = 50, 17, 300
+    group): every walker, every layout, and two singular walkers whose zero
+    pivots come at different steps (16x16x4 and 4x4x4 overlap forms)."""
+    nw = 300
     print("green_theta M=%d n=%d nw=%d with singular walkers" % (M, n, nw), flush=True)
     _, trial, walkers = random_system(M, n, 1, nw, seed=11)
     walkers[5, :, 3] = 0.0                     # zero columns: exactly zero overlap columns,
