@@ -86,7 +86,8 @@ def test_half_rotation(ctx, M, n, X):
 # 16x16x4 form
 @pytest.mark.parametrize("M,n,nw", [(48, 8, 16), (37, 1, 3), (50, 17, 5), (70, 33, 4), (100, 60, 3),
                                     (64, 64, 2), (131, 47, 5), (5, 5, 2), (140, 100, 3), (120, 112, 2),
-                                    (32, 2, 5), (96, 46, 4), (160, 64, 7), (48, 16, 3), (400, 60, 9)])
+                                    (32, 2, 5), (96, 46, 4), (160, 64, 7), (48, 16, 3), (400, 60, 9),
+                                    (64, 33, 3)])
 def test_green_theta(ctx, M, n, nw):
     print("green_theta M=%d n=%d nw=%d" % (M, n, nw), flush=True)
     if (M, n) == (48, 8):
