@@ -914,6 +914,23 @@ def main():
         results[s["epsilon"]] = split
         log("LO eps=%g: %.3f ms/step (green_theta %.3f, LO %.3f)" % (s["epsilon"], s["ms_per_step"],
                                                                      s["green_theta_ms"], s["local_energy_lo_ms"]))
+    # the headline step again with walker-major theta ([w][r][j]), for the
+    # layout comparison (same energies bit for bit)
+    def lo_step_wm(ev):
+        if ev is not None:
+            ev["a"].record()
+        ctx.green_theta(trial_d, phi_d, theta, logov, info)
+        if ev is not None:
+            ev["b"].record()
+        ctx.local_energy_lo(factors[head_eps], theta, info, energy)
+        if ev is not None:
+            ev["c"].record()
+    head_eps = head["epsilon"]
+    tot_w, _, kern_w = time_route(torch, ctx, lo_step_wm, args.steps, min(args.warmup, 50), marks)
+    lo_wm = {"epsilon": head_eps, "ms_per_step": round(tot_w / args.steps, 4),
+             "walker_energies_per_s": round(nw / (tot_w / args.steps / 1e3), 1),
+             "kernel_us": {k: round(t / c * 1e3, 2) for k, (c, t) in kern_w.items()}}
+    log("LO eps=%g, walker-major theta: %.3f ms/step" % (head_eps, lo_wm["ms_per_step"]))
     full_steps = max(1, min(args.steps, 10))
     tot_f, split_f, kern_f = time_route(torch, ctx, full_step, full_steps, min(args.warmup, 2), marks)
     full_ms = tot_f / full_steps
@@ -970,7 +987,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg.name, "M": M, "n_occ": n, "n_chol": X, "walkers": nw, "sigma": cfg.sigma,
                    "cholesky_tol": cfg.chol_tol, "route": "LO", "epsilon": eps_h,
+                   "theta_layout": "[w][j][r] (each walker's theta transposed)",
                    "gate": "max over walkers of |Re(E_LO - E_full)| <= 1 mHa"},
+        "lo_walker_major_theta": lo_wm,
         "value_mean_gate": {"value": round(head_mean["walker_energies_per_s"], 1), "unit": "walker-energies/s",
                             "epsilon": head_mean["epsilon"],
                             "gate": "|mean Re(E_LO - E_full)| + 2 stderr <= 1 mHa over the walkers"},
