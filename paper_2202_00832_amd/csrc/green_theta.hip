@@ -555,8 +555,16 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
       }
     }
   };
+  // the sweeping wave runs at raised issue priority from its first half
+  // through its second, so that on a SIMD shared with other waves (the rank-8
+  // updates, the other walker's workgroup) the serial chain issues first
+  // (225 against 235 us for green_theta at 512 walkers; raising the next
+  // sweeper's update as well gave nothing)
   for (int b = 0; b < NB; ++b) {
-    if (wv == b) sweep_half(std::integral_constant<int, 0>{}, b);
+    if (wv == b) {
+      __builtin_amdgcn_s_setprio(3);
+      sweep_half(std::integral_constant<int, 0>{}, b);
+    }
     __syncthreads();
     zero = sZero[0];
     if (zero) break;
@@ -564,7 +572,10 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
       update_self(std::integral_constant<int, 0>{}, 2 * b);
     else
       update_other(2 * b, 0);
-    if (wv == b) sweep_half(std::integral_constant<int, 1>{}, b);
+    if (wv == b) {
+      sweep_half(std::integral_constant<int, 1>{}, b);
+      __builtin_amdgcn_s_setprio(0);
+    }
     __syncthreads();
     zero = sZero[1];
     if (zero) break;
@@ -573,6 +584,7 @@ __global__ __launch_bounds__(64 * NB) void invert_kernel(int n, int64_t w0, doub
     else
       update_other(2 * b + 1, 1);
   }
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
 
   // R in pivot order, row-contiguous (identity on the padding)
