@@ -771,6 +771,9 @@ def main():
     ap.add_argument("--no-residual", action="store_true",
                     help="skip the learned-residual study (800-site chain: about 30 GB of device memory)")
     ap.add_argument("--no-md", action="store_true", help="skip the multi-determinant study")
+    ap.add_argument("--no-wm", action="store_true",
+                    help="skip the headline step with walker-major theta (counter runs: every pass-1 launch of "
+                         "the LO route then reads transposed theta)")
     ap.add_argument("--no-hr", action="store_true",
                     help="skip the half-rotated ERI route (Eq. 17; its pair blocks take 2.3 GB)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -828,6 +831,8 @@ def main():
 
     theta, logov, info = ctx.green_theta(trial_d, phi_d)
     e_full = ctx.local_energy_full(lbar, theta, info)
+    # the LO route reads theta transposed ([w][j][r]), in the accuracy sweep too
+    theta_tr, _, _ = ctx.green_theta(trial_d, phi_d, transposed=True)
     torch.cuda.synchronize()
     assert int((info != 0).sum()) == 0, "singular walker overlap"
     e_full_h = e_full.cpu().numpy()
@@ -841,7 +846,7 @@ def main():
         f = ctx.build_lo_factors(lbar, eps)
         t_build = time.perf_counter() - t
         factors[eps] = f
-        e_lo = ctx.local_energy_lo(f, theta, info)
+        e_lo = ctx.local_energy_lo(f, theta_tr, info, transposed=True)
         torch.cuda.synchronize()
         E2_lo = e_lo.cpu().numpy().sum(axis=1)
         dre = (E2_lo - E2_full).real
@@ -873,10 +878,9 @@ def main():
     eps_h = head["epsilon"]
 
     energy = torch.empty((nw, 2), dtype=torch.complex128, device="cuda")
-    # the LO step hands theta over transposed ([w][j][r]), the layout whose
-    # orbital columns pass 1 loads in whole cache lines (same energies bit
-    # for bit as walker-major theta)
-    theta_tr = torch.empty((nw, n, M), dtype=torch.complex128, device="cuda")
+    # the LO step hands theta over transposed ([w][j][r], theta_tr), the
+    # layout whose orbital columns pass 1 loads in whole cache lines (same
+    # energies bit for bit as walker-major theta)
 
     def lo_step_for(f):
         def step(ev):
@@ -926,11 +930,13 @@ def main():
         if ev is not None:
             ev["c"].record()
     head_eps = head["epsilon"]
-    tot_w, _, kern_w = time_route(torch, ctx, lo_step_wm, args.steps, min(args.warmup, 50), marks)
-    lo_wm = {"epsilon": head_eps, "ms_per_step": round(tot_w / args.steps, 4),
-             "walker_energies_per_s": round(nw / (tot_w / args.steps / 1e3), 1),
-             "kernel_us": {k: round(t / c * 1e3, 2) for k, (c, t) in kern_w.items()}}
-    log("LO eps=%g, walker-major theta: %.3f ms/step" % (head_eps, lo_wm["ms_per_step"]))
+    lo_wm = None
+    if not args.no_wm:
+        tot_w, _, kern_w = time_route(torch, ctx, lo_step_wm, args.steps, min(args.warmup, 50), marks)
+        lo_wm = {"epsilon": head_eps, "ms_per_step": round(tot_w / args.steps, 4),
+                 "walker_energies_per_s": round(nw / (tot_w / args.steps / 1e3), 1),
+                 "kernel_us": {k: round(t / c * 1e3, 2) for k, (c, t) in kern_w.items()}}
+        log("LO eps=%g, walker-major theta: %.3f ms/step" % (head_eps, lo_wm["ms_per_step"]))
     full_steps = max(1, min(args.steps, 10))
     tot_f, split_f, kern_f = time_route(torch, ctx, full_step, full_steps, min(args.warmup, 2), marks)
     full_ms = tot_f / full_steps
