@@ -249,7 +249,8 @@ int green_theta(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t nw, const double*
  *               FP32 or split-BF16 copy in the context workspace and support
  *               nw <= 65535 and n_chol <= 65535
  *   energy    : complex [nw][2] (output) = (E_J, E_K) per walker
- * flags must be 0.  Supports n_occ <= 112 (LO_FP64), <= 96 (LO_FP32) or <= 64
+ * flags must be 0 (a theta layout flag gives LO_EUNSUPPORTED, any other bit
+ * LO_EINVAL).  Supports n_occ <= 112 (LO_FP64), <= 96 (LO_FP32) or <= 64
  * (LO_BF16X3). */
 int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int64_t nw,
                       const double* lbar, const double* theta, const int32_t* info,

@@ -1459,6 +1459,8 @@ int local_energy_full(lo_ctx* ctx, int64_t M, int64_t n_occ, int64_t n_chol, int
   if (n_occ > M) return fail(ctx, LO_EINVAL, "n_occ exceeds M");
   if (precision != LO_FP64 && precision != LO_FP32 && precision != LO_BF16X3)
     return fail(ctx, LO_EINVAL, "unknown precision %d", precision);
+  if (flags == LO_THETA_ORBITAL_MAJOR || flags == LO_THETA_TRANSPOSED)
+    return fail(ctx, LO_EUNSUPPORTED, "the full route reads walker-major theta only");
   if (flags != 0) return fail(ctx, LO_EINVAL, "unknown flags 0x%x", flags);
   const int max_occ = precision == LO_FP64 ? kMaxOccTheta : (precision == LO_FP32 ? kMaxOccWide : kMaxOcc);
   if (n_occ > max_occ) return fail(ctx, LO_EUNSUPPORTED, "n_occ above %d for this precision", max_occ);

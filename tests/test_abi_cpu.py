@@ -67,6 +67,8 @@ def test_validation_errors_need_no_device(lib):
         assert lib.green_theta(h, 8, 2, 3, fake, fake, fake, None, fake, T | 1) == L.LO_EINVAL
         assert lib.green_theta(h, 8, 2, 0, None, None, None, None, None, T) == L.LO_OK   # empty batch
         assert lib.local_energy_hr(h, fake, 4, fake, None, T, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP64, T, fake) == L.LO_EUNSUPPORTED
+        assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP64, 1, fake) == L.LO_EUNSUPPORTED
         assert lib.local_energy_lo(h, fake, 4, fake, None, 9, 0, None, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, 3, 4, fake, fake, None, L.LO_FP64, 7, fake) == L.LO_EINVAL
         assert lib.local_energy_full(h, 8, 2, -3, 4, fake, fake, None, L.LO_FP64, 0, fake) == L.LO_EINVAL
