@@ -164,3 +164,16 @@ def test_multideterminant_validation_needs_no_device(lib):
         assert lib.lo_md_info(None, None, None, None, None, None) == L.LO_EINVAL
     finally:
         lib.lo_destroy(h)
+
+
+def test_theta_layout_shapes():
+    """The binding's theta layouts: [nw][M][n], [n][M][nw] (orbital-major) and
+    [nw][n][M] (transposed), with the flag each passes to the library."""
+    import numpy as np
+    from paper_2202_00832_amd.lofqmc import _theta_layout
+    M, n, nw = 40, 6, 9
+    assert _theta_layout(np.empty((nw, M, n)), M, n, False, False) == (nw, 0, (nw, M, n))
+    assert _theta_layout(np.empty((n, M, nw)), M, n, True, False) == (nw, L.LO_THETA_ORBITAL_MAJOR, (n, M, nw))
+    assert _theta_layout(np.empty((nw, n, M)), M, n, False, True) == (nw, L.LO_THETA_TRANSPOSED, (nw, n, M))
+    with pytest.raises(ValueError):
+        _theta_layout(np.empty((nw, n, M)), M, n, True, True)
